@@ -1,0 +1,247 @@
+"""Seeded synthetic circuit generators.
+
+This module only draws random numbers and lists gates by name. It holds none of
+the simulation arithmetic (no gate matrices, no amplitude updates), so both the
+CPU oracle and the GPU path can consume its output without sharing any of the
+method's code.
+
+A gate is a ``Gate`` record:
+  name   gate kind, one of GATE_NAMES
+  q0     first qubit (target of a 1-qubit gate; control of CNOT; first operand
+         of a 2-qubit gate = the high bit of the gate-local 2-bit index)
+  q1     second qubit, -1 for 1-qubit and n-qubit gates
+  angle  rotation / phase angle in radians (RX, RY, RZ, P, CPHASE)
+  param  -1, or an index into a per-circuit parameter vector that replaces
+         ``angle`` (used by the QNN ansatz)
+  index  basis index for MARK (sign flip of one basis state), else 0
+
+Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
+"""
+from __future__ import annotations
+
+import math
+from typing import List, NamedTuple, Optional, Sequence
+
+import numpy as np
+
+
+class Gate(NamedTuple):
+    name: str
+    q0: int
+    q1: int = -1
+    angle: float = 0.0
+    param: int = -1
+    index: int = 0
+
+
+ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P")
+TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE")
+N_QUBIT = ("MARK",)
+GATE_NAMES = ONE_QUBIT + TWO_QUBIT + N_QUBIT
+ANGLED = ("RX", "RY", "RZ", "P", "CPHASE")
+
+# Gate pools of the seeded random workloads.
+RANDOM_1Q_POOL = ("H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ")
+RANDOM_2Q_POOL = ("CNOT", "CZ", "SWAP", "CPHASE")
+CAPACITY_DENSE_POOL = ("RX", "RY")
+CAPACITY_SPARSE_POOL = ("RZ", "S", "T", "X")
+CAPACITY_2Q_POOL = ("CZ", "CPHASE", "CNOT")
+
+
+def _layer_pairs(rng: np.random.Generator, n: int, pool: Sequence[str],
+                 p_pair: float) -> List[Gate]:
+    """Shuffle the qubits, pair them up (perm[2i], perm[2i+1]) and give each
+    pair a gate drawn uniformly from ``pool`` with probability ``p_pair``."""
+    perm = rng.permutation(n)
+    out = []
+    for i in range(n // 2):
+        a, b = int(perm[2 * i]), int(perm[2 * i + 1])
+        if rng.random() < p_pair:
+            name = pool[int(rng.integers(len(pool)))]
+            ang = float(rng.uniform(0.0, 2.0 * math.pi)) if name == "CPHASE" else 0.0
+            out.append(Gate(name, a, b, ang))
+    return out
+
+
+def random_circuit(n: int, depth: int, seed: int) -> List[Gate]:
+    """Random circuit of the plain-method workloads (n=12 depth 20; n=28 depth 100).
+
+    Per layer: for q = 0..n-1 a gate drawn uniformly from RANDOM_1Q_POOL
+    (angles U[0, 2pi)), then the qubits are shuffled and paired, and each pair
+    gets a gate from RANDOM_2Q_POOL with probability 0.5 (CPHASE angle U[0, 2pi)).
+    RNG: numpy PCG64 seeded with ``seed``; draw order as written here.
+    """
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = []
+    for _ in range(depth):
+        for q in range(n):
+            name = RANDOM_1Q_POOL[int(rng.integers(len(RANDOM_1Q_POOL)))]
+            ang = float(rng.uniform(0.0, 2.0 * math.pi)) if name in ANGLED else 0.0
+            gates.append(Gate(name, q, -1, ang))
+        if n >= 2:
+            gates.extend(_layer_pairs(rng, n, RANDOM_2Q_POOL, 0.5))
+    return gates
+
+
+def capacity_circuit(n: int, layers: int, seed: int) -> List[Gate]:
+    """Capacity workload: an H layer on every qubit, then ``layers`` layers in
+    which each qubit gets, with probability 0.1, a dense gate from
+    CAPACITY_DENSE_POOL and otherwise a gate from CAPACITY_SPARSE_POOL, followed
+    by random disjoint pairs (probability 0.5) from CAPACITY_2Q_POOL."""
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = [Gate("H", q) for q in range(n)]
+    for _ in range(layers):
+        for q in range(n):
+            if rng.random() < 0.1:
+                name = CAPACITY_DENSE_POOL[int(rng.integers(len(CAPACITY_DENSE_POOL)))]
+            else:
+                name = CAPACITY_SPARSE_POOL[int(rng.integers(len(CAPACITY_SPARSE_POOL)))]
+            ang = float(rng.uniform(0.0, 2.0 * math.pi)) if name in ANGLED else 0.0
+            gates.append(Gate(name, q, -1, ang))
+        if n >= 2:
+            gates.extend(_layer_pairs(rng, n, CAPACITY_2Q_POOL, 0.5))
+    return gates
+
+
+def grover_iterations(n: int) -> int:
+    """Iteration count floor(pi/4 * sqrt(2^n)) (804 for n = 20)."""
+    return int(math.floor(math.pi / 4.0 * math.sqrt(2.0 ** n)))
+
+
+def grover_marked(n: int, seed: int) -> int:
+    """Seeded marked index, uniform in [0, 2^n)."""
+    rng = np.random.default_rng(seed)
+    return int(rng.integers(0, 1 << n))
+
+
+def grover_circuit(n: int, marked: int, iterations: Optional[int] = None) -> List[Gate]:
+    """Grover search as a gate list: an H layer, then per iteration the phase
+    oracle MARK(marked), an H layer, MARK(0) (the zero-state reflection
+    I - 2|0><0|) and an H layer. Each iteration therefore equals -D*O with the
+    diffusion D = 2|s><s| - I, i.e. a global factor (-1)^iterations."""
+    k = grover_iterations(n) if iterations is None else iterations
+    gates: List[Gate] = [Gate("H", q) for q in range(n)]
+    for _ in range(k):
+        gates.append(Gate("MARK", -1, -1, 0.0, -1, marked))
+        gates.extend(Gate("H", q) for q in range(n))
+        gates.append(Gate("MARK", -1, -1, 0.0, -1, 0))
+        gates.extend(Gate("H", q) for q in range(n))
+    return gates
+
+
+def qnn_ansatz(n: int, layers: int) -> List[Gate]:
+    """Hardware-efficient ansatz of the QNN workloads, with parameter references.
+
+    Parameter vector layout: params[0:n] = the input encoding x (RY(x_q) on every
+    qubit), params[n + (2*l + 0)*n + q] = RY angle of layer l on qubit q,
+    params[n + (2*l + 1)*n + q] = RZ angle. Each layer ends with the CNOT ring
+    CNOT(q, (q+1) mod n) for q = 0..n-1 in that order. Output: <Z_0>.
+    """
+    gates: List[Gate] = [Gate("RY", q, -1, 0.0, q) for q in range(n)]
+    for l in range(layers):
+        gates.extend(Gate("RY", q, -1, 0.0, n + (2 * l + 0) * n + q) for q in range(n))
+        gates.extend(Gate("RZ", q, -1, 0.0, n + (2 * l + 1) * n + q) for q in range(n))
+        if n >= 2:
+            gates.extend(Gate("CNOT", q, (q + 1) % n) for q in range(n))
+    return gates
+
+
+def qnn_n_params(n: int, layers: int) -> int:
+    return n + 2 * n * layers
+
+
+def qnn_params(n: int, layers: int, batch: int, seed: int) -> np.ndarray:
+    """[batch, n + 2nL] float64: x ~ U[-pi, pi]^n then theta ~ N(0, 1)^(2nL)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((batch, qnn_n_params(n, layers)), dtype=np.float64)
+    for b in range(batch):
+        out[b, :n] = rng.uniform(-math.pi, math.pi, size=n)
+        out[b, n:] = rng.standard_normal(2 * n * layers)
+    return out
+
+
+class QNNRequest(NamedTuple):
+    rid: int
+    arrival_s: float      # offset from stream start, seconds
+    n: int
+    layers: int
+    params: np.ndarray    # [n + 2nL] float64
+
+
+def poisson_requests(count: int, rate_hz: float, seed: int,
+                     n_range=(8, 20), layer_range=(4, 16)) -> List[QNNRequest]:
+    """Poisson stream of QNN requests: exponential inter-arrival times at
+    ``rate_hz``, n ~ U{n_range}, L ~ U{layer_range} (inclusive),
+    x ~ U[-pi, pi]^n, theta ~ N(0, 1)^(2nL)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(count):
+        t += float(rng.exponential(1.0 / rate_hz)) if rate_hz > 0 else 0.0
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        layers = int(rng.integers(layer_range[0], layer_range[1] + 1))
+        p = np.empty(qnn_n_params(n, layers))
+        p[:n] = rng.uniform(-math.pi, math.pi, size=n)
+        p[n:] = rng.standard_normal(2 * n * layers)
+        out.append(QNNRequest(rid, t, n, layers, p))
+    return out
+
+
+def random_state(n: int, seed: int) -> np.ndarray:
+    """Seeded normalised complex128 state (Gaussian real and imaginary parts)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return v / np.linalg.norm(v)
+
+
+def random_1q_unitary_free_circuit(n: int, count: int, seed: int,
+                                   names: Sequence[str] = GATE_NAMES) -> List[Gate]:
+    """``count`` gates drawn uniformly from ``names`` on random qubits (distinct
+    pairs for 2-qubit kinds, random index for MARK). Used by exhaustive tests."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        name = names[int(rng.integers(len(names)))]
+        ang = float(rng.uniform(0.0, 2.0 * math.pi)) if name in ANGLED else 0.0
+        if name in TWO_QUBIT:
+            if n < 2:
+                continue
+            a, b = rng.choice(n, size=2, replace=False)
+            out.append(Gate(name, int(a), int(b), ang))
+        elif name == "MARK":
+            out.append(Gate(name, -1, -1, 0.0, -1, int(rng.integers(0, 1 << n))))
+        else:
+            out.append(Gate(name, int(rng.integers(n)), -1, ang))
+    return out
+
+
+def amplitude_gate_updates(n: int, gates: Sequence[Gate]) -> int:
+    """Work measure: every gate counts 2^n amplitude updates per state."""
+    return len(gates) * (1 << n)
+
+
+_SELF_INVERSE = ("I", "X", "Y", "Z", "H", "CNOT", "CZ", "SWAP", "MARK")
+_INVERSE_NAME = {"S": "SDG", "SDG": "S", "T": "TDG", "TDG": "T"}
+
+
+def inverse_circuit(gates: Sequence[Gate]) -> List[Gate]:
+    """Gate list of the inverse circuit: reversed order, each gate replaced by
+    its inverse (named inverse, or the same rotation with the angle negated).
+    Parameter references are not supported (resolve them first)."""
+    out = []
+    for g in reversed(gates):
+        if g.param >= 0:
+            raise ValueError("resolve parameter references before inverting")
+        if g.name in _SELF_INVERSE:
+            out.append(g)
+        elif g.name in _INVERSE_NAME:
+            out.append(g._replace(name=_INVERSE_NAME[g.name]))
+        else:  # RX, RY, RZ, P, CPHASE
+            out.append(g._replace(angle=-g.angle))
+    return out
+
+
+def resolve_params(gates: Sequence[Gate], params) -> List[Gate]:
+    """Replace parameter references by the referenced angle values."""
+    return [g._replace(angle=float(params[g.param]), param=-1) if g.param >= 0 else g
+            for g in gates]

@@ -1,0 +1,329 @@
+"""Pins of the CPU FP64 oracle against what the paper and the mathematics fix.
+
+None of these checks re-uses the oracle's own arithmetic: each compares it with
+an independent route (paper-printed values, Kronecker-product operators formed
+with numpy, scipy's matrix exponential, closed forms, invariants).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import synth
+from oracle import gates as G
+from oracle import oracle as O
+from oracle import ref_kron as K
+from oracle import rh as RH
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+# Pauli matrices: X and Y as printed in Sec. III-A1, Z textbook.
+PX = np.array([[0, 1], [1, 0]], dtype=complex)
+PY = np.array([[0, -1j], [1j, 0]], dtype=complex)
+PZ = np.array([[1, 0], [0, -1]], dtype=complex)
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# ---------------------------------------------------------------- gate table
+
+ANGLES = [0.0, 0.3, 1.7, math.pi, 4.9, -2.2]
+
+
+@pytest.mark.parametrize("name", [n for n in synth.GATE_NAMES if n != "MARK"])
+def test_gate_unitary(name):
+    for a in ANGLES:
+        m = G.matrix(name, a)
+        assert np.allclose(m.conj().T @ m, np.eye(m.shape[0]), atol=1e-15)
+
+
+def test_paper_pauli_x_y():
+    assert np.array_equal(G.matrix("X"), PX)
+    assert np.array_equal(G.matrix("Y"), PY)
+
+
+def test_paper_yx_dax_example():
+    rows = _golden_lines("paper_yx_dax.txt")
+    yx = np.kron(G.matrix("Y"), G.matrix("X")).reshape(-1)
+    nz = np.flatnonzero(yx)
+    assert list(nz) == [int(r[0]) for r in rows]
+    for r in rows:
+        assert yx[int(r[0])] == complex(float(r[1]), float(r[2]))
+    # memory figures of the example: 4 entries of 24 B vs 16 elements of 16 B
+    assert len(nz) * 24 == 96 and yx.size * 16 == 256
+
+
+@pytest.mark.parametrize("name,pauli", [("RX", PX), ("RY", PY), ("RZ", PZ)])
+def test_rotations_are_exponentials(name, pauli):
+    for a in ANGLES:
+        ref = scipy.linalg.expm(-0.5j * a * pauli)
+        assert np.allclose(G.matrix(name, a), ref, atol=1e-14)
+
+
+def test_gate_identities():
+    m = G.matrix
+    assert np.allclose(m("S") @ m("S"), m("Z"))
+    assert np.allclose(m("T") @ m("T"), m("S"))
+    assert np.allclose(m("SDG"), m("S").conj().T)
+    assert np.allclose(m("TDG"), m("T").conj().T)
+    assert np.allclose(m("P", math.pi / 2), m("S"))
+    assert np.allclose(m("P", math.pi / 4), m("T"))
+    assert np.allclose(m("H") @ m("X") @ m("H"), m("Z"))
+    assert np.allclose(m("H") * math.sqrt(2), [[1, 1], [1, -1]])
+    assert np.allclose(m("CPHASE", math.pi), m("CZ"))
+    ih = np.kron(np.eye(2), m("H"))          # H on the low local bit = the target
+    assert np.allclose(ih @ m("CZ") @ ih, m("CNOT"))
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    B = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+    assert np.allclose(m("SWAP") @ np.kron(A, B) @ m("SWAP"), np.kron(B, A))
+    # CNOT with the first operand as control: |10> -> |11>
+    e10 = np.zeros(4)
+    e10[2] = 1
+    assert np.allclose(m("CNOT") @ e10, [0, 0, 0, 1])
+
+
+# ------------------------------------------------- two independent embeddings
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_2q_embeddings_agree(n):
+    rng = np.random.default_rng(n)
+    g = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    for q0 in range(n):
+        for q1 in range(n):
+            if q0 != q1:
+                assert np.allclose(K.embed_2q_kron(n, q0, q1, g), K.embed_2q_def(n, q0, q1, g))
+
+
+def test_1q_embedding_is_paper_kron_order():
+    # paper qubit k = 1 is the leftmost factor = most significant bit = q = n-1
+    n = 3
+    U = K.embed_1q(n, n - 1, G.matrix("X"))
+    assert np.array_equal(U @ np.eye(8)[:, 0], np.eye(8)[:, 4])
+
+
+# ----------------------------------------- per-gate oracle vs brute-force MTP
+
+def _all_single_gates(n, rng):
+    out = []
+    for name in synth.GATE_NAMES:
+        ar = G.arity(name)
+        ang = float(rng.uniform(0, 2 * math.pi))
+        if ar == 1:
+            out += [synth.Gate(name, q, -1, ang) for q in range(n)]
+        elif ar == 2 and n >= 2:
+            out += [synth.Gate(name, a, b, ang) for a in range(n) for b in range(n) if a != b]
+        elif ar == 0:
+            out += [synth.Gate(name, -1, -1, 0.0, -1, int(j)) for j in
+                    sorted(set([0, (1 << n) - 1, int(rng.integers(1 << n))]))]
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
+def test_every_gate_every_position_vs_kron(n):
+    rng = np.random.default_rng(100 + n)
+    for g in _all_single_gates(n, rng):
+        psi0 = synth.random_state(n, int(rng.integers(1 << 30)))
+        ref = K.mtp_operator(n, g) @ psi0
+        got = O.simulate(n, [g], psi0=psi0)
+        assert np.max(np.abs(got - ref)) < 1e-14, g
+
+
+@pytest.mark.parametrize("n,depth,seed", [(5, 10, 0), (8, 4, 1), (10, 2, 2)])
+def test_random_circuit_vs_kron(n, depth, seed):
+    gates = synth.random_circuit(n, depth, seed)
+    ref = K.simulate_kron(n, gates)
+    got = O.simulate(n, gates)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_capacity_mix_vs_kron():
+    gates = synth.capacity_circuit(7, 6, 3)
+    assert np.max(np.abs(O.simulate(7, gates) - K.simulate_kron(7, gates))) < 1e-12
+
+
+def test_qnn_ansatz_vs_kron():
+    n, L = 5, 3
+    gates = synth.qnn_ansatz(n, L)
+    p = synth.qnn_params(n, L, 1, 7)[0]
+    assert np.max(np.abs(O.simulate(n, gates, p) - K.simulate_kron(n, gates, p))) < 1e-12
+
+
+# -------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 4, 9, 13])
+def test_hadamard_layer_on_basis_states(n):
+    hl = [synth.Gate("H", q) for q in range(n)]
+    psi = O.simulate(n, hl)
+    assert np.max(np.abs(psi - 2.0 ** (-n / 2))) < 1e-15
+    j = (0x2D5B & ((1 << n) - 1)) | 1
+    psi = O.simulate(n, hl, psi0=O.basis_state(n, j))
+    r = np.arange(1 << n)
+    par = np.array([bin(x & j).count("1") & 1 for x in r])
+    assert np.max(np.abs(psi - 2.0 ** (-n / 2) * (1 - 2 * par))) < 1e-15
+
+
+@pytest.mark.parametrize("n", [2, 5, 12])
+def test_ghz(n):
+    gates = [synth.Gate("H", 0)] + [synth.Gate("CNOT", q, q + 1) for q in range(n - 1)]
+    psi = O.simulate(n, gates)
+    ref = np.zeros(1 << n, dtype=complex)
+    ref[0] = ref[-1] = 1 / math.sqrt(2)
+    assert np.max(np.abs(psi - ref)) < 1e-15
+
+
+def test_norm_and_mirror():
+    n = 11
+    gates = synth.random_circuit(n, 12, 5)
+    psi = O.simulate(n, gates)
+    assert abs(O.norm2(psi) - 1.0) < 1e-13
+    back = O.apply(psi, n, synth.inverse_circuit(gates))
+    assert np.max(np.abs(back - O.basis_state(n))) < 1e-13
+
+
+def test_readouts():
+    n = 6
+    for j in (0, 5, 63, 42):
+        psi = O.basis_state(n, j)
+        for q in range(n):
+            assert O.expect_z(psi, q) == 1 - 2 * ((j >> q) & 1)
+    for a in ANGLES:
+        for name in ("RY", "RX"):
+            psi = O.simulate(1, [synth.Gate(name, 0, -1, a)])
+            assert abs(O.expect_z(psi, 0) - math.cos(a)) < 1e-15
+        psi = O.simulate(1, [synth.Gate("RY", 0, -1, 0.7), synth.Gate("RZ", 0, -1, a)])
+        assert abs(O.expect_z(psi, 0) - math.cos(0.7)) < 1e-15
+    psi = synth.random_state(9, 3)
+    assert abs(O.norm2(psi) - 1.0) < 1e-14
+    assert abs(O.inner(psi, psi) - 1.0) < 1e-14
+    phi = synth.random_state(9, 4)
+    assert abs(O.inner(psi, phi) - np.vdot(psi, phi)) < 1e-14
+
+
+# ----------------------------------------------------------- RH and Alg. 1
+
+def test_paper_sign_example():
+    (row,) = [r for r in _golden_lines("paper_rh_signs.txt") if r[0] == "sign"]
+    kv = dict(x.split("=") for x in row[1:4])
+    assert RH.compute_sign(int(kv["r"]), int(kv["c"]), int(kv["n"])) == int(row[4])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_quadrant_sign_matches_kronecker_hadamard(n):
+    Hn = K.kron_all([G.matrix("H")] * n) * math.sqrt(1 << n)
+    for r in range(1 << n):
+        for c in range(1 << n):
+            assert RH.compute_sign(r, c, n) == round(Hn[r, c].real)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7])
+def test_rh_mvm_methods_vs_kron_and_oracle(n):
+    S = synth.random_state(n, 50 + n)
+    ref = K.kron_all([G.matrix("H")] * n) @ S
+    via_oracle = O.simulate(n, [synth.Gate("H", q) for q in range(n)], psi0=S)
+    assert np.max(np.abs(via_oracle - ref)) < 1e-14
+    outs = [RH.rh_mvm_logarithm(S)[0], RH.rh_mvm_quarter(S)[0]]
+    if n <= 5:
+        outs.append(RH.rh_mvm_non_optimized(S)[0])
+    if n >= 2:
+        outs.append(RH.rh_mvm_block(S, 2 if n > 2 else 1)[0])
+    for o in outs:
+        assert np.max(np.abs(o - ref)) < 1e-13
+
+
+def test_sign_counts_table2_and_n5_examples():
+    rows = _golden_lines("paper_rh_signs.txt")
+    S = synth.random_state(5, 0)
+    for r in rows:
+        kv = dict(x.split("=") for x in r[1:] if "=" in x)
+        if r[0] == "quarter":
+            _, cnt = RH.rh_mvm_quarter(S)
+            assert cnt == int(kv["rows"]) * int(kv["per_row"])
+        elif r[0] == "block":
+            b = int(kv["b"])
+            _, cnt = RH.rh_mvm_block(S, b)
+            assert cnt == 16 * int(kv["per_row"])
+        elif r[0] == "logarithm":
+            _, cnt = RH.rh_mvm_logarithm(S)
+            assert cnt == 16 * (int(kv["per_row"]) - 1)   # index 0 is not computed
+    for n in range(2, 8):
+        S = synth.random_state(n, n)
+        assert RH.rh_mvm_logarithm(S)[1] == RH.sign_count_formula("logarithm", n)
+        assert RH.rh_mvm_quarter(S)[1] == RH.sign_count_formula("quarter", n)
+        for b in (1, 2):
+            if (1 << (n - 1)) % b == 0:
+                assert RH.rh_mvm_block(S, b)[1] == RH.sign_count_formula("block", n, b)
+    S = synth.random_state(4, 1)
+    assert RH.rh_mvm_non_optimized(S)[1] == RH.sign_count_formula("non-optimized", 4)
+
+
+def test_theorem3_optimal_block():
+    for n in (3, 5, 7, 9):
+        f = {b: (1 << (n - 1)) // b + b - 1 for b in [1 << i for i in range(n)]}
+        best = min(f.values())
+        b_opt = math.sqrt(1 << (n - 1))
+        # the optimum over powers of two sits at the power(s) of two next to sqrt(2^(n-1))
+        assert any(f[b] == best and b / 2 <= b_opt <= 2 * b for b in f)
+
+
+# ---------------------------------------------------------------- Grover
+
+@pytest.mark.parametrize("n", [3, 4, 6, 9, 12])
+def test_grover_closed_form(n):
+    m = synth.grover_marked(n, n)
+    k = synth.grover_iterations(n)
+    psi = O.simulate(n, synth.grover_circuit(n, m))
+    a, b, p = O.grover_closed_form(n, k)
+    sgn = (-1) ** k
+    assert abs(psi[m] - sgn * a) < 1e-12
+    others = np.delete(psi, m)
+    assert np.max(np.abs(others - sgn * b)) < 1e-12
+    assert abs(abs(psi[m]) ** 2 - p) < 1e-12
+
+
+def test_grover_golden_n20():
+    rows = {r[0]: float(r[1]) for r in _golden_lines("grover_n20.txt")}
+    a, b, p = O.grover_closed_form(20, 804)
+    assert rows["marked"] == a and rows["unmarked"] == b and rows["p_success"] == p
+    assert synth.grover_iterations(20) == int(rows["iterations"])
+
+
+# ------------------------------------------------------------- gradients
+
+def test_gradients_single_qubit_closed_form():
+    # f(t) = <Z> of RY(t)|0> = cos t, so df/dt = -sin t
+    g = [synth.Gate("RY", 0, -1, 0.0, 0)]
+    for t in ANGLES:
+        p = np.array([t])
+        assert abs(O.grad_param_shift(1, g, p, [0])[0] + math.sin(t)) < 1e-15
+        assert abs(O.grad_fd(1, g, p, [0])[0] + math.sin(t)) < 1e-9
+
+
+def test_gradients_ps_fd_kron_agree():
+    n, L = 4, 2
+    gates = synth.qnn_ansatz(n, L)
+    p = synth.qnn_params(n, L, 1, 11)[0]
+    which = list(range(len(p)))
+    ps = O.grad_param_shift(n, gates, p, which)
+    fd = O.grad_fd(n, gates, p, which)
+    assert np.max(np.abs(ps - fd)) < 1e-8
+    # third route: d psi / dt with the gate's matrix replaced by -i/2 P U(t),
+    # every operator formed by brute-force Kronecker products
+    Zn = K.embed_1q(n, 0, PZ)
+    psi = K.simulate_kron(n, gates, p)
+    for k, par in enumerate(which):
+        dpsi = np.zeros(1 << n, dtype=complex)
+        dpsi[0] = 1.0
+        for g in gates:
+            U = K.mtp_operator(n, g, p)
+            if g.param == par:
+                Pm = K.embed_1q(n, g.q0, G.generator(g.name))
+                U = -0.5j * Pm @ U
+            dpsi = U @ dpsi
+        d = 2 * np.real(np.vdot(psi, Zn @ dpsi))
+        assert abs(d - ps[k]) < 1e-12
