@@ -1,0 +1,200 @@
+/*
+ * sv.h — C ABI of the MI355X (gfx950) state-vector gate-application library.
+ *
+ * The library applies the gates of a circuit in place to 2^n complex
+ * amplitudes on one GPU, never forming the 2^n x 2^n operation matrix
+ * U = I^(k-1) (x) G (x) I^(n-k) of the paper's Sec. II-A. Sparse gates are
+ * applied from a gate-local compressed form (value + index, the DAX idea of
+ * Sec. III-A), dense 1- and 2-qubit gates as strided butterflies, and
+ * Hadamard layers from the RH rule of Sec. III-B (one magnitude 2^(-m/2) and
+ * signs (-1)^popcount(r & c) computed on demand).
+ *
+ * Conventions
+ *   - Amplitude index i = sum_q b_q 2^q: qubit q is bit q (the paper's qubit k,
+ *     the k-th Kronecker factor from the left, is q = n - k).
+ *   - A state is interleaved complex: SV_C128 = (double re, double im),
+ *     SV_C64 = (float re, float im), the memory layout of torch.complex128 /
+ *     torch.complex64. A batch of B states is [B][2^n], row-major.
+ *   - A 2-qubit gate's 4x4 matrix is indexed by (b_q0 << 1) | b_q1: the first
+ *     operand is the high local bit (CNOT: q0 = control, q1 = target).
+ *
+ * Errors
+ *   Every call returns an sv_status and never throws. Argument errors are
+ *   detected on the host before anything is launched and leave the state
+ *   unchanged; sv_last_error() (thread-local) describes the last failure.
+ *   Device faults surface as SV_EDEVICE at the next synchronizing call.
+ *   A handle is not thread-safe: use it from one host thread.
+ *
+ * Streams
+ *   All device work of a handle goes to the HIP stream given at sv_alloc
+ *   (NULL = the default stream) or set later with sv_set_stream.
+ *   sv_apply_circuit is asynchronous; the readouts synchronize that stream.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sv_status {
+    SV_OK = 0,
+    SV_EINVAL = -1,       /* bad argument: nothing was launched */
+    SV_ENOMEM = -2,       /* device or host allocation failed */
+    SV_EDEVICE = -3,      /* a HIP call or a kernel failed */
+    SV_EUNSUPPORTED = -4  /* valid request this build does not support */
+} sv_status;
+
+typedef enum sv_dtype { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
+
+/* Gate kinds. Matrices (c = cos(t/2), s = sin(t/2)):
+ *   X = [[0,1],[1,0]], Y = [[0,-i],[i,0]] (both printed in Sec. III-A1),
+ *   Z = diag(1,-1), H = [[1,1],[1,-1]]/sqrt2, S = diag(1,i), SDG = S^dagger,
+ *   T = diag(1,e^{i pi/4}), TDG = T^dagger, RX(t) = [[c,-is],[-is,c]],
+ *   RY(t) = [[c,-s],[s,c]], RZ(t) = diag(e^{-it/2}, e^{it/2}), P(t) = diag(1,e^{it}),
+ *   CNOT, CZ = diag(1,1,1,-1), SWAP, CPHASE(t) = diag(1,1,1,e^{it}),
+ *   MARK = I - 2|m><m| on all n qubits (m = sv_gate.index; the Grover oracle
+ *   of Sec. IV-D, and with m = 0 the zero-state reflection). */
+typedef enum sv_gate_kind {
+    SV_GATE_I = 0, SV_GATE_X = 1, SV_GATE_Y = 2, SV_GATE_Z = 3, SV_GATE_H = 4,
+    SV_GATE_S = 5, SV_GATE_SDG = 6, SV_GATE_T = 7, SV_GATE_TDG = 8,
+    SV_GATE_RX = 9, SV_GATE_RY = 10, SV_GATE_RZ = 11, SV_GATE_P = 12,
+    SV_GATE_CNOT = 13, SV_GATE_CZ = 14, SV_GATE_SWAP = 15, SV_GATE_CPHASE = 16,
+    SV_GATE_MARK = 17,
+    SV_GATE_KIND_COUNT = 18
+} sv_gate_kind;
+
+/* One gate, 32 bytes. q1 = -1 for 1-qubit gates and MARK; q0 = -1 for MARK.
+ * param = -1: use `angle`; param >= 0: the angle is params[b][param] for batch
+ * entry b (see sv_apply_circuit). index: basis index of MARK, else ignored. */
+typedef struct sv_gate {
+    int32_t kind;
+    int32_t q0;
+    int32_t q1;
+    int32_t param;
+    double angle;
+    uint64_t index;
+} sv_gate;
+
+typedef struct sv_state_s *sv_state;
+
+/* Create a batch of `batch` n-qubit states set to |0...0> (Sec. II-A: the
+ * register of 2^n amplitudes). 1 <= n_qubits <= 34, batch >= 1.
+ * dev_buf: NULL -> the library allocates (hipMalloc) and owns the memory;
+ *          else a device buffer of at least batch * 2^n * sizeof(amplitude)
+ *          bytes, 256-byte aligned, that the library borrows: the caller keeps
+ *          it alive until sv_free returns and the stream work has completed.
+ * hip_stream: a hipStream_t or NULL (default stream).
+ * Errors: SV_EINVAL (bad n, dtype, batch, size or alignment), SV_ENOMEM. */
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, int batch, void *dev_buf,
+                   size_t buf_bytes, void *hip_stream, sv_state *out);
+
+/* Release the handle (and the memory it owns). Waits for its stream. */
+sv_status sv_free(sv_state s);
+
+/* Use another HIP stream for the handle's later work. */
+sv_status sv_set_stream(sv_state s, void *hip_stream);
+
+/* Set every state of the batch to the basis state |j>, j < 2^n. */
+sv_status sv_set_basis(sv_state s, uint64_t j);
+
+/* The caller wrote the amplitudes through the device buffer (for example a
+ * borrowed torch tensor): forget any known basis state, so that no Hadamard
+ * layer is generated instead of read. */
+sv_status sv_mark_modified(sv_state s);
+
+/* Apply the gates in order, in place, to every state of the batch
+ * (U_m ... U_1 |psi>, Sec. II-A), asynchronously on the handle's stream.
+ * gates: host array of n_gates records, copied before return.
+ * params: host array [batch][n_params] (row-major) of angles referenced by
+ *         gates with param >= 0, or NULL when no gate references one.
+ * Gates are validated first (kind, qubits in range and distinct, MARK index
+ * < 2^n, param < n_params); on SV_EINVAL nothing was launched.
+ * When the handle is known to hold a basis state |j> (after sv_alloc or
+ * sv_set_basis) and the circuit opens with Hadamards, those amplitudes are
+ * generated on demand from the RH rule instead of being read (Sec. III-B). */
+sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates,
+                           const double *params, size_t n_params);
+
+/* <Z_q> = sum_i |a_i|^2 (1 - 2 b_q(i)) for every batch entry, accumulated in
+ * FP64 in a fixed order (Sec. II-A: probabilities are |alpha|^2).
+ * out: host array [batch]. Synchronizes the stream. */
+sv_status sv_expect_z(sv_state s, int qubit, double *out);
+
+/* sum_i |a_i|^2 per batch entry (should be 1), FP64. out: host [batch]. */
+sv_status sv_norm(sv_state s, double *out);
+
+/* Amplitudes of batch entry b at k basis indices idx[0..k) (each < 2^n),
+ * returned as FP64 (re, im) pairs in out[0 .. 2k). Synchronizes the stream. */
+sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double *out);
+
+/* Adjoint gradient of f_b = <Z_qubit> (of the circuit applied to |0...0>) with
+ * respect to params[b][p], for every batch entry b. Runs the forward circuit
+ * from |0...0> (the handle ends holding the final states), then one reverse
+ * sweep on two states per entry, psi and lambda = Z_qubit psi:
+ * for each gate g from last to first, if g is RX/RY/RZ(params[b][p]) then
+ * df/dp += Im <lambda|P|psi> (P its Pauli), then psi <- U_g^dagger psi and
+ * lambda <- U_g^dagger lambda. Inner products accumulate in FP64.
+ * expect: host [batch] (may be NULL); grad: host [batch][n_params], zeroed
+ * for parameters no rotation uses. Needs a second device buffer of the
+ * handle's size (allocated by the library). Synchronizes the stream.
+ * Only RX, RY and RZ may reference parameters (SV_EUNSUPPORTED otherwise). */
+sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates,
+                              const double *params, size_t n_params, int qubit,
+                              double *expect, double *grad);
+
+/* Wait for the handle's stream; reports asynchronous device faults. */
+sv_status sv_sync(sv_state s);
+
+/* Device pointer of batch entry 0 (amplitudes are contiguous). */
+void *sv_device_ptr(sv_state s);
+
+/* Tuning and testing options (values are validated, SV_EINVAL otherwise):
+ *   SV_OPT_FUSE           1 (default): fuse gates into LDS-tiled passes;
+ *                         0: one pass per gate (parity of fused vs unfused).
+ *   SV_OPT_MIN_LOW_QUBITS lowest qubits always inside a tile (contiguous HBM
+ *                         runs of 2^value amplitudes), 3..7, default 6.
+ *   SV_OPT_MAX_DENSE      dense gates allowed per pass (ALU budget), >= 1.
+ *   SV_OPT_ON_DEMAND_H    1 (default): generate leading Hadamard layers of a
+ *                         basis state on demand; 0: apply them as gates.
+ *   SV_OPT_SMALL_PATH     1 (default): states of n below the tiled minimum run
+ *                         in one workgroup; 2: force that path when n allows.
+ *   SV_OPT_PROFILE        1: time every pass kernel with HIP events (see
+ *                         sv_profile_read); 0 (default): off. */
+enum sv_option {
+    SV_OPT_FUSE = 1,
+    SV_OPT_MIN_LOW_QUBITS = 2,
+    SV_OPT_MAX_DENSE = 3,
+    SV_OPT_ON_DEMAND_H = 4,
+    SV_OPT_SMALL_PATH = 5,
+    SV_OPT_PROFILE = 6
+};
+sv_status sv_set_option(sv_state s, int option, int64_t value);
+
+/* Statistics of the last sv_apply_circuit plan. out[0] = passes,
+ * out[1] = register-tile exchanges through LDS, out[2] = gates applied,
+ * out[3] = leading Hadamards generated on demand, out[4] = kernel launches,
+ * out[5] = algorithmic HBM bytes of the plan (2 * 2^n * amplitude bytes per
+ * pass, one read fewer when a pass generates its input), per batch entry. */
+sv_status sv_plan_stats(sv_state s, int64_t out[8]);
+
+/* With SV_OPT_PROFILE on: total milliseconds and count of the pass-kernel
+ * launches timed since the last read (HIP events on the handle's stream);
+ * resets the counters. Synchronizes the stream. */
+sv_status sv_profile_read(sv_state s, double *total_ms, int64_t *launches,
+                          double *bytes);
+
+/* Description of the last error on this thread ("" if none). */
+const char *sv_last_error(void);
+
+/* Library version string. */
+const char *sv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H */

@@ -1,0 +1,612 @@
+// C ABI of the state-vector library: handles, validation, errors, streams,
+// plan upload and kernel launches. Declarations and contracts: include/sv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "../../include/sv_debug.h"
+#include "sv_kernels.hpp"
+#include "sv_planner.hpp"
+
+using namespace sv;
+
+namespace {
+
+thread_local std::string g_err;
+
+sv_status fail(sv_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+sv_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? SV_ENOMEM : SV_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define SV_HIP(call, what)                              \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+struct sv_state_s {
+    int n = 0;
+    sv_dtype dt = SV_C128;
+    int batch = 1;
+    size_t amp_bytes = 16;
+    size_t bytes = 0;
+    void *buf = nullptr;
+    bool owned = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    bool basis_known = true;
+    uint64_t basis_j = 0;
+
+    // options
+    bool fuse = true;
+    int min_low = 6;
+    int max_dense = 1 << 20;
+    bool gen_h = true;
+    int small_mode = 1;
+    bool profile = false;
+
+    // plan upload: pinned staging + device copy
+    void *h_stage = nullptr;
+    size_t h_cap = 0;
+    void *d_plan = nullptr;
+    size_t d_cap = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+
+    // readout scratch
+    double *d_red = nullptr;
+    size_t d_red_cap = 0;
+    double *h_out = nullptr;
+    size_t h_out_cap = 0;
+    uint64_t *d_idx = nullptr;
+    size_t d_idx_cap = 0;
+
+    // adjoint: second state
+    void *d_lambda = nullptr;
+
+    int64_t stats[8] = {0};
+
+    struct Timed { hipEvent_t a, b; double bytes; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+PlanOptions plan_options(const sv_state_s *s) {
+    PlanOptions o;
+    if (s->dt == SV_C128) {
+        o.R = kRegBitsC128;
+        o.v = 0;
+        o.m = 3;
+        o.small_max = kSmallMaxQubitsC128;
+    } else {
+        o.R = kRegBitsC64;
+        o.v = 1;
+        o.m = 4;
+        o.small_max = kSmallMaxQubitsC64;
+    }
+    o.c = s->min_low;
+    o.w_max = kMaxThreadBits;
+    o.fuse = s->fuse;
+    o.max_dense = s->max_dense;
+    o.gen_h = s->gen_h;
+    o.basis_known = s->basis_known;
+    o.basis_j = s->basis_j;
+    o.small_mode = s->small_mode;
+    return o;
+}
+
+sv_status ensure_device_buf(void **p, size_t *cap, size_t need, const char *what) {
+    if (*cap >= need) return SV_OK;
+    if (*p) {
+        hipError_t e = hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    size_t sz = std::max<size_t>(need, 4096);
+    SV_HIP(hipMalloc(p, sz), what);
+    *cap = sz;
+    return SV_OK;
+}
+
+sv_status ensure_host_buf(void **p, size_t *cap, size_t need, const char *what) {
+    if (*cap >= need) return SV_OK;
+    if (*p) {
+        hipError_t e = hipHostFree(*p);
+        *p = nullptr;
+        *cap = 0;
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    size_t sz = std::max<size_t>(need, 4096);
+    SV_HIP(hipHostMalloc(p, sz, hipHostMallocDefault), what);
+    *cap = sz;
+    return SV_OK;
+}
+
+hipEvent_t get_event(sv_state_s *s) {
+    if (!s->event_pool.empty()) {
+        hipEvent_t e = s->event_pool.back();
+        s->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Sections of the uploaded plan, 256-byte aligned.
+struct Layout {
+    size_t passes = 0, layouts = 0, ops = 0, sops = 0, consts = 0, total = 0;
+};
+
+Layout plan_sections(const Plan &p, int batch, size_t real_bytes) {
+    Layout L;
+    size_t o = 0;
+    L.passes = o;
+    o = align_up(o + p.passes.size() * sizeof(DevPass), 256);
+    L.layouts = o;
+    o = align_up(o + p.layouts.size() * sizeof(DevLayout), 256);
+    L.ops = o;
+    o = align_up(o + p.ops.size() * sizeof(DevOp), 256);
+    L.sops = o;
+    o = align_up(o + p.sops.size() * sizeof(SmallOp), 256);
+    L.consts = o;
+    o = align_up(o + (size_t)batch * p.cstride * real_bytes, 256);
+    L.total = std::max<size_t>(o, 256);
+    return L;
+}
+
+void serialize_plan(const Plan &p, const Layout &L, const sv_gate *gates, const double *params,
+                    size_t n_params, int batch, bool f32, char *dst) {
+    if (!p.passes.empty()) std::memcpy(dst + L.passes, p.passes.data(), p.passes.size() * sizeof(DevPass));
+    if (!p.layouts.empty())
+        std::memcpy(dst + L.layouts, p.layouts.data(), p.layouts.size() * sizeof(DevLayout));
+    if (!p.ops.empty()) std::memcpy(dst + L.ops, p.ops.data(), p.ops.size() * sizeof(DevOp));
+    if (!p.sops.empty()) std::memcpy(dst + L.sops, p.sops.data(), p.sops.size() * sizeof(SmallOp));
+    if (p.cstride) materialize_consts(p, gates, params, n_params, batch, f32, dst + L.consts);
+}
+
+sv_status check_handle(sv_state s) {
+    if (!s) return fail(SV_EINVAL, "null handle");
+    hipError_t e = hipSetDevice(s->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return SV_OK;
+}
+
+// Upload plan and launch it on the handle's stream, on `state`.
+sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gates,
+                   const double *params, size_t n_params) {
+    const bool f32 = s->dt == SV_C64;
+    const size_t real_bytes = f32 ? 4 : 8;
+    const Layout L = plan_sections(p, s->batch, real_bytes);
+    if (s->upload_pending) {
+        SV_HIP(hipEventSynchronize(s->upload_done), "wait for previous plan upload");
+        s->upload_pending = false;
+    }
+    sv_status st = ensure_host_buf(&s->h_stage, &s->h_cap, L.total, "hipHostMalloc(plan)");
+    if (st != SV_OK) return st;
+    // the device plan buffer may still be read by queued kernels: grow only
+    // after the stream has drained
+    if (s->d_cap < L.total) {
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        st = ensure_device_buf(&s->d_plan, &s->d_cap, L.total, "hipMalloc(plan)");
+        if (st != SV_OK) return st;
+    }
+    serialize_plan(p, L, gates, params, n_params, s->batch, f32, static_cast<char *>(s->h_stage));
+    SV_HIP(hipMemcpyAsync(s->d_plan, s->h_stage, L.total, hipMemcpyHostToDevice, s->stream),
+           "hipMemcpyAsync(plan)");
+    if (!s->upload_done) SV_HIP(hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming), "hipEventCreate");
+    SV_HIP(hipEventRecord(s->upload_done, s->stream), "hipEventRecord");
+    s->upload_pending = true;
+
+    char *d = static_cast<char *>(s->d_plan);
+    const uint64_t N = 1ull << s->n;
+    const double io_bytes = 2.0 * (double)N * (double)s->amp_bytes * s->batch;
+    if (p.small) {
+        if (p.sops.empty()) return SV_OK;
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (s->profile) {
+            ea = get_event(s);
+            eb = get_event(s);
+            if (ea) hipEventRecord(ea, s->stream);
+        }
+        SV_HIP(launch_small((int)s->dt, state, s->n, s->batch,
+                            reinterpret_cast<const SmallOp *>(d + L.sops), (int)p.sops.size(),
+                            d + L.consts, p.cstride, s->stream),
+               "launch k_small");
+        if (s->profile && ea && eb) {
+            hipEventRecord(eb, s->stream);
+            s->timed.push_back({ea, eb, io_bytes});
+        }
+        return SV_OK;
+    }
+    const DevPass *dpass = reinterpret_cast<const DevPass *>(d + L.passes);
+    for (size_t i = 0; i < p.passes.size(); ++i) {
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (s->profile) {
+            ea = get_event(s);
+            eb = get_event(s);
+            if (ea) hipEventRecord(ea, s->stream);
+        }
+        SV_HIP(launch_pass((int)s->dt, state, N, s->batch, dpass, (int)i, p.passes[i],
+                           reinterpret_cast<const DevLayout *>(d + L.layouts),
+                           reinterpret_cast<const DevOp *>(d + L.ops), d + L.consts, p.cstride,
+                           s->stream),
+               "launch k_pass");
+        if (s->profile && ea && eb) {
+            hipEventRecord(eb, s->stream);
+            const bool gen = (p.passes[i].flags & PASS_GENERATE) != 0;
+            s->timed.push_back({ea, eb, gen ? io_bytes * 0.5 : io_bytes});
+        }
+    }
+    return SV_OK;
+}
+
+int64_t plan_hbm_bytes(const Plan &p, int n, size_t amp_bytes) {
+    const int64_t N = 1ll << n;
+    if (p.small) return p.sops.empty() ? 0 : 2 * N * (int64_t)amp_bytes;
+    int64_t b = 0;
+    for (const DevPass &dp : p.passes)
+        b += ((dp.flags & PASS_GENERATE) ? 1 : 2) * N * (int64_t)amp_bytes;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+const char *sv_version(void) { return "sv-gfx950 0.1"; }
+
+sv_status sv_alloc(int n_qubits, sv_dtype dtype, int batch, void *dev_buf, size_t buf_bytes,
+                   void *hip_stream, sv_state *out) {
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
+    if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch %d outside 1..65535", batch);
+    const size_t amp = dtype == SV_C128 ? 16 : 8;
+    const size_t bytes = ((size_t)1 << n_qubits) * amp * (size_t)batch;
+    if (dev_buf) {
+        if (buf_bytes < bytes)
+            return fail(SV_EINVAL, "buffer of %zu bytes is smaller than the %zu needed", buf_bytes, bytes);
+        if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
+            return fail(SV_EINVAL, "device buffer is not 256-byte aligned");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    sv_state_s *s = new (std::nothrow) sv_state_s();
+    if (!s) return fail(SV_ENOMEM, "host allocation failed");
+    s->n = n_qubits;
+    s->dt = dtype;
+    s->batch = batch;
+    s->amp_bytes = amp;
+    s->bytes = bytes;
+    s->device = dev;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    if (const char *fail_alloc = std::getenv("SV_DEBUG_FAIL_ALLOC")) {
+        if (std::atoi(fail_alloc) != 0 && !dev_buf) {
+            delete s;
+            return fail(SV_ENOMEM, "allocation failure injected by SV_DEBUG_FAIL_ALLOC");
+        }
+    }
+    if (dev_buf) {
+        s->buf = dev_buf;
+        s->owned = false;
+    } else {
+        e = hipMalloc(&s->buf, bytes);
+        if (e != hipSuccess) {
+            delete s;
+            return hip_fail(e, "hipMalloc(state)");
+        }
+        s->owned = true;
+    }
+    e = launch_fill_basis((int)dtype, s->buf, 1ull << n_qubits, batch, 0, s->stream);
+    if (e != hipSuccess) {
+        if (s->owned) hipFree(s->buf);
+        delete s;
+        return hip_fail(e, "launch fill");
+    }
+    s->basis_known = true;
+    s->basis_j = 0;
+    *out = s;
+    return SV_OK;
+}
+
+sv_status sv_free(sv_state s) {
+    if (!s) return SV_OK;
+    hipSetDevice(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    for (auto &t : s->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    for (hipEvent_t ev : s->event_pool) hipEventDestroy(ev);
+    if (s->upload_done) hipEventDestroy(s->upload_done);
+    if (s->owned && s->buf) hipFree(s->buf);
+    if (s->d_lambda) hipFree(s->d_lambda);
+    if (s->d_plan) hipFree(s->d_plan);
+    if (s->d_red) hipFree(s->d_red);
+    if (s->d_idx) hipFree(s->d_idx);
+    if (s->h_stage) hipHostFree(s->h_stage);
+    if (s->h_out) hipHostFree(s->h_out);
+    delete s;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize at free");
+    return SV_OK;
+}
+
+sv_status sv_set_stream(sv_state s, void *hip_stream) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return SV_OK;
+}
+
+sv_status sv_set_basis(sv_state s, uint64_t j) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    if (j >= (1ull << s->n)) return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)j, s->n);
+    SV_HIP(launch_fill_basis((int)s->dt, s->buf, 1ull << s->n, s->batch, j, s->stream), "launch fill");
+    s->basis_known = true;
+    s->basis_j = j;
+    return SV_OK;
+}
+
+sv_status sv_mark_modified(sv_state s) {
+    if (!s) return fail(SV_EINVAL, "null handle");
+    s->basis_known = false;
+    return SV_OK;
+}
+
+sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, const double *params,
+                           size_t n_params) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+    std::string err;
+    if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
+        return fail(SV_EINVAL, "%s", err.c_str());
+    if (n_gates == 0) return SV_OK;
+    Plan p = build_plan(s->n, gates, n_gates, plan_options(s));
+    st = run_plan(s, s->buf, p, gates, params, n_params);
+    if (st != SV_OK) return st;
+    s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
+    s->stats[1] = p.n_exch;
+    s->stats[2] = p.gates_applied;
+    s->stats[3] = p.n_gen_h;
+    s->stats[4] = p.small ? (p.sops.empty() ? 0 : 1) : (int64_t)p.passes.size();
+    s->stats[5] = plan_hbm_bytes(p, s->n, s->amp_bytes);
+    if (p.gates_applied > 0) s->basis_known = false;
+    return SV_OK;
+}
+
+static sv_status reduce(sv_state s, int qubit, double *out) {
+    const size_t np = reduce_partials_size(s->n) * (size_t)s->batch + (size_t)s->batch;
+    sv_status st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap,
+                                     np * sizeof(double), "hipMalloc(reduce)");
+    if (st != SV_OK) return st;
+    st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap,
+                         (size_t)s->batch * sizeof(double), "hipHostMalloc(out)");
+    if (st != SV_OK) return st;
+    double *d_out = s->d_red + reduce_partials_size(s->n) * (size_t)s->batch;
+    SV_HIP(launch_reduce((int)s->dt, s->buf, s->n, s->batch, qubit, s->d_red, d_out, s->stream),
+           "launch reduce");
+    SV_HIP(hipMemcpyAsync(s->h_out, d_out, (size_t)s->batch * sizeof(double), hipMemcpyDeviceToHost,
+                          s->stream),
+           "hipMemcpyAsync(out)");
+    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    std::memcpy(out, s->h_out, (size_t)s->batch * sizeof(double));
+    return SV_OK;
+}
+
+sv_status sv_expect_z(sv_state s, int qubit, double *out) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
+    return reduce(s, qubit, out);
+}
+
+sv_status sv_norm(sv_state s, double *out) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    if (!out) return fail(SV_EINVAL, "out is NULL");
+    return reduce(s, -1, out);
+}
+
+sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double *out) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    if (b < 0 || b >= s->batch) return fail(SV_EINVAL, "batch entry %d out of range", b);
+    if (k == 0) return SV_OK;
+    if (!idx || !out) return fail(SV_EINVAL, "idx or out is NULL");
+    const uint64_t N = 1ull << s->n;
+    for (size_t i = 0; i < k; ++i)
+        if (idx[i] >= N) return fail(SV_EINVAL, "index %llu >= 2^%d", (unsigned long long)idx[i], s->n);
+    const size_t need_host = std::max(k * sizeof(uint64_t), 2 * k * sizeof(double));
+    st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, need_host, "hipHostMalloc");
+    if (st != SV_OK) return st;
+    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_idx), &s->d_idx_cap,
+                           k * sizeof(uint64_t) + 2 * k * sizeof(double), "hipMalloc(idx)");
+    if (st != SV_OK) return st;
+    // the pinned buffer may still feed an earlier copy only after a sync, which
+    // every readout performs; safe to reuse here
+    std::memcpy(s->h_out, idx, k * sizeof(uint64_t));
+    SV_HIP(hipMemcpyAsync(s->d_idx, s->h_out, k * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream),
+           "hipMemcpyAsync(idx)");
+    double *d_vals = reinterpret_cast<double *>(s->d_idx + k);
+    const char *base = static_cast<const char *>(s->buf) + (size_t)b * N * s->amp_bytes;
+    SV_HIP(launch_gather((int)s->dt, base, s->d_idx, k, d_vals, s->stream), "launch gather");
+    SV_HIP(hipMemcpyAsync(s->h_out, d_vals, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+           "hipMemcpyAsync(amplitudes)");
+    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    std::memcpy(out, s->h_out, 2 * k * sizeof(double));
+    return SV_OK;
+}
+
+sv_status sv_sync(sv_state s) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    return SV_OK;
+}
+
+void *sv_device_ptr(sv_state s) { return s ? s->buf : nullptr; }
+
+sv_status sv_set_option(sv_state s, int option, int64_t value) {
+    if (!s) return fail(SV_EINVAL, "null handle");
+    switch (option) {
+    case SV_OPT_FUSE:
+        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_FUSE takes 0 or 1");
+        s->fuse = value != 0;
+        return SV_OK;
+    case SV_OPT_MIN_LOW_QUBITS:
+        if (value < 3 || value > 7) return fail(SV_EINVAL, "SV_OPT_MIN_LOW_QUBITS takes 3..7");
+        s->min_low = (int)value;
+        return SV_OK;
+    case SV_OPT_MAX_DENSE:
+        if (value < 1 || value > (1 << 20)) return fail(SV_EINVAL, "SV_OPT_MAX_DENSE takes >= 1");
+        s->max_dense = (int)value;
+        return SV_OK;
+    case SV_OPT_ON_DEMAND_H:
+        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_ON_DEMAND_H takes 0 or 1");
+        s->gen_h = value != 0;
+        return SV_OK;
+    case SV_OPT_SMALL_PATH:
+        if (value != 1 && value != 2) return fail(SV_EINVAL, "SV_OPT_SMALL_PATH takes 1 or 2");
+        s->small_mode = (int)value;
+        return SV_OK;
+    case SV_OPT_PROFILE:
+        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_PROFILE takes 0 or 1");
+        s->profile = value != 0;
+        return SV_OK;
+    default:
+        return fail(SV_EINVAL, "unknown option %d", option);
+    }
+}
+
+sv_status sv_plan_stats(sv_state s, int64_t out[8]) {
+    if (!s || !out) return fail(SV_EINVAL, "null argument");
+    std::memcpy(out, s->stats, sizeof s->stats);
+    return SV_OK;
+}
+
+sv_status sv_profile_read(sv_state s, double *total_ms, int64_t *launches, double *bytes) {
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    double tot = 0.0, by = 0.0;
+    for (auto &t : s->timed) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+        by += t.bytes;
+        s->event_pool.push_back(t.a);
+        s->event_pool.push_back(t.b);
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)s->timed.size();
+    if (bytes) *bytes = by;
+    s->timed.clear();
+    return SV_OK;
+}
+
+sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, const double *params,
+                              size_t n_params, int qubit, double *expect, double *grad) {
+    (void)gates; (void)n_gates; (void)params; (void)n_params; (void)qubit; (void)expect; (void)grad;
+    sv_status st = check_handle(s);
+    if (st != SV_OK) return st;
+    return fail(SV_EUNSUPPORTED, "adjoint backward not built yet");
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics (include/sv_debug.h)
+
+int64_t sv_debug_plan(int n, int dtype, const sv_gate *gates, size_t n_gates, const double *params,
+                      size_t n_params, const int64_t *opts, void *out, size_t cap) {
+    if (n < 1 || n > 34 || (dtype != SV_C64 && dtype != SV_C128)) {
+        fail(SV_EINVAL, "bad n or dtype");
+        return SV_EINVAL;
+    }
+    std::string err;
+    if (!validate_gates(n, gates, n_gates, n_params, params != nullptr, err)) {
+        fail(SV_EINVAL, "%s", err.c_str());
+        return SV_EINVAL;
+    }
+    sv_state_s tmp;
+    tmp.n = n;
+    tmp.dt = (sv_dtype)dtype;
+    if (opts) {
+        tmp.fuse = opts[0] != 0;
+        tmp.min_low = (int)opts[1];
+        tmp.max_dense = (int)opts[2];
+        tmp.gen_h = opts[3] != 0;
+        tmp.basis_known = opts[4] != 0;
+        tmp.basis_j = (uint64_t)opts[5];
+        tmp.small_mode = (int)opts[6];
+    }
+    const PlanOptions po = plan_options(&tmp);
+    Plan p = build_plan(n, gates, n_gates, po);
+    const size_t real_bytes = 8;  // constants reported in FP64
+    const Layout L = plan_sections(p, 1, real_bytes);
+    const size_t header = 256;
+    const size_t total = header + L.total;
+    if (!out || cap < total) return (int64_t)total;
+    char *o = static_cast<char *>(out);
+    std::memset(o, 0, total);
+    int64_t *h = reinterpret_cast<int64_t *>(o);
+    int k = 0, w = 0;
+    tile_geometry(n, po, k, w);
+    h[0] = p.small;
+    h[1] = (int64_t)p.passes.size();
+    h[2] = (int64_t)p.layouts.size();
+    h[3] = (int64_t)p.ops.size();
+    h[4] = (int64_t)p.sops.size();
+    h[5] = (int64_t)p.cstride;
+    h[6] = p.n_exch;
+    h[7] = p.n_gen_h;
+    h[8] = p.gates_applied;
+    h[9] = k;
+    h[10] = w;
+    h[11] = po.R;
+    h[12] = po.m;
+    h[13] = (int64_t)(header + L.passes);
+    h[14] = (int64_t)(header + L.layouts);
+    h[15] = (int64_t)(header + L.ops);
+    h[16] = (int64_t)(header + L.sops);
+    h[17] = (int64_t)(header + L.consts);
+    h[18] = plan_hbm_bytes(p, n, dtype == SV_C128 ? 16 : 8);
+    serialize_plan(p, L, gates, params, n_params, 1, false, o + header);
+    return (int64_t)total;
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// Host-side launchers of the gfx950 kernels (defined in sv_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sv_plan.hpp"
+
+namespace sv {
+
+// Register bits per thread of the tiled pass kernel, per precision.
+// complex128: 16 amplitudes (64 VGPRs); complex64: 32 amplitudes (64 VGPRs).
+constexpr int kRegBitsC128 = 4;
+constexpr int kRegBitsC64 = 5;
+constexpr int kMaxThreadBits = 8;    // 256 threads per workgroup
+constexpr int kMinThreadBits = 6;    // at least one full 64-lane wave
+
+// Largest state (qubits) the one-workgroup kernel keeps in 64 KiB of LDS.
+constexpr int kSmallMaxQubitsC128 = 12;
+constexpr int kSmallMaxQubitsC64 = 13;
+
+// dt: 1 = complex64, 2 = complex128 (the sv_dtype values).
+hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch,
+                             uint64_t j, hipStream_t st);
+
+hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch,
+                       const DevPass *d_passes, int pass_idx, const DevPass &h_pass,
+                       const DevLayout *d_layouts, const DevOp *d_ops,
+                       const void *d_consts, uint64_t const_stride, hipStream_t st);
+
+hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_ops,
+                        int n_ops, const void *d_consts, uint64_t const_stride,
+                        hipStream_t st);
+
+// Per-state sum of |a_i|^2 * (qubit < 0 ? 1 : 1 - 2 b_qubit(i)) in FP64.
+// d_partials needs reduce_partials_size(n) * batch doubles; d_out batch doubles.
+size_t reduce_partials_size(int n);
+hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
+                         double *d_partials, double *d_out, hipStream_t st);
+
+// out[2i], out[2i+1] = FP64 (re, im) of amplitude idx[i] of the state at `state`.
+hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_t k,
+                         double *d_out, hipStream_t st);
+
+}  // namespace sv

@@ -1,0 +1,279 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU FP64 oracle.
+
+Tolerances per amplitude vs the FP64 oracle: complex128 <= 1e-12,
+complex64 <= 1e-5; readouts (<Z>, norm) the same.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-12, "c64": 1e-5}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_15332_amd as pkg
+    return pkg
+
+
+def run(P, n, gates, dtype="c128", psi0=None, params=None, batch=1, opts=None, basis=None):
+    with P.StateVector(n, dtype, batch) as sv:
+        for k, v in (opts or {}).items():
+            sv.set_option(k, v)
+        if psi0 is not None:
+            sv.load(psi0)
+        if basis is not None:
+            sv.set_basis(basis)
+        sv.apply(gates, params)
+        out = sv.numpy().astype(np.complex128)
+        stats = sv.plan_stats()
+    return (out[0] if batch == 1 else out), stats
+
+
+def maxdiff(a, b):
+    return float(np.max(np.abs(a - b)))
+
+
+def all_kinds_circuit(n, seed):
+    rng = np.random.default_rng(seed)
+    gates = []
+    for name in synth.GATE_NAMES:
+        for q in range(n):
+            ang = float(rng.uniform(0, 2 * math.pi))
+            if name in synth.TWO_QUBIT:
+                gates.append(synth.Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
+            elif name == "MARK":
+                gates.append(synth.Gate(name, -1, -1, 0.0, -1, int(rng.integers(1 << n))))
+            else:
+                gates.append(synth.Gate(name, q, -1, ang))
+    rng.shuffle(gates)
+    return gates
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 10, 12, 14, 17])
+def test_every_kind_every_position(P, n, dtype):
+    gates = all_kinds_circuit(n, n)
+    psi0 = synth.random_state(n, 100 + n)
+    ref = O.simulate(n, gates, psi0=psi0)
+    got, _ = run(P, n, gates, dtype, psi0=psi0)
+    assert maxdiff(got, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_plain_method_n12_depth20(P, seed):
+    gates = synth.random_circuit(12, 20, seed)
+    ref = O.simulate(12, gates)
+    got, _ = run(P, 12, gates, "c128")
+    assert maxdiff(got, ref) <= TOL["c128"]
+    got, _ = run(P, 12, gates, "c64")
+    assert maxdiff(got, ref) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,depth", [(11, 8), (13, 8), (15, 6), (16, 6), (18, 4), (20, 4), (22, 2)])
+def test_random_circuits_many_tiles(P, n, depth, dtype):
+    gates = synth.random_circuit(n, depth, 7 * n)
+    ref = O.simulate(n, gates)
+    got, st = run(P, n, gates, dtype)
+    assert maxdiff(got, ref) <= TOL[dtype]
+    assert st["gates"] == len(gates)
+
+
+@pytest.mark.parametrize("opts", [
+    {1: 0},            # unfused: one pass per gate
+    {2: 3}, {2: 4}, {2: 5}, {2: 7},   # lowest qubits kept in a tile
+    {3: 1}, {3: 3},    # dense gates per pass
+    {4: 0},            # no on-demand Hadamards
+])
+def test_plan_options_agree(P, opts):
+    n = 16
+    gates = synth.capacity_circuit(n, 4, 11)
+    ref = O.simulate(n, gates)
+    for dtype in ("c128", "c64"):
+        got, _ = run(P, n, gates, dtype, opts=opts)
+        assert maxdiff(got, ref) <= TOL[dtype]
+
+
+def test_fused_equals_unfused(P):
+    n = 15
+    gates = synth.random_circuit(n, 6, 3)
+    fused, sf = run(P, n, gates)
+    unfused, su = run(P, n, gates, opts={1: 0})
+    assert sf["passes"] < su["passes"]
+    assert maxdiff(fused, unfused) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [10, 12])
+def test_small_path_vs_tiled(P, n):
+    gates = synth.random_circuit(n, 10, n)
+    ref = O.simulate(n, gates)
+    tiled, _ = run(P, n, gates)
+    small, _ = run(P, n, gates, opts={5: 2})
+    assert maxdiff(tiled, ref) <= 1e-12 and maxdiff(small, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 7])
+def test_tiny_states(P, n):
+    gates = synth.random_circuit(n, 8, n)
+    ref = O.simulate(n, gates)
+    for dtype in ("c128", "c64"):
+        got, _ = run(P, n, gates, dtype)
+        assert maxdiff(got, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("j", [0, 12345])
+def test_on_demand_hadamard_layer(P, j):
+    n = 20
+    gates = [synth.Gate("H", q) for q in range(n)]
+    r = np.arange(1 << n)
+    par = np.array([bin(x).count("1") & 1 for x in (r & j)])
+    ref = 2.0 ** (-n / 2) * (1 - 2 * par)
+    got, st = run(P, n, gates, basis=j)
+    assert st["generated_h"] == n and st["passes"] == 1
+    assert maxdiff(got, ref) <= 1e-15
+    got, st = run(P, n, gates, basis=j, opts={4: 0})
+    assert st["generated_h"] == 0
+    assert maxdiff(got, ref) <= 1e-14
+
+
+def test_generation_then_gates(P):
+    n = 18
+    gates = [synth.Gate("H", q) for q in range(0, n, 2)] + synth.random_circuit(n, 3, 5)
+    ref = O.simulate(n, gates, psi0=O.basis_state(n, 77))
+    got, st = run(P, n, gates, basis=77)
+    assert st["generated_h"] == n // 2
+    assert maxdiff(got, ref) <= 1e-12
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return {ln.split()[0]: float(ln.split()[1]) for ln in f if ln.strip() and not ln.startswith("#")}
+
+
+def test_grover_n12_closed_form(P):
+    n = 12
+    m = synth.grover_marked(n, 3)
+    k = synth.grover_iterations(n)
+    got, _ = run(P, n, synth.grover_circuit(n, m))
+    a, b, p = O.grover_closed_form(n, k)
+    sgn = (-1) ** k
+    assert abs(got[m] - sgn * a) <= 1e-12
+    assert np.max(np.abs(np.delete(got, m) - sgn * b)) <= 1e-12
+
+
+def test_grover_n20_804_iterations(P):
+    n = 20
+    g = _golden("grover_n20.txt")
+    k = int(g["iterations"])
+    m = synth.grover_marked(n, 0)
+    gates = synth.grover_circuit(n, m, k)
+    with P.StateVector(n, "c128") as sv:
+        sv.apply(gates)
+        amp = sv.amplitudes([m, (m + 1) % (1 << n), 0])
+        nrm = sv.norm()[0]
+    sgn = (-1) ** k
+    assert abs(amp[0] - sgn * g["marked"]) <= 1e-10
+    assert abs(abs(amp[0]) ** 2 - g["p_success"]) <= 1e-10
+    assert abs(amp[1] - sgn * g["unmarked"]) <= 1e-12
+    assert abs(nrm - 1.0) <= 1e-12
+
+
+def test_ghz_n24(P):
+    n = 24
+    gates = [synth.Gate("H", 0)] + [synth.Gate("CNOT", q, q + 1) for q in range(n - 1)]
+    with P.StateVector(n, "c128") as sv:
+        sv.apply(gates)
+        amp = sv.amplitudes([0, (1 << n) - 1, 1, 12345])
+        nrm = sv.norm()[0]
+        z = sv.expect_z(n - 1)[0]
+    r = 1 / math.sqrt(2)
+    assert np.max(np.abs(amp - [r, r, 0, 0])) <= 1e-15
+    assert abs(nrm - 1) <= 1e-14 and abs(z) <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_readouts(P, dtype):
+    n = 16
+    gates = synth.random_circuit(n, 5, 21)
+    ref = O.simulate(n, gates)
+    idx = np.random.default_rng(0).integers(0, 1 << n, size=300)
+    with P.StateVector(n, dtype) as sv:
+        sv.apply(gates)
+        zs = [sv.expect_z(q)[0] for q in range(n)]
+        z_again = sv.expect_z(3)[0]
+        nrm = sv.norm()[0]
+        amp = sv.amplitudes(idx)
+    for q in range(n):
+        assert abs(zs[q] - O.expect_z(ref, q)) <= TOL[dtype]
+    assert z_again == zs[3]                     # fixed reduction order
+    assert abs(nrm - O.norm2(ref)) <= TOL[dtype]
+    assert np.max(np.abs(amp - ref[idx])) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [12, 14])
+def test_batched_parameters(P, n, dtype):
+    L, B = 3, 4
+    gates = synth.qnn_ansatz(n, L)
+    params = synth.qnn_params(n, L, B, 5)
+    got, _ = run(P, n, gates, dtype, params=params, batch=B)
+    with P.StateVector(n, dtype, B) as sv:
+        sv.apply(gates, params)
+        z = sv.expect_z(0)
+    for b in range(B):
+        ref = O.simulate(n, gates, params[b])
+        assert maxdiff(got[b], ref) <= TOL[dtype]
+        assert abs(z[b] - O.expect_z(ref, 0)) <= TOL[dtype]
+
+
+def test_empty_identity_and_errors(P):
+    n = 14
+    with P.StateVector(n, "c128") as sv:
+        sv.apply([])
+        sv.apply([synth.Gate("I", 3)])
+        assert sv.amplitudes([0])[0] == 1.0
+        sv.apply(synth.random_circuit(n, 2, 1))
+        before = sv.numpy().copy()
+        for bad in ([synth.Gate("X", n)], [synth.Gate("CNOT", 1, 1)],
+                    [synth.Gate("MARK", -1, -1, 0.0, -1, 1 << n)]):
+            with pytest.raises(P.SVError):
+                sv.apply(synth.random_circuit(n, 1, 2) + bad)
+        with pytest.raises(P.SVError):
+            sv.expect_z(n)
+        with pytest.raises(P.SVError):
+            sv.amplitudes([1 << n])
+        assert np.array_equal(sv.numpy(), before)
+
+
+def test_plain_method_at_scale_n28(P):
+    """The n = 28, depth-100 workload in the benchmark's launch configuration:
+    norm after the circuit, the mirror circuit C^dagger C returning |0...0>, and
+    the first layer against the oracle on sampled amplitudes."""
+    n = 28
+    gates = synth.random_circuit(n, 100, 0)
+    with P.StateVector(n, "c128") as sv:
+        sv.apply(gates)
+        nrm = sv.norm()[0]
+        sv.apply(synth.inverse_circuit(gates))
+        back = sv.amplitudes([0, 1, 12345, (1 << n) - 1])
+        nrm2 = sv.norm()[0]
+    assert abs(nrm - 1) <= 1e-12 and abs(nrm2 - 1) <= 1e-12
+    assert abs(back[0] - 1) <= 1e-10 and np.max(np.abs(back[1:])) <= 1e-10
+    layer = synth.random_circuit(n, 1, 0)
+    ref = O.simulate(n, layer)
+    idx = np.random.default_rng(1).integers(0, 1 << n, size=4096)
+    with P.StateVector(n, "c128") as sv:
+        sv.apply(layer)
+        amp = sv.amplitudes(idx)
+    assert np.max(np.abs(amp - ref[idx])) <= 1e-12

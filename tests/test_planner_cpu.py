@@ -1,0 +1,152 @@
+"""Host planner checks on the CPU (no GPU): the C ABI library loads and exports
+every declared symbol, argument validation, and the pass plans — executed by a
+slow numpy emulation of the documented op semantics — reproduce the oracle."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+P = pytest.importorskip("paper_2411_15332_amd")
+from plan_emulator import run_plan  # noqa: E402
+
+
+def _declared_symbols():
+    names = []
+    for h in ("sv.h", "sv_debug.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        names += re.findall(r"^\S[^\n(]*?\b(sv_[a-z_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(P.sv.LIB_PATH)
+    names = _declared_symbols()
+    assert "sv_alloc" in names and "sv_apply_circuit" in names and "sv_debug_plan" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_gate_record_layout():
+    assert P.sv.GATE_DTYPE.itemsize == 32
+    kinds = P.GATE_KIND
+    assert set(kinds) == set(synth.GATE_NAMES)
+    src = open(os.path.join(ROOT, "include", "sv.h")).read()
+    for name, code in kinds.items():
+        assert re.search(rf"SV_GATE_{name} = {code}\b", src), name
+
+
+@pytest.mark.parametrize("bad", [
+    [synth.Gate("X", 12)],
+    [synth.Gate("CNOT", 3, 3)],
+    [synth.Gate("CZ", 0, -1)],
+    [synth.Gate("MARK", -1, -1, 0.0, -1, 1 << 12)],
+    [synth.Gate("RY", 0, -1, 0.0, 5)],
+    [synth.Gate("H", 0, -1, 0.0, 0)],
+])
+def test_validation_rejects(bad):
+    with pytest.raises(P.SVError) as e:
+        P.debug_plan(12, bad)
+    assert e.value.status == -1
+    assert P.last_error()
+
+
+def _emulate(n, gates, dtype="c128", psi0=None, basis=0, **kw):
+    plan = P.debug_plan(n, gates, dtype=dtype, basis=basis if psi0 is None else None, **kw)
+    psi = O.basis_state(n, basis) if psi0 is None else psi0.copy()
+    return run_plan(plan, psi, n), plan
+
+
+CASES = [(10, 3, 0), (11, 4, 1), (12, 4, 2), (13, 3, 3), (14, 2, 4)]
+
+
+@pytest.mark.parametrize("n,depth,seed", CASES)
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_plan_emulation_random_circuits(n, depth, seed, dtype):
+    gates = synth.random_circuit(n, depth, seed)
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates, dtype)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    if not plan["small"]:
+        assert plan["gates"] == len([g for g in gates if g.name != "I"])
+
+
+@pytest.mark.parametrize("opts", [dict(fuse=False), dict(min_low=3), dict(min_low=7),
+                                  dict(max_dense=1), dict(gen_h=False)])
+def test_plan_options(opts):
+    n = 12
+    gates = synth.capacity_circuit(n, 3, 5)
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates, **opts)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_every_gate_kind_every_position():
+    n = 11
+    rng = np.random.default_rng(0)
+    gates = []
+    for name in synth.GATE_NAMES:
+        for q in range(n):
+            ang = float(rng.uniform(0, 2 * math.pi))
+            if name in synth.TWO_QUBIT:
+                gates.append(synth.Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
+            elif name == "MARK":
+                gates.append(synth.Gate(name, -1, -1, 0.0, -1, int(rng.integers(1 << n))))
+            else:
+                gates.append(synth.Gate(name, q, -1, ang))
+    rng.shuffle(gates)
+    psi0 = synth.random_state(n, 9)
+    ref = O.simulate(n, gates, psi0=psi0)
+    for dt in ("c128", "c64"):
+        got, _ = _emulate(n, gates, dt, psi0=psi0)
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("j", [0, 5, 1023])
+def test_generation_prologue(j):
+    n = 12
+    gates = [synth.Gate("H", q) for q in (3, 0, 7, 11, 5)] + synth.random_circuit(n, 2, 1)
+    ref = O.simulate(n, gates, psi0=O.basis_state(n, j))
+    got, plan = _emulate(n, gates, basis=j)
+    assert plan["generated_h"] == 5
+    assert np.max(np.abs(got - ref)) < 1e-12
+    only_h = [synth.Gate("H", q) for q in range(n)]
+    got, plan = _emulate(n, only_h, basis=j)
+    assert plan["generated_h"] == n and len(plan["passes"]) == 1
+    ref = O.simulate(n, only_h, psi0=O.basis_state(n, j))
+    assert np.max(np.abs(got - ref)) < 1e-15
+
+
+def test_grover_plan():
+    n = 12
+    m = synth.grover_marked(n, 1)
+    gates = synth.grover_circuit(n, m, iterations=3)
+    ref = O.simulate(n, gates)
+    got, _ = _emulate(n, gates)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+def test_small_path_plans(n):
+    gates = synth.random_circuit(n, 6, n)
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates)
+    assert plan["small"]
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_large_plan_statistics():
+    gates = synth.random_circuit(28, 100, 0)
+    plan = P.debug_plan(28, gates)
+    npass = len(plan["passes"])
+    assert plan["gates"] == len(gates)
+    assert plan["hbm_bytes"] == npass * 2 * (1 << 28) * 16 - (1 << 28) * 16 * 0
+    # every gate of a pass lies on its tile qubits or is diagonal
+    assert 30 < npass < 200
+    assert plan["k"] == 12 and plan["w"] == 8
