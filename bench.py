@@ -1,0 +1,177 @@
+"""Benchmark: amplitude-gate updates/s of the fused gate-application path.
+
+Workload (one step): the seeded random circuit n = 28, complex128, depth 100
+(3523 gates, seed 0) applied in place to |0...0> on one GPU — state reset,
+every gate, then the readouts <Z_0> and the norm (FP64). Inputs are resident in
+HBM when the timed region starts.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(k_pass: algorithmic bytes per launch / average launch duration from HIP events
+on the handle's stream during the timed region; HBM traffic from the committed
+rocprofv3 counter summary when it matches the current kernel source), and the
+CPU FP64 oracle timed on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "amplitude-gate updates/s + % HBM peak; QNN circuits/s with p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2411_15332_amd", "csrc", "sv_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_c128_n28_traffic.json")
+
+
+def kernel_src_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per k_pass launch from the committed counter summary, or None
+    when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha") != kernel_src_hash():
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(n, gates, target_s=12.0):
+    """The oracle (as it stands) on the first gates of the same circuit, on all
+    host threads; amplitude-gate updates/s scaled from the sample."""
+    import numpy as np
+    from oracle import oracle as O
+    threads = O.max_threads()
+    psi = O.basis_state(n)
+    t0 = time.perf_counter()
+    O.apply(psi, n, gates[:1])
+    first = time.perf_counter() - t0
+    count = max(1, min(len(gates) - 1, int(target_s / max(first, 1e-3))))
+    t0 = time.perf_counter()
+    O.apply(psi, n, gates[1:1 + count])
+    dt = time.perf_counter() - t0
+    del psi
+    _ = np
+    return {"value": count * (1 << n) / dt, "unit": "amplitude-gate updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"gates 2..{count + 1} of the n={n} depth-100 circuit from |0...0>, "
+                      f"{dt:.1f} s on {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=28)
+    ap.add_argument("--depth", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain device copy of the state's size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build runs the "
+              "gate path on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2411_15332_amd as P
+
+    torch.cuda.set_device(0)
+    n = args.n
+    gates = synth.random_circuit(n, args.depth, args.seed)
+    arr = P.gate_array(gates)
+    work = len(gates) * (1 << n)
+
+    sv = P.StateVector(n, "c128")
+
+    def step():
+        sv.set_basis(0)
+        sv.apply(arr)
+        z = sv.expect_z(0)[0]
+        nrm = sv.norm()[0]
+        return z, nrm
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.set_option(P.sv.OPT_PROFILE, 1)
+    sv.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z, nrm = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k_ms, k_launches, k_bytes = sv.profile_read()
+    sv.set_option(P.sv.OPT_PROFILE, 0)
+    stats = sv.plan_stats()
+    if abs(nrm - 1.0) > 1e-10:
+        raise SystemExit(f"norm drifted: {nrm}")
+
+    if args.calib_copy:
+        src = torch.empty((1 << n,), dtype=torch.complex128, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sv.close()
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = work / ((t1 - t0) / args.steps)
+    avg_ms = k_ms / max(k_launches, 1)
+    bytes_per_launch = k_bytes / max(k_launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tr = traffic_per_launch()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "amplitude-gate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"seeded random circuit, n={n} complex128 ({(1 << n) * 16 // 2**30} GiB state), "
+                        f"depth {args.depth}, seed {args.seed}, {len(gates)} gates, from |0...0>, "
+                        f"then <Z_0> and norm",
+            "n_qubits": n, "depth": args.depth, "gates": len(gates), "seed": args.seed,
+            "passes": stats["passes"], "lds_exchanges": stats["exchanges"],
+        },
+        "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_pass<double>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": tr, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_ms, "launches": k_launches,
+        },
+        "checks": {"expect_z0": z, "norm": nrm},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, gates)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

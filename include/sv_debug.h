@@ -24,7 +24,7 @@ extern "C" {
  *   [5] constant reals per batch entry, [6] exchanges, [7] generated
  *   Hadamards, [8] gates applied, [9] k, [10] w, [11] R, [12] swizzle width,
  *   [13..17] byte offsets of the pass, layout, op, small-op and constant
- *   arrays, [18] algorithmic HBM bytes,
+ *   arrays, [18] algorithmic HBM bytes, [19] relabelled permutation gates,
  * followed by those arrays (constants in FP64, batch entry 0).
  * Returns the number of bytes the dump needs (nothing is written when `out`
  * is NULL or `cap` is smaller), or a negative sv_status on bad input. */

@@ -24,6 +24,9 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
+    # keep uniform (scalar-branch) regions unstructurized: the pass kernel's
+    # op dispatch then merges the register tile without whole-tile copies
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     f"-I{os.path.join(HERE, '..', 'include')}",
 ]
 

@@ -172,7 +172,7 @@ Layout plan_sections(const Plan &p, int batch, size_t real_bytes) {
     L.layouts = o;
     o = align_up(o + p.layouts.size() * sizeof(DevLayout), 256);
     L.ops = o;
-    o = align_up(o + p.ops.size() * sizeof(DevOp), 256);
+    o = align_up(o + (size_t)batch * p.ops.size() * sizeof(DevOp), 256);
     L.sops = o;
     o = align_up(o + p.sops.size() * sizeof(SmallOp), 256);
     L.consts = o;
@@ -186,7 +186,7 @@ void serialize_plan(const Plan &p, const Layout &L, const sv_gate *gates, const 
     if (!p.passes.empty()) std::memcpy(dst + L.passes, p.passes.data(), p.passes.size() * sizeof(DevPass));
     if (!p.layouts.empty())
         std::memcpy(dst + L.layouts, p.layouts.data(), p.layouts.size() * sizeof(DevLayout));
-    if (!p.ops.empty()) std::memcpy(dst + L.ops, p.ops.data(), p.ops.size() * sizeof(DevOp));
+    if (!p.ops.empty()) materialize_ops(p, gates, params, n_params, batch, f32, dst + L.ops);
     if (!p.sops.empty()) std::memcpy(dst + L.sops, p.sops.data(), p.sops.size() * sizeof(SmallOp));
     if (p.cstride) materialize_consts(p, gates, params, n_params, batch, f32, dst + L.consts);
 }
@@ -255,7 +255,7 @@ sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gat
         }
         SV_HIP(launch_pass((int)s->dt, state, N, s->batch, dpass, (int)i, p.passes[i],
                            reinterpret_cast<const DevLayout *>(d + L.layouts),
-                           reinterpret_cast<const DevOp *>(d + L.ops), d + L.consts, p.cstride,
+                           reinterpret_cast<const DevOp *>(d + L.ops), (uint64_t)p.ops.size(),
                            s->stream),
                "launch k_pass");
         if (s->profile && ea && eb) {
@@ -404,6 +404,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
     s->stats[3] = p.n_gen_h;
     s->stats[4] = p.small ? (p.sops.empty() ? 0 : 1) : (int64_t)p.passes.size();
     s->stats[5] = plan_hbm_bytes(p, s->n, s->amp_bytes);
+    s->stats[6] = p.n_relabel;
     if (p.gates_applied > 0) s->basis_known = false;
     return SV_OK;
 }
@@ -605,6 +606,7 @@ int64_t sv_debug_plan(int n, int dtype, const sv_gate *gates, size_t n_gates, co
     h[16] = (int64_t)(header + L.sops);
     h[17] = (int64_t)(header + L.consts);
     h[18] = plan_hbm_bytes(p, n, dtype == SV_C128 ? 16 : 8);
+    h[19] = p.n_relabel;
     serialize_plan(p, L, gates, params, n_params, 1, false, o + header);
     return (int64_t)total;
 }

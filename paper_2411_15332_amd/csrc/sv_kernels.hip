@@ -19,7 +19,6 @@
 
 #include "sv_kernels.hpp"
 #include "sv_plan.hpp"
-#include "sv_swizzle.hpp"
 
 namespace sv {
 
@@ -62,28 +61,51 @@ __device__ __forceinline__ cpx<T> ldc(const T *p) {
 // Register-tile operations. P, PA, PB are register-bit positions (compile
 // time); every loop is fully unrolled so the tile never leaves VGPRs.
 
+// In-place forms: every new value is computed so that it can take the
+// register of the old value it replaces (no temporaries live across the
+// update), which keeps the register tile in fixed VGPRs across the
+// interpreter's dispatch merge.
+
+// a *= d, with one temporary product
+template <typename T>
+__device__ __forceinline__ void cmul_ip(cpx<T> &a, cpx<T> d) {
+    const T t = a.x * d.y;
+    const T u = a.y * d.y;
+    a.x = __builtin_fma(a.x, d.x, -u);
+    a.y = __builtin_fma(a.y, d.x, t);
+}
+
+// Hadamard butterfly (x0 + x1, x0 - x1) as x0 <- x0 + x1, x1 <- x0' - 2 x1
 template <int P, typename T, int NR>
 __device__ __forceinline__ void r_h(cpx<T> (&a)[NR]) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << P)) continue;
         const int j1 = j | (1 << P);
-        const cpx<T> x0 = a[j], x1 = a[j1];
-        a[j] = cadd(x0, x1);
-        a[j1] = csub(x0, x1);
+        a[j].x = a[j].x + a[j1].x;
+        a[j1].x = __builtin_fma((T)-2, a[j1].x, a[j].x);
+        a[j].y = a[j].y + a[j1].y;
+        a[j1].y = __builtin_fma((T)-2, a[j1].y, a[j].y);
     }
 }
 
 template <int P, typename T, int NR>
-__device__ __forceinline__ void r_dense1(cpx<T> (&a)[NR], const T *m) {
-    const cpx<T> g00 = ldc(m), g01 = ldc(m + 2), g10 = ldc(m + 4), g11 = ldc(m + 6);
+__device__ __forceinline__ void r_dense1(cpx<T> (&a)[NR], cpx<T> g00, cpx<T> g01, cpx<T> g10,
+                                         cpx<T> g11) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << P)) continue;
         const int j1 = j | (1 << P);
-        const cpx<T> x0 = a[j], x1 = a[j1];
-        a[j] = cmul2(g00, x0, g01, x1);
-        a[j1] = cmul2(g10, x0, g11, x1);
+        const cpx<T> x0 = a[j];
+        // x1 <- g10 x0 + g11 x1 (last use of x1 is here), then x0 from the copy
+        const T nx1 = g10.x * x0.x - g10.y * x0.y + g11.x * a[j1].x - g11.y * a[j1].y;
+        const T ny1 = g10.x * x0.y + g10.y * x0.x + g11.x * a[j1].y + g11.y * a[j1].x;
+        const T nx0 = g00.x * x0.x - g00.y * x0.y + g01.x * a[j1].x - g01.y * a[j1].y;
+        const T ny0 = g00.x * x0.y + g00.y * x0.x + g01.x * a[j1].y + g01.y * a[j1].x;
+        a[j1].x = nx1;
+        a[j1].y = ny1;
+        a[j].x = nx0;
+        a[j].y = ny0;
     }
 }
 
@@ -99,20 +121,7 @@ __device__ __forceinline__ void r_x(cpx<T> (&a)[NR]) {
     }
 }
 
-// Y: (x0, x1) -> (-i x1, i x0)
-template <int P, typename T, int NR>
-__device__ __forceinline__ void r_y(cpx<T> (&a)[NR]) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if (j & (1 << P)) continue;
-        const int j1 = j | (1 << P);
-        const cpx<T> x0 = a[j], x1 = a[j1];
-        a[j] = mk<T>(x1.y, -x1.x);
-        a[j1] = mk<T>(-x0.y, x0.x);
-    }
-}
-
-// Controlled swap on bit P, control = register bit PC.
+// Swap the pairs of bit P in the slots whose bit PC is set.
 template <int P, int PC, typename T, int NR>
 __device__ __forceinline__ void r_cx_reg(cpx<T> (&a)[NR]) {
 #pragma unroll
@@ -126,93 +135,38 @@ __device__ __forceinline__ void r_cx_reg(cpx<T> (&a)[NR]) {
     }
 }
 
-// Controlled swap on bit P with a control bit that is the same for every
-// register slot of this thread (selects, no divergent branch).
+// Swap the pairs of bit P when c (the same for every slot of this thread):
+// per-component selects, no branch.
 template <int P, typename T, int NR>
 __device__ __forceinline__ void r_cx_uni(cpx<T> (&a)[NR], bool c) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << P)) continue;
         const int j1 = j | (1 << P);
-        const cpx<T> x0 = a[j], x1 = a[j1];
-        a[j] = c ? x1 : x0;
-        a[j1] = c ? x0 : x1;
+        const T x0 = a[j].x, y0 = a[j].y, x1 = a[j1].x, y1 = a[j1].y;
+        a[j].x = c ? x1 : x0;
+        a[j].y = c ? y1 : y0;
+        a[j1].x = c ? x0 : x1;
+        a[j1].y = c ? y0 : y1;
     }
 }
 
-// SWAP of register bits PA > PB: exchange slots with (bA, bB) = (1, 0) and (0, 1).
-template <int PA, int PB, typename T, int NR>
-__device__ __forceinline__ void r_swap(cpx<T> (&a)[NR]) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if (!(j & (1 << PA)) || (j & (1 << PB))) continue;
-        const int j2 = (j & ~(1 << PA)) | (1 << PB);
-        const cpx<T> t = a[j];
-        a[j] = a[j2];
-        a[j2] = t;
-    }
-}
-
-// 4x4 on register bits PA (high local bit) > PB (low local bit).
-template <int PA, int PB, typename T, int NR>
-__device__ __forceinline__ void r_dense2(cpx<T> (&a)[NR], const T *m) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if (j & ((1 << PA) | (1 << PB))) continue;
-        const int jj[4] = {j, j | (1 << PB), j | (1 << PA), j | (1 << PA) | (1 << PB)};
-        cpx<T> x[4];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) x[l] = a[jj[l]];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const T *row = m + 8 * r;
-            cpx<T> acc = cmul2(ldc(row), x[0], ldc(row + 2), x[1]);
-            acc = cadd(acc, cmul2(ldc(row + 4), x[2], ldc(row + 6), x[3]));
-            a[jj[r]] = acc;
-        }
-    }
-}
-
-// 1-qubit diagonal with the qubit on register bit P.
 template <int P, typename T, int NR>
-__device__ __forceinline__ void r_d1_reg(cpx<T> (&a)[NR], const T *d) {
-    const cpx<T> d0 = ldc(d), d1 = ldc(d + 2);
+__device__ __forceinline__ void r_d1_reg(cpx<T> (&a)[NR], cpx<T> d0, cpx<T> d1) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) a[j] = cmul(a[j], (j & (1 << P)) ? d1 : d0);
+    for (int j = 0; j < NR; ++j) cmul_ip(a[j], (j & (1 << P)) ? d1 : d0);
 }
 
-// 2-qubit diagonal, both qubits on register bits (PA = q0's bit, PB = q1's).
 template <int PA, int PB, typename T, int NR>
-__device__ __forceinline__ void r_d2_regreg(cpx<T> (&a)[NR], const T *d) {
-    cpx<T> dd[4];
+__device__ __forceinline__ void r_d2_regreg(cpx<T> (&a)[NR], const cpx<T> (&d)[4]) {
 #pragma unroll
-    for (int l = 0; l < 4; ++l) dd[l] = ldc(d + 2 * l);
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        const int l = (((j >> PA) & 1) << 1) | ((j >> PB) & 1);
-        a[j] = cmul(a[j], dd[l]);
-    }
-}
-
-// 2-qubit diagonal: q0 on register bit PA, q1's bit known per thread (ub).
-template <int PA, typename T, int NR>
-__device__ __forceinline__ void r_d2_reg_hi(cpx<T> (&a)[NR], const T *d, int ub) {
-    const cpx<T> e0 = ldc(d + 2 * (0 + ub)), e1 = ldc(d + 2 * (2 + ub));
-#pragma unroll
-    for (int j = 0; j < NR; ++j) a[j] = cmul(a[j], (j & (1 << PA)) ? e1 : e0);
-}
-// 2-qubit diagonal: q1 on register bit PB, q0's bit known per thread (ub).
-template <int PB, typename T, int NR>
-__device__ __forceinline__ void r_d2_reg_lo(cpx<T> (&a)[NR], const T *d, int ub) {
-    const cpx<T> e0 = ldc(d + 2 * (2 * ub + 0)), e1 = ldc(d + 2 * (2 * ub + 1));
-#pragma unroll
-    for (int j = 0; j < NR; ++j) a[j] = cmul(a[j], (j & (1 << PB)) ? e1 : e0);
+    for (int j = 0; j < NR; ++j) cmul_ip(a[j], d[(((j >> PA) & 1) << 1) | ((j >> PB) & 1)]);
 }
 
 template <typename T, int NR>
 __device__ __forceinline__ void r_mul_all(cpx<T> (&a)[NR], cpx<T> d) {
 #pragma unroll
-    for (int j = 0; j < NR; ++j) a[j] = cmul(a[j], d);
+    for (int j = 0; j < NR; ++j) cmul_ip(a[j], d);
 }
 
 template <typename T, int NR>
@@ -249,48 +203,21 @@ __device__ __forceinline__ void r_scale(cpx<T> (&a)[NR], T s) {
         SV_CASE_B(4, __VA_ARGS__) SV_CASE_B(5, __VA_ARGS__) default : break;   \
     }
 
-// Per-layout index tables of one thread.
-template <int NR>
-struct LayoutIdx {
-    uint64_t gthr;        // global index bits contributed by the thread bits
-    uint64_t greg[NR];    // ... by the register slot bits
-    uint32_t sthr;        // swizzled LDS slot, thread part
-    uint32_t sreg[NR];    // ... register part
-};
-
-template <int R, int M>
-__device__ __forceinline__ void make_layout(LayoutIdx<1 << R> &L, const DevLayout &dl,
-                                            const uint8_t *q, int w, int tid) {
-    constexpr int NR = 1 << R;
-    uint64_t g = 0;
-    uint32_t l = 0;
-    for (int s = 0; s < w; ++s) {
-        if ((tid >> s) & 1) {
-            const int lb = dl.thr_local[s];
-            l |= 1u << lb;
-            g |= 1ull << q[lb];
-        }
-    }
-    L.gthr = g;
-    L.sthr = l ^ swz_fold(l, M);
-    uint64_t gb[R];
-    uint32_t lbit[R];
-#pragma unroll
-    for (int p = 0; p < R; ++p) {
-        lbit[p] = 1u << dl.reg_local[p];
-        gb[p] = 1ull << q[dl.reg_local[p]];
-    }
-    L.greg[0] = 0;
-    uint32_t lr[NR];
-    lr[0] = 0;
-#pragma unroll
-    for (int j = 1; j < NR; ++j) {
-        const int p = __builtin_ctz(j);
-        L.greg[j] = L.greg[j & (j - 1)] | gb[p];
-        lr[j] = lr[j & (j - 1)] | lbit[p];
-    }
-#pragma unroll
-    for (int j = 0; j < NR; ++j) L.sreg[j] = lr[j] ^ swz_fold(lr[j], M);
+// Payload element i of an operation, as T (i is a compile-time constant at
+// every call site, so the record stays in scalar registers).
+template <typename T>
+__device__ __forceinline__ T pl(const DevOp &op, int i);
+template <>
+__device__ __forceinline__ double pl<double>(const DevOp &op, int i) {
+    return __builtin_bit_cast(double, op.payload[i]);
+}
+template <>
+__device__ __forceinline__ float pl<float>(const DevOp &op, int i) {
+    return __builtin_bit_cast(float, (uint32_t)(op.payload[i >> 1] >> (32 * (i & 1))));
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> plc(const DevOp &op, int e) {
+    return mk<T>(pl<T>(op, 2 * e), pl<T>(op, 2 * e + 1));
 }
 
 template <typename T>
@@ -298,184 +225,241 @@ struct PassTraits;
 template <>
 struct PassTraits<double> {
     static constexpr int R = kRegBitsC128;
-    static constexpr int M = 3;
 };
 template <>
 struct PassTraits<float> {
     static constexpr int R = kRegBitsC64;
-    static constexpr int M = 4;
 };
+
+// Thread part of a layout: global-index bits and byte address of the LDS slot.
+__device__ __forceinline__ void thr_part(const DevLayout &L, int w, int tid, int slot_shift,
+                                         uint64_t &g, uint32_t &s) {
+    g = L.goff_xor;
+    uint32_t sl = L.slot_xor;
+    for (int b = 0; b < w; ++b) {
+        const bool on = (tid >> b) & 1;
+        g ^= on ? L.thr_goff[b] : 0ull;
+        sl ^= on ? L.thr_slot[b] : 0u;
+    }
+    s = sl << slot_shift;
+}
+
+// Register part: one value per slot j, XOR of the per-bit entries of j.
+template <int R>
+__device__ __forceinline__ void reg_goff(const DevLayout &L, uint64_t (&g)[1 << R]) {
+    g[0] = L.reg_goff_xor;
+#pragma unroll
+    for (int j = 1; j < (1 << R); ++j) g[j] = g[j & (j - 1)] ^ L.reg_goff[__builtin_ctz(j)];
+}
+template <int R>
+__device__ __forceinline__ void reg_slot(const DevLayout &L, int slot_shift, uint32_t (&s)[1 << R]) {
+    s[0] = 0;
+#pragma unroll
+    for (int j = 1; j < (1 << R); ++j) s[j] = s[j & (j - 1)] ^ (L.reg_slot[__builtin_ctz(j)] << slot_shift);
+}
+
+__device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
+    const int pos = src & SRC_POS_MASK;
+    return (src & ~SRC_POS_MASK) == SRC_THR ? (tid >> pos) & 1 : (int)((base >> pos) & 1);
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
                                               const DevPass *__restrict__ passes, int pass_idx,
                                               const DevLayout *__restrict__ layouts,
-                                              const DevOp *__restrict__ ops,
-                                              const T *__restrict__ consts,
-                                              uint64_t const_stride) {
+                                              const DevOp *__restrict__ ops, uint64_t ops_stride) {
     constexpr int R = PassTraits<T>::R;
-    constexpr int M = PassTraits<T>::M;
     constexpr int NR = 1 << R;
+    constexpr int SH = sizeof(T) == 8 ? 4 : 3;   // log2 of the slot size in bytes
     __shared__ cpx<T> lds[NR << kMaxThreadBits];
+    char *const ldsb = reinterpret_cast<char *>(lds);
 
     const DevPass &P = passes[pass_idx];
     const int tid = threadIdx.x;
     const int w = P.w;
     const int k = P.k;
-    uint8_t q[32];
-#pragma unroll
-    for (int l = 0; l < 32; ++l) q[l] = P.q[l];
-
+    const DevLayout *LB = layouts + P.layout_begin;
     cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
-    const T *cst = consts + (uint64_t)blockIdx.y * const_stride;
+    const DevOp *opb = ops + (uint64_t)blockIdx.y * ops_stride;
 
     // Global index of the tile's amplitude with all tile-local bits zero:
     // the tile number with zeros inserted at the tile qubits (ascending).
     uint64_t base = blockIdx.x;
     for (int l = 0; l < k; ++l) {
-        const int b = q[l];
+        const int b = P.q[l];
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
 
-    LayoutIdx<NR> L;
-    int cur = P.layout_begin;
-    make_layout<R, M>(L, layouts[cur], q, w, tid);
-
     cpx<T> a[NR];
-    const bool pair_io = (sizeof(T) == 4) && layouts[cur].reg_local[0] == 0 && q[0] == 0;
-    if (P.flags & PASS_GENERATE) {
-        // On-demand Hadamard-layer amplitudes of H^M |j>:
-        // 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M.
-        const uint64_t gm = P.gen_mask, gj = P.gen_j;
-        const T mag = (T)P.gen_scale;
+    {
+        const DevLayout &L = LB[0];
+        uint64_t gthr;
+        uint32_t sdummy;
+        thr_part(L, w, tid, SH, gthr, sdummy);
+        uint64_t greg[NR];
+        reg_goff<R>(L, greg);
+        const cpx<T> *tp = st + (base | gthr);
+        if (P.flags & PASS_GENERATE) {
+            // On-demand Hadamard-layer amplitudes of H^M |j>:
+            // 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M.
+            const uint64_t gm = P.gen_mask, gj = P.gen_j;
+            const T mag = (T)P.gen_scale;
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const uint64_t i = base | L.gthr | L.greg[j];
-            const bool on = ((i ^ gj) & ~gm) == 0;
-            const T v = (__popcll(i & gj & gm) & 1) ? -mag : mag;
-            a[j] = mk<T>(on ? v : (T)0, (T)0);
+            for (int j = 0; j < NR; ++j) {
+                const uint64_t i = base | gthr | greg[j];
+                const bool on = ((i ^ gj) & ~gm) == 0;
+                const T v = (__popcll(i & gj & gm) & 1) ? -mag : mag;
+                a[j] = mk<T>(on ? v : (T)0, (T)0);
+            }
+        } else if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
+#pragma unroll
+            for (int j = 0; j < NR; j += 2) {
+                const float4 v = *reinterpret_cast<const float4 *>(tp + greg[j]);
+                a[j] = mk<T>((T)v.x, (T)v.y);
+                a[j + 1] = mk<T>((T)v.z, (T)v.w);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) a[j] = tp[greg[j]];
         }
-    } else if (pair_io) {
-#pragma unroll
-        for (int j = 0; j < NR; j += 2) {
-            const float4 v = *reinterpret_cast<const float4 *>(st + (base | L.gthr | L.greg[j]));
-            a[j] = mk<T>((T)v.x, (T)v.y);
-            a[j + 1] = mk<T>((T)v.z, (T)v.w);
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NR; ++j) a[j] = st[base | L.gthr | L.greg[j]];
     }
 
-    for (int oi = P.op_begin; oi < P.op_end; ++oi) {
-        const DevOp op = ops[oi];
-        switch (op.code) {
-        case OP_EXCH: {
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < NR; ++j) lds[L.sthr ^ L.sreg[j]] = a[j];
-            __syncthreads();
-            cur = P.layout_begin + op.a;
-            make_layout<R, M>(L, layouts[cur], q, w, tid);
-#pragma unroll
-            for (int j = 0; j < NR; ++j) a[j] = lds[L.sthr ^ L.sreg[j]];
-            break;
-        }
-        case OP_D1: {
-            const T *d = cst + op.data;
-            const int kind = op.sa & ~SRC_POS_MASK, pos = op.sa & SRC_POS_MASK;
-            if (kind == SRC_REG) {
-                SV_SWITCH_A(pos, r_d1_reg<PA>(a, d))
-            } else {
-                const int bit = kind == SRC_THR ? (tid >> pos) & 1 : (int)((base >> pos) & 1);
-                r_mul_all(a, ldc(d + 2 * bit));
-            }
-            break;
-        }
-        case OP_D2: {
-            const T *d = cst + op.data;
-            const int ka = op.sa & ~SRC_POS_MASK, pa = op.sa & SRC_POS_MASK;
-            const int kb = op.sb & ~SRC_POS_MASK, pb = op.sb & SRC_POS_MASK;
-            const int ua = ka == SRC_THR ? (tid >> pa) & 1 : (int)((base >> pa) & 1);
-            const int ub = kb == SRC_THR ? (tid >> pb) & 1 : (int)((base >> pb) & 1);
-            if (ka == SRC_REG && kb == SRC_REG) {
-                SV_SWITCH_A(pa, SV_SWITCH_B(pb, if constexpr (PA != PB) r_d2_regreg<PA, PB>(a, d)))
-            } else if (ka == SRC_REG) {
-                SV_SWITCH_A(pa, r_d2_reg_hi<PA>(a, d, ub))
-            } else if (kb == SRC_REG) {
-                SV_SWITCH_B(pb, r_d2_reg_lo<PB>(a, d, ua))
-            } else {
-                r_mul_all(a, ldc(d + 2 * ((ua << 1) | ub)));
-            }
-            break;
-        }
-        case OP_MARK: {
-            if (base == op.data && tid == (int)op.b) {
+    cpx<T> f = mk<T>((T)1, (T)0);   // per-thread diagonal factor (OP_UD1/OP_UD2)
+    const int oe = P.op_end;
+    int oi = P.op_begin;
+    if (oi < oe) {
+        DevOp op = opb[oi];
+        for (;;) {
+            const DevOp nxt = opb[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
+            switch (op.code) {
+            case OP_EXCH: {
+                uint64_t gd;
+                uint32_t sthr, sreg[NR];
+                thr_part(LB[op.a], w, tid, SH, gd, sthr);
+                reg_slot<R>(LB[op.a], SH, sreg);
+                __syncthreads();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
-                    if (j == (int)op.a) a[j] = mk<T>(-a[j].x, -a[j].y);
+                    *reinterpret_cast<cpx<T> *>(ldsb + (sthr ^ sreg[j])) = a[j];
+                __syncthreads();
+                thr_part(LB[op.b], w, tid, SH, gd, sthr);
+                reg_slot<R>(LB[op.b], SH, sreg);
+#pragma unroll
+                for (int j = 0; j < NR; ++j)
+                    a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (sthr ^ sreg[j]));
+                break;
             }
-            break;
-        }
-        case OP_DENSE1: {
-            const T *m = cst + op.data;
-            SV_SWITCH_A(op.a, r_dense1<PA>(a, m))
-            break;
-        }
-        case OP_H: {
-            SV_SWITCH_A(op.a, r_h<PA>(a))
-            break;
-        }
-        case OP_X: {
-            SV_SWITCH_A(op.a, r_x<PA>(a))
-            break;
-        }
-        case OP_Y: {
-            SV_SWITCH_A(op.a, r_y<PA>(a))
-            break;
-        }
-        case OP_CX: {
-            const int kc = op.sa & ~SRC_POS_MASK, pc = op.sa & SRC_POS_MASK;
-            if (kc == SRC_REG) {
-                SV_SWITCH_A(op.a, SV_SWITCH_B(pc, if constexpr (PA != PB) r_cx_reg<PA, PB>(a)))
-            } else {
-                const bool c = kc == SRC_THR ? ((tid >> pc) & 1) : ((base >> pc) & 1);
+            case OP_D1R: {
+                const cpx<T> d0 = cmul(f, plc<T>(op, 0)), d1 = cmul(f, plc<T>(op, 1));
+                f = mk<T>((T)1, (T)0);
+                SV_SWITCH_A(op.a, r_d1_reg<PA>(a, d0, d1))
+                break;
+            }
+            case OP_UD1: {
+                const int b = src_bit(op.sa, tid, base);
+                f = cmul(f, b ? plc<T>(op, 1) : plc<T>(op, 0));
+                break;
+            }
+            case OP_UD2: {
+                const int e = (src_bit(op.sa, tid, base) << 1) | src_bit(op.sb, tid, base);
+                const cpx<T> d01 = (e & 1) ? plc<T>(op, 1) : plc<T>(op, 0);
+                const cpx<T> d23 = (e & 1) ? plc<T>(op, 3) : plc<T>(op, 2);
+                f = cmul(f, (e & 2) ? d23 : d01);
+                break;
+            }
+            case OP_APPLYF: {
+                r_mul_all(a, f);
+                f = mk<T>((T)1, (T)0);
+                break;
+            }
+            case OP_D2RR: {
+                const cpx<T> d[4] = {cmul(f, plc<T>(op, 0)), cmul(f, plc<T>(op, 1)),
+                                     cmul(f, plc<T>(op, 2)), cmul(f, plc<T>(op, 3))};
+                f = mk<T>((T)1, (T)0);
+                SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA != PB) r_d2_regreg<PA, PB>(a, d)))
+                break;
+            }
+            case OP_D2RU: {
+                const int u = src_bit(op.sa, tid, base);
+                const cpx<T> e0 = cmul(f, u ? plc<T>(op, 2) : plc<T>(op, 0));
+                const cpx<T> e1 = cmul(f, u ? plc<T>(op, 3) : plc<T>(op, 1));
+                f = mk<T>((T)1, (T)0);
+                SV_SWITCH_A(op.a, r_d1_reg<PA>(a, e0, e1))
+                break;
+            }
+            case OP_DENSE1: {
+                const cpx<T> g00 = cmul(f, plc<T>(op, 0)), g01 = cmul(f, plc<T>(op, 1));
+                const cpx<T> g10 = cmul(f, plc<T>(op, 2)), g11 = cmul(f, plc<T>(op, 3));
+                f = mk<T>((T)1, (T)0);
+                SV_SWITCH_A(op.a, r_dense1<PA>(a, g00, g01, g10, g11))
+                break;
+            }
+            case OP_H: {
+                SV_SWITCH_A(op.a, r_h<PA>(a))
+                break;
+            }
+            case OP_X: {
+                SV_SWITCH_A(op.a, r_x<PA>(a))
+                break;
+            }
+            case OP_CXR: {
+                SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA != PB) r_cx_reg<PA, PB>(a)))
+                break;
+            }
+            case OP_CXU: {
+                const bool c = src_bit(op.sa, tid, base) != 0;
                 SV_SWITCH_A(op.a, r_cx_uni<PA>(a, c))
+                break;
             }
-            break;
-        }
-        case OP_SWAP: {
-            SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA > PB) r_swap<PA, PB>(a)))
-            break;
-        }
-        case OP_DENSE2: {
-            const T *m = cst + op.data;
-            SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA > PB) r_dense2<PA, PB>(a, m)))
-            break;
-        }
-        case OP_SCALE: {
-            r_scale(a, cst[op.data]);
-            break;
-        }
-        default:
-            break;
+            case OP_CXT: {
+                if ((base >> (op.sa & SRC_POS_MASK)) & 1) {
+                    SV_SWITCH_A(op.a, r_x<PA>(a))
+                }
+                break;
+            }
+            case OP_MARK: {
+                if (base == op.data && tid == (int)op.b) {
+#pragma unroll
+                    for (int j = 0; j < NR; ++j)
+                        if (j == (int)op.a) a[j] = mk<T>(-a[j].x, -a[j].y);
+                }
+                break;
+            }
+            case OP_SCALE: {
+                r_scale(a, pl<T>(op, 0));
+                break;
+            }
+            default:
+                break;
+            }
+            if (++oi >= oe) break;
+            op = nxt;
         }
     }
 
-    const bool pair_out = (sizeof(T) == 4) && layouts[cur].reg_local[0] == 0 && q[0] == 0;
-    if (pair_out) {
+    if (P.flags & PASS_SYNC_STORE) __syncthreads();
+    {
+        const DevLayout &L = LB[P.store_layout];
+        uint64_t gthr;
+        uint32_t sdummy;
+        thr_part(L, w, tid, SH, gthr, sdummy);
+        uint64_t greg[NR];
+        reg_goff<R>(L, greg);
+        cpx<T> *tp = st + (base | gthr);
+        if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
 #pragma unroll
-        for (int j = 0; j < NR; j += 2) {
-            float4 v;
-            v.x = (float)a[j].x;
-            v.y = (float)a[j].y;
-            v.z = (float)a[j + 1].x;
-            v.w = (float)a[j + 1].y;
-            *reinterpret_cast<float4 *>(st + (base | L.gthr | L.greg[j])) = v;
+            for (int j = 0; j < NR; j += 2) {
+                float4 v;
+                v.x = (float)a[j].x;
+                v.y = (float)a[j].y;
+                v.z = (float)a[j + 1].x;
+                v.w = (float)a[j + 1].y;
+                *reinterpret_cast<float4 *>(tp + greg[j]) = v;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) tp[greg[j]] = a[j];
         }
-    } else {
-#pragma unroll
-        for (int j = 0; j < NR; ++j) st[base | L.gthr | L.greg[j]] = a[j];
     }
 }
 
@@ -684,18 +668,15 @@ hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch, ui
 
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const DevPass *d_passes,
                        int pass_idx, const DevPass &h_pass, const DevLayout *d_layouts,
-                       const DevOp *d_ops, const void *d_consts, uint64_t const_stride,
-                       hipStream_t st) {
+                       const DevOp *d_ops, uint64_t ops_stride, hipStream_t st) {
     const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
     const dim3 block(1u << h_pass.w);
     if (dt == 2)
         hipLaunchKernelGGL(k_pass<double>, grid, block, 0, st, (cpx<double> *)state, n_amps,
-                           d_passes, pass_idx, d_layouts, d_ops, (const double *)d_consts,
-                           const_stride);
+                           d_passes, pass_idx, d_layouts, d_ops, ops_stride);
     else
         hipLaunchKernelGGL(k_pass<float>, grid, block, 0, st, (cpx<float> *)state, n_amps,
-                           d_passes, pass_idx, d_layouts, d_ops, (const float *)d_consts,
-                           const_stride);
+                           d_passes, pass_idx, d_layouts, d_ops, ops_stride);
     return hipGetLastError();
 }
 

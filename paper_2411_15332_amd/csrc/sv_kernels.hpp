@@ -27,8 +27,8 @@ hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch,
 
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch,
                        const DevPass *d_passes, int pass_idx, const DevPass &h_pass,
-                       const DevLayout *d_layouts, const DevOp *d_ops,
-                       const void *d_consts, uint64_t const_stride, hipStream_t st);
+                       const DevLayout *d_layouts, const DevOp *d_ops, uint64_t ops_stride,
+                       hipStream_t st);
 
 hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_ops,
                         int n_ops, const void *d_consts, uint64_t const_stride,

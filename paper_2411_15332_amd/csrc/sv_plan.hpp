@@ -7,42 +7,51 @@
 // the tile once, applies every operation of the pass, and writes it back once.
 //
 // Inside the workgroup a tile is held in registers: thread t (of 2^w) holds
-// 2^R amplitudes. A "layout" says which tile-local bits are register bits and
-// which are thread bits. Gates whose non-diagonal part lives on register bits
-// are applied without communication; an EXCH operation re-distributes the tile
-// through LDS into a new layout. Diagonal gates need no register bits at all:
-// each thread knows the global index of every amplitude it holds.
+// 2^R amplitudes in register slots j. A "layout" maps (thread bit s, register
+// bit p) to tile-local index bits ("labels"), plus an XOR mask c on the labels:
+// the amplitude in (t, j) has tile-local index  L(t, j) ^ c. Permutation gates
+// on tile qubits are applied by changing the layout instead of moving data
+// (SWAP exchanges two labels, X flips a label's XOR bit): the index part of a
+// value+index (DAX) entry is absorbed into the addressing, only values remain.
+// An EXCH operation re-distributes the tile through LDS into a new layout.
 #pragma once
 
 #include <cstdint>
 
 namespace sv {
 
-// Bit sources: where the value of one global index bit comes from, for the
-// amplitude a thread holds in register slot j.
+// Bit sources: where the value of one index bit comes from, for the amplitude a
+// thread holds in register slot j (already corrected for the layout's XOR mask
+// by the planner, which permutes the operation's constants instead).
 enum : uint8_t {
     SRC_REG = 0 << 6,   // bit p of the register slot j (p < R)
     SRC_THR = 1 << 6,   // bit s of the thread index
-    SRC_TILE = 2 << 6,  // bit q of the tile's base index (outside the tile)
+    SRC_TILE = 2 << 6,  // bit q of the tile's base index (a qubit outside the tile)
     SRC_POS_MASK = 63
 };
 
 enum OpCode : uint8_t {
-    OP_EXCH = 1,     // a = layout index within the pass
-    OP_D1 = 2,       // 1-qubit diagonal: amp *= d[bit];   sa; data = const offset (4 reals)
-    OP_D2 = 3,       // 2-qubit diagonal: amp *= d[(b0<<1)|b1]; sa, sb; data (8 reals)
-    OP_MARK = 4,     // amp[idx == m] *= -1: a = register slot, b = thread, data = tile base of m
-    OP_DENSE1 = 5,   // 2x2 on register bit a; data (8 reals, row-major g00 g01 g10 g11)
-    OP_H = 6,        // unscaled Hadamard butterfly (x0 + x1, x0 - x1) on register bit a
-    OP_X = 7,        // swap pairs on register bit a
-    OP_Y = 8,        // (x0, x1) -> (-i x1, i x0) on register bit a
-    OP_CX = 9,       // controlled swap on register bit a, control bit source sa
-    OP_SWAP = 10,    // swap of register bits a, b (a > b)
-    OP_DENSE2 = 11,  // 4x4 on register bits a (high local bit) and b (low), a > b; data (32 reals)
-    OP_SCALE = 12,   // amp *= s (real); data (1 real)
+    OP_EXCH = 1,     // write tile to LDS in layout a, read it back in layout b (pass-relative)
+    OP_D1R = 2,      // amp *= f d[bit p of j], f = 1; a = p; payload d0, d1
+    OP_UD1 = 3,      // per-thread factor f *= d[bit]; sa = THR/TILE source; payload d0, d1
+    OP_UD2 = 4,      // f *= d[(bit sa << 1) | bit sb]; payload d[4]
+    OP_APPLYF = 5,   // amp *= f for every slot; f = 1
+    OP_D2RR = 6,     // amp *= f d[(bit a of j << 1) | bit b of j], f = 1; payload d[4]
+    OP_D2RU = 7,     // amp *= f e[u][bit a of j], u = bit of source sa, f = 1; payload e[2][2]
+    OP_DENSE1 = 8,   // f times a 2x2 on register bit a, f = 1; payload g00 g01 g10 g11
+    OP_H = 9,        // unscaled Hadamard butterfly (x0 + x1, x0 - x1) on register bit a
+    OP_X = 10,       // swap the pairs of register bit a
+    OP_CXR = 11,     // swap the pairs of register bit a where register bit b is 1
+    OP_CXU = 12,     // swap the pairs of register bit a when the bit of source sa is 1
+    OP_MARK = 13,    // amp(slot a, thread b) *= -1 in the tile whose base equals `data`
+    OP_SCALE = 14,   // amp *= s; payload s (one real)
+    OP_CXT = 15,     // swap the pairs of register bit a when tile-base bit `sa` (a qubit
+                     // outside the tile, the same for the whole workgroup) is 1
 };
 
-struct DevOp {        // 16 bytes
+// One operation: 16-byte header and 64-byte payload (8 doubles or 16 floats:
+// the constants in the precision of the state). Stored per batch entry.
+struct DevOp {
     uint8_t code;
     uint8_t a;
     uint8_t b;
@@ -50,21 +59,42 @@ struct DevOp {        // 16 bytes
     uint8_t sb;
     uint8_t pad[3];
     uint64_t data;
+    uint64_t payload[8];
 };
 
-struct DevLayout {    // 16 bytes
-    uint8_t reg_local[8];   // tile-local bit held by register bit p
-    uint8_t thr_local[8];   // tile-local bit held by thread bit s
+// Per-layout tables, precomputed on the host. The global index of the
+// amplitude in (t, j) is  tile_base | gthr(t) | greg(j)  (disjoint bits) with
+//   gthr(t) = goff_xor ^ XOR_{s: t_s = 1} thr_goff[s],
+//   greg(j) = reg_goff_xor ^ XOR_{p: j_p = 1} reg_goff[p],
+// and its LDS slot (swizzled) is  sthr(t) ^ sreg(j), built the same way.
+struct DevLayout {
+    uint64_t thr_goff[8];
+    uint64_t reg_goff[8];
+    uint32_t thr_slot[8];
+    uint32_t reg_slot[8];
+    uint64_t goff_xor;       // global offset of the XOR-mask labels held by thread bits
+    uint32_t slot_xor;       // LDS slot contribution of the whole XOR mask
+    uint32_t flags;          // LAYOUT_PAIR_IO: slots j, j^1 are adjacent in HBM (complex64 16-byte I/O)
+    uint8_t reg_local[8];    // label held by register bit p
+    uint8_t thr_local[8];    // label held by thread bit s
+    uint32_t xor_local;      // XOR mask c on the labels
+    uint32_t pad0;
+    uint64_t reg_goff_xor;   // global offset of the XOR-mask labels held by register bits
+    uint8_t pad[16];
 };
+
+enum : uint32_t { LAYOUT_PAIR_IO = 1u };
 
 enum : uint32_t {
     PASS_GENERATE = 1u,     // no load: amplitudes of H^M |j> generated in place
+    PASS_SYNC_STORE = 2u,   // barrier before the store: the store layout moves amplitudes
+                            // between waves and no exchange has separated loads from stores
 };
 
 struct DevPass {      // 96 bytes
     int32_t k;              // tile qubits
     int32_t w;              // thread bits (2^w threads; k = w + R)
-    int32_t op_begin;       // index into the op array
+    int32_t op_begin;       // index into the op array of a batch entry
     int32_t op_end;
     int32_t layout_begin;   // index of this pass's layout 0 (the load layout)
     uint32_t flags;
@@ -72,12 +102,13 @@ struct DevPass {      // 96 bytes
     uint64_t gen_j;         // generation: basis state j
     uint64_t gen_mask;      // generation: Hadamard qubit mask M
     double gen_scale;       // generation: magnitude 2^(-|M|/2) times folded scale
-    uint8_t q[32];          // global qubit of tile-local bit l (ascending)
+    int32_t store_layout;   // pass-relative index of the layout the tile is stored from
+    uint8_t q[28];          // global qubit of tile-local bit l (ascending)
     uint8_t pad[8];
 };
 
-static_assert(sizeof(DevOp) == 16, "DevOp layout");
-static_assert(sizeof(DevLayout) == 16, "DevLayout layout");
+static_assert(sizeof(DevOp) == 80, "DevOp layout");
+static_assert(sizeof(DevLayout) == 256, "DevLayout layout");
 static_assert(sizeof(DevPass) == 96, "DevPass layout");
 
 // Ops of the one-workgroup small-state kernel: the whole state sits in LDS.

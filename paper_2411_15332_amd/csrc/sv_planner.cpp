@@ -1,22 +1,29 @@
-// Gate classification, pass planning and constant tables (host side).
+// Gate classification, pass planning and operation payloads (host side).
 //
 // Classification follows the paper's observation (Sec. II-C, Table 1) that
-// most gates are sparse: diagonal and monomial gates are applied from their
-// gate-local non-zeros only (DAX: value + index, Sec. III-A1), Hadamards from
-// one magnitude plus index-derived signs (RH, Sec. III-B1), and only the rest
-// as dense 2x2 / 4x4 butterflies. Where the paper composes a stage's gates into
-// one compressed operator before a single matrix-vector product (Sec. III-A2),
-// the planner composes a run of gates into one pass over HBM instead: the
-// operator is never formed, only the schedule.
+// most gates are sparse. Diagonal gates are applied from their phases alone,
+// monomial gates from their gate-local (value, index) form — the DAX entry of
+// Sec. III-A1 restricted to the gate's own 2^k x 2^k matrix — and a
+// Hadamard from one magnitude plus index-derived signs (RH, Sec. III-B1).
+// Where the paper composes a stage's gates into one compressed operator before
+// a single matrix-vector product (Sec. III-A2, MTP before MVM), the planner
+// composes a run of gates into one pass over HBM: permutations are absorbed
+// into the tile's addressing (the index part of a DAX entry), runs of 1-qubit
+// gates on one register bit are multiplied into one 2x2, and diagonal factors
+// that are constant across a thread's registers are folded into one scalar.
+// The 2^n x 2^n operator is never formed.
 #include "sv_planner.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 
 #include "sv_swizzle.hpp"
 
 namespace sv {
+
+using cd = std::complex<double>;
 
 static inline int popc(uint64_t x) { return __builtin_popcountll(x); }
 static inline uint64_t bit(int q) { return 1ull << q; }
@@ -109,11 +116,10 @@ CGate classify(const sv_gate &g, int n, int src) {
     case G_D1: c.diag = true; c.support = bit(c.q0); break;
     case G_D2: c.diag = true; c.support = bit(c.q0) | bit(c.q1); break;
     case G_MARK: c.diag = true; c.support = (n >= 64) ? ~0ull : (bit(n) - 1); break;
-    case G_X: case G_Y: case G_H: case G_DENSE1:
-        c.support = bit(c.q0); c.need = bit(c.q0); break;
-    case G_CX: c.support = bit(c.q0) | bit(c.q1); c.need = bit(c.q1); break;
-    case G_SWAP: case G_DENSE2:
-        c.support = bit(c.q0) | bit(c.q1); c.need = c.support; break;
+    case G_X: case G_Y: c.support = c.qneed = bit(c.q0); break;
+    case G_H: case G_DENSE1: c.support = c.qneed = c.rneed = bit(c.q0); break;
+    case G_CX: c.support = bit(c.q0) | bit(c.q1); c.qneed = c.rneed = bit(c.q1); break;
+    case G_SWAP: c.support = c.qneed = bit(c.q0) | bit(c.q1); break;
     default: break;
     }
     return c;
@@ -138,218 +144,7 @@ struct Blocker {
     }
 };
 
-static bool is_dense(GClass c) { return c == G_DENSE1 || c == G_DENSE2; }
-
-namespace {
-
-struct PassCtx {
-    const PlanOptions &opt;
-    Plan &P;
-    const std::vector<CGate> &cg;
-    int n, k, w;
-    uint8_t q[32];
-    int local_of[64];
-    int pass_layout_begin = 0;
-    DevLayout cur;
-    int reg_of_local[32];   // register bit of a tile-local bit, -1 if a thread bit
-    int thr_of_local[32];
-
-    PassCtx(const PlanOptions &o, Plan &p, const std::vector<CGate> &g, int n_, int k_, int w_)
-        : opt(o), P(p), cg(g), n(n_), k(k_), w(w_) {}
-
-    uint64_t U_mask() const {  // local bits that may hold registers in a storable layout
-        uint64_t u = 0;
-        for (int l = opt.v + 6; l < k; ++l) u |= bit(l);
-        return u;
-    }
-    uint64_t V_mask() const { return opt.v ? 1ull : 0ull; }
-    uint64_t lanes_mask() const {
-        uint64_t u = 0;
-        for (int l = opt.v; l < opt.v + 6; ++l) u |= bit(l);
-        return u;
-    }
-    uint64_t to_local(uint64_t qmask) const {
-        uint64_t r = 0;
-        for (int qq = 0; qq < n; ++qq)
-            if ((qmask >> qq) & 1) r |= bit(local_of[qq]);
-        return r;
-    }
-
-    // regs_u: R - v tile-local bits from U_mask().
-    DevLayout storable(uint64_t regs_u) const {
-        DevLayout L;
-        std::memset(&L, 0, sizeof L);
-        int p = 0;
-        for (int l = 0; l < opt.v; ++l) L.reg_local[p++] = (uint8_t)l;
-        for (int l = 0; l < k; ++l)
-            if ((regs_u >> l) & 1) L.reg_local[p++] = (uint8_t)l;
-        int s = 0;
-        for (int l = opt.v; l < opt.v + 6; ++l) L.thr_local[s++] = (uint8_t)l;
-        const uint64_t rest = U_mask() & ~regs_u;
-        for (int l = 0; l < k; ++l)
-            if ((rest >> l) & 1) L.thr_local[s++] = (uint8_t)l;
-        return L;
-    }
-
-    // regs: R tile-local bits; lanes 0..m-1 get thread bits whose swizzle
-    // images are linearly independent (conflict-free LDS rows).
-    DevLayout general(uint64_t regs) const {
-        DevLayout L;
-        std::memset(&L, 0, sizeof L);
-        int p = 0;
-        for (int l = 0; l < k; ++l)      // ascending: local bit 0 lands on register 0
-            if ((regs >> l) & 1) L.reg_local[p++] = (uint8_t)l;
-        std::vector<int> thr;
-        for (int l = 0; l < k; ++l)
-            if (!((regs >> l) & 1)) thr.push_back(l);
-        std::vector<int> lanes;
-        uint32_t basis[8] = {0};  // GF(2) basis indexed by leading bit
-        std::vector<int> others;
-        for (int l : thr) {
-            uint32_t x = swz_image(l, opt.m);
-            for (int b = opt.m - 1; b >= 0 && x; --b) {
-                if (!((x >> b) & 1)) continue;
-                if (basis[b]) x ^= basis[b];
-                else { basis[b] = x; break; }
-            }
-            if (x && (int)lanes.size() < opt.m) lanes.push_back(l);
-            else others.push_back(l);
-        }
-        int s = 0;
-        for (int l : lanes) L.thr_local[s++] = (uint8_t)l;
-        for (int l : others) L.thr_local[s++] = (uint8_t)l;
-        return L;
-    }
-
-    bool is_storable(const DevLayout &L) const {
-        for (int p = 0; p < opt.v; ++p)
-            if (L.reg_local[p] != p) return false;
-        for (int s = 0; s < 6; ++s)
-            if (L.thr_local[s] != opt.v + s) return false;
-        return true;
-    }
-
-    uint64_t reg_mask(const DevLayout &L) const {
-        uint64_t r = 0;
-        for (int p = 0; p < opt.R; ++p) r |= bit(L.reg_local[p]);
-        return r;
-    }
-
-    void set_current(const DevLayout &L) {
-        cur = L;
-        for (int l = 0; l < 32; ++l) reg_of_local[l] = thr_of_local[l] = -1;
-        for (int p = 0; p < opt.R; ++p) reg_of_local[L.reg_local[p]] = p;
-        for (int s = 0; s < w; ++s) thr_of_local[L.thr_local[s]] = s;
-    }
-
-    int add_layout(const DevLayout &L) {
-        P.layouts.push_back(L);
-        return (int)P.layouts.size() - 1 - pass_layout_begin;
-    }
-
-    uint8_t src_of(int qubit) const {
-        const int l = local_of[qubit];
-        if (l >= 0) {
-            if (reg_of_local[l] >= 0) return (uint8_t)(SRC_REG | reg_of_local[l]);
-            return (uint8_t)(SRC_THR | thr_of_local[l]);
-        }
-        return (uint8_t)(SRC_TILE | qubit);
-    }
-    int reg_of(int qubit) const { return reg_of_local[local_of[qubit]]; }
-
-    uint64_t add_const(ConstKind kind, int gate, int count, bool swap_bits = false,
-                       double scale = 1.0) {
-        ConstBlock b;
-        b.kind = kind;
-        b.gate = gate;
-        b.scale = scale;
-        b.off = P.cstride;
-        b.swap_bits = swap_bits;
-        P.cblocks.push_back(b);
-        P.cstride += (uint64_t)count;
-        return b.off;
-    }
-
-    // Emit the op of gate g in the current layout. Returns the index of its
-    // constant block in P.cblocks, or -1.
-    int emit(const CGate &g, int &h_count) {
-        DevOp op;
-        std::memset(&op, 0, sizeof op);
-        int cb = -1;
-        switch (g.cls) {
-        case G_D1:
-            op.code = OP_D1;
-            op.sa = src_of(g.q0);
-            cb = (int)P.cblocks.size();
-            op.data = add_const(CK_D1, g.src, 4);
-            break;
-        case G_D2:
-            op.code = OP_D2;
-            op.sa = src_of(g.q0);
-            op.sb = src_of(g.q1);
-            cb = (int)P.cblocks.size();
-            op.data = add_const(CK_D2, g.src, 8);
-            break;
-        case G_MARK: {
-            op.code = OP_MARK;
-            uint64_t qmask = 0;
-            for (int l = 0; l < k; ++l) qmask |= bit(q[l]);
-            op.data = g.index & ~qmask;
-            int t = 0, j = 0;
-            for (int l = 0; l < k; ++l) {
-                if (!((g.index >> q[l]) & 1)) continue;
-                if (reg_of_local[l] >= 0) j |= 1 << reg_of_local[l];
-                else t |= 1 << thr_of_local[l];
-            }
-            op.a = (uint8_t)j;
-            op.b = (uint8_t)t;
-            break;
-        }
-        case G_X: op.code = OP_X; op.a = (uint8_t)reg_of(g.q0); break;
-        case G_Y: op.code = OP_Y; op.a = (uint8_t)reg_of(g.q0); break;
-        case G_H: op.code = OP_H; op.a = (uint8_t)reg_of(g.q0); ++h_count; break;
-        case G_DENSE1:
-            op.code = OP_DENSE1;
-            op.a = (uint8_t)reg_of(g.q0);
-            cb = (int)P.cblocks.size();
-            op.data = add_const(CK_DENSE1, g.src, 8);
-            break;
-        case G_CX:
-            op.code = OP_CX;
-            op.a = (uint8_t)reg_of(g.q1);
-            op.sa = src_of(g.q0);
-            break;
-        case G_SWAP: {
-            int a = reg_of(g.q0), b = reg_of(g.q1);
-            if (a < b) std::swap(a, b);
-            op.code = OP_SWAP;
-            op.a = (uint8_t)a;
-            op.b = (uint8_t)b;
-            break;
-        }
-        case G_DENSE2: {
-            int a = reg_of(g.q0), b = reg_of(g.q1);
-            const bool sw = a < b;
-            if (sw) std::swap(a, b);
-            op.code = OP_DENSE2;
-            op.a = (uint8_t)a;
-            op.b = (uint8_t)b;
-            cb = (int)P.cblocks.size();
-            op.data = add_const(CK_DENSE2, g.src, 32, sw);
-            break;
-        }
-        default:
-            return -1;
-        }
-        P.ops.push_back(op);
-        ++P.gates_applied;
-        return cb;
-    }
-};
-
-}  // namespace
-
-// Split `gates` into passes; each entry lists indices into cg.
+// Split the gates into passes (lists of indices into cg) and their tile sets.
 static std::vector<std::vector<int>> form_passes(const std::vector<CGate> &cg,
                                                  const std::vector<int> &order, int n, int k,
                                                  const PlanOptions &opt, int c,
@@ -357,7 +152,7 @@ static std::vector<std::vector<int>> form_passes(const std::vector<CGate> &cg,
     std::vector<std::vector<int>> passes;
     std::vector<int> pending = order;
     const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
-    const uint64_t low = (c >= 64) ? ~0ull : (bit(c) - 1);
+    const uint64_t low = bit(c) - 1;
     while (!pending.empty()) {
         uint64_t Q = low & all;
         Blocker blk;
@@ -370,14 +165,13 @@ static std::vector<std::vector<int>> form_passes(const std::vector<CGate> &cg,
             if (closed) { deferred.push_back(gi); continue; }
             bool take = false;
             if (!blk.conflicts(g)) {
-                const uint64_t need = g.need;
-                const bool dense_ok = !is_dense(g.cls) || dense < opt.max_dense;
-                if (dense_ok && (need & ~Q) == 0) take = true;
-                else if (dense_ok && popc(Q | need) <= k) { Q |= need; take = true; }
+                const bool dense_ok = g.cls != G_DENSE1 || dense < opt.max_dense;
+                if (dense_ok && (g.qneed & ~Q) == 0) take = true;
+                else if (dense_ok && popc(Q | g.qneed) <= k) { Q |= g.qneed; take = true; }
             }
             if (take) {
                 taken.push_back(gi);
-                if (is_dense(g.cls)) ++dense;
+                if (g.cls == G_DENSE1) ++dense;
                 if (!opt.fuse) closed = true;
             } else {
                 deferred.push_back(gi);
@@ -385,8 +179,7 @@ static std::vector<std::vector<int>> form_passes(const std::vector<CGate> &cg,
                 if ((blk.nondiag & all) == all) closed = true;  // nothing can move past
             }
         }
-        // fill Q up to k qubits with the lowest ones not yet in it
-        for (int qq = 0; qq < n && popc(Q) < k; ++qq) Q |= bit(qq);
+        for (int qq = 0; qq < n && popc(Q) < k; ++qq) Q |= bit(qq);  // fill with the lowest qubits
         passes.push_back(taken);
         qsets.push_back(Q);
         pending.swap(deferred);
@@ -400,6 +193,405 @@ static double hadamard_magnitude(int h) {
     if (h & 1) s *= 0.70710678118654752440;
     return s;
 }
+
+namespace {
+
+// Structural class of a pending register-bit product.
+enum : uint8_t { PC_I = 0, PC_D, PC_A, PC_H, PC_G };
+
+uint8_t compose_class(uint8_t cur, uint8_t fc) {
+    if (cur == PC_I) return fc;
+    if ((cur == PC_D || cur == PC_A) && (fc == PC_D || fc == PC_A))
+        return cur == fc ? PC_D : PC_A;
+    return PC_G;
+}
+
+struct Pending {
+    uint8_t cls = PC_I;
+    bool pure_x = true;
+    std::vector<Factor> f;
+};
+
+struct Src {
+    uint8_t code;   // SRC_* | position
+    int inv;        // 1 when the physical bit is the label bit XOR 1
+    bool reg;
+    int p;          // register bit when reg
+};
+
+struct PassCtx {
+    const PlanOptions &opt;
+    Plan &P;
+    const std::vector<CGate> &cg;
+    int n, k, w;
+    uint8_t q[32];
+    int label_of[64];
+    // layout state: position of every label and the XOR mask
+    int reg_label[8], thr_label[8];
+    int pos_reg[32], pos_thr[32];   // register / thread bit holding label l, or -1
+    uint32_t xmask = 0;
+    int layout_begin = 0;
+    int cur_layout = -1;            // pass-relative index of the materialized state, -1: not yet
+    Pending pend[8];
+    bool f_used = false;
+    int h_count = 0;
+    int first_payload = -1;
+
+    PassCtx(const PlanOptions &o, Plan &p, const std::vector<CGate> &g, int n_, int k_, int w_)
+        : opt(o), P(p), cg(g), n(n_), k(k_), w(w_) {}
+
+    uint64_t U_labels() const {   // labels that may hold registers in a storable layout
+        uint64_t u = 0;
+        for (int l = opt.v + 6; l < k; ++l) u |= bit(l);
+        return u;
+    }
+
+    void set_state(const int *regl, const int *thrl, uint32_t xm) {
+        for (int l = 0; l < 32; ++l) pos_reg[l] = pos_thr[l] = -1;
+        for (int p = 0; p < opt.R; ++p) { reg_label[p] = regl[p]; pos_reg[regl[p]] = p; }
+        for (int s = 0; s < w; ++s) { thr_label[s] = thrl[s]; pos_thr[thrl[s]] = s; }
+        xmask = xm;
+        cur_layout = -1;
+    }
+
+    // regs_u: R - v labels from U_labels(); lanes hold labels v..v+5.
+    void storable_state(uint64_t regs_u) {
+        int regl[8], thrl[8], p = 0, s = 0;
+        for (int l = 0; l < opt.v; ++l) regl[p++] = l;
+        for (int l = 0; l < k; ++l) if ((regs_u >> l) & 1) regl[p++] = l;
+        for (int l = opt.v; l < opt.v + 6; ++l) thrl[s++] = l;
+        const uint64_t rest = U_labels() & ~regs_u;
+        for (int l = 0; l < k; ++l) if ((rest >> l) & 1) thrl[s++] = l;
+        set_state(regl, thrl, 0);
+    }
+
+    // regs: R labels; lanes 0..m-1 get labels whose swizzle images are
+    // linearly independent (conflict-free LDS rows).
+    void general_state(uint64_t regs) {
+        int regl[8], thrl[8], p = 0;
+        for (int l = 0; l < k; ++l) if ((regs >> l) & 1) regl[p++] = l;
+        std::vector<int> lanes, others;
+        uint32_t basis[8] = {0};
+        for (int l = 0; l < k; ++l) {
+            if ((regs >> l) & 1) continue;
+            uint32_t x = swz_image(l, opt.m);
+            for (int b = opt.m - 1; b >= 0 && x; --b) {
+                if (!((x >> b) & 1)) continue;
+                if (basis[b]) x ^= basis[b];
+                else { basis[b] = x; break; }
+            }
+            if (x && (int)lanes.size() < opt.m) lanes.push_back(l);
+            else others.push_back(l);
+        }
+        int s = 0;
+        for (int l : lanes) thrl[s++] = l;
+        for (int l : others) thrl[s++] = l;
+        set_state(regl, thrl, 0);
+    }
+
+    bool is_storable() const {
+        for (int s = 0; s < 6; ++s)
+            if (thr_label[s] < opt.v || thr_label[s] >= opt.v + 6) return false;
+        if (opt.v && (reg_label[0] != 0 || (xmask & 1))) return false;
+        return true;
+    }
+
+    uint64_t reg_labels() const {
+        uint64_t r = 0;
+        for (int p = 0; p < opt.R; ++p) r |= bit(reg_label[p]);
+        return r;
+    }
+
+    static uint32_t slot_lin(int l, int m) {
+        return (1u << l) ^ (l >= m ? swz_image(l, m) : 0u);
+    }
+
+    int layout_index() {
+        if (cur_layout >= 0) return cur_layout;
+        DevLayout L;
+        std::memset(&L, 0, sizeof L);
+        for (int s = 0; s < w; ++s) {
+            L.thr_goff[s] = 1ull << q[thr_label[s]];
+            L.thr_slot[s] = slot_lin(thr_label[s], opt.m);
+            L.thr_local[s] = (uint8_t)thr_label[s];
+        }
+        for (int p = 0; p < opt.R; ++p) {
+            L.reg_goff[p] = 1ull << q[reg_label[p]];
+            L.reg_slot[p] = slot_lin(reg_label[p], opt.m);
+            L.reg_local[p] = (uint8_t)reg_label[p];
+        }
+        for (int l = 0; l < k; ++l) {
+            if ((xmask >> l) & 1) {
+                if (pos_reg[l] >= 0) L.reg_goff_xor ^= 1ull << q[l];
+                else L.goff_xor ^= 1ull << q[l];
+                L.slot_xor ^= slot_lin(l, opt.m);
+            }
+        }
+        L.xor_local = xmask;
+        if (opt.v && reg_label[0] == 0 && !(xmask & 1)) L.flags |= LAYOUT_PAIR_IO;
+        P.layouts.push_back(L);
+        cur_layout = (int)P.layouts.size() - 1 - layout_begin;
+        return cur_layout;
+    }
+
+    Src src_of(int qubit) const {
+        Src s{};
+        const int l = label_of[qubit];
+        if (l < 0) {
+            s.code = (uint8_t)(SRC_TILE | qubit);
+            s.inv = 0;
+            s.reg = false;
+            return s;
+        }
+        s.inv = (int)((xmask >> l) & 1);
+        if (pos_reg[l] >= 0) {
+            s.code = (uint8_t)(SRC_REG | pos_reg[l]);
+            s.reg = true;
+            s.p = pos_reg[l];
+        } else {
+            s.code = (uint8_t)(SRC_THR | pos_thr[l]);
+            s.reg = false;
+        }
+        return s;
+    }
+
+    HostOp &emit(uint8_t code) {
+        P.ops.emplace_back();
+        HostOp &o = P.ops.back();
+        o.hdr.code = code;
+        return o;
+    }
+    void note_payload() {
+        if (first_payload < 0) first_payload = (int)P.ops.size() - 1;
+    }
+
+    void compose(int p, Factor f, uint8_t fc, bool is_x) {
+        Pending &pd = pend[p];
+        pd.cls = compose_class(pd.cls, fc);
+        pd.pure_x = pd.pure_x && is_x;
+        pd.f.push_back(f);
+    }
+
+    void flush(int p) {
+        Pending &pd = pend[p];
+        if (pd.cls == PC_I) { pd = Pending(); return; }
+        if (pd.cls == PC_D) {
+            HostOp &o = emit(OP_D1R);
+            o.hdr.a = (uint8_t)p;
+            o.pk = PK_DIAG2;
+            o.factors = pd.f;
+            note_payload();
+            f_used = false;   // the op multiplies by the pending per-thread factor
+        } else if (pd.cls == PC_A && pd.pure_x) {
+            HostOp &o = emit(OP_X);
+            o.hdr.a = (uint8_t)p;
+        } else if (pd.cls == PC_H) {
+            HostOp &o = emit(OP_H);
+            o.hdr.a = (uint8_t)p;
+            ++h_count;
+        } else {
+            HostOp &o = emit(OP_DENSE1);
+            o.hdr.a = (uint8_t)p;
+            o.pk = PK_MAT2;
+            o.factors = pd.f;
+            note_payload();
+            f_used = false;
+        }
+        pd = Pending();
+    }
+    void flush_nondiag(int p) {
+        if (pend[p].cls != PC_I && pend[p].cls != PC_D) flush(p);
+    }
+    void flush_all() {
+        for (int p = 0; p < opt.R; ++p) flush(p);
+        if (f_used) {
+            emit(OP_APPLYF);
+            f_used = false;
+        }
+    }
+
+    // Register needs in this pass: a CNOT's control inside the tile is asked
+    // for too, so that the CNOT becomes a compile-time register swap (a
+    // control outside the tile is uniform per workgroup instead).
+    uint64_t rneed_of(const CGate &g) const {
+        uint64_t r = g.rneed;
+        if (g.cls == G_CX && label_of[g.q0] >= 0) r |= bit(g.q0);
+        return r;
+    }
+
+    bool absorbable(const CGate &g) const {
+        const uint64_t rn = rneed_of(g);
+        for (int qq = 0; qq < n; ++qq) {
+            if (!((rn >> qq) & 1)) continue;
+            const int l = label_of[qq];
+            if (l < 0 || pos_reg[l] < 0) return false;
+        }
+        return true;
+    }
+
+    // Gate-local index of a 2-qubit diagonal entry from physical bits (x of
+    // q0's position, y of q1's position) and the labels' XOR bits.
+    static uint8_t d4_index(int x, int y, int inv0, int inv1) {
+        return (uint8_t)(((x ^ inv0) << 1) | (y ^ inv1));
+    }
+
+    void apply(const CGate &g) {
+        ++P.gates_applied;
+        switch (g.cls) {
+        case G_D1: {
+            const Src s = src_of(g.q0);
+            if (s.reg) {
+                compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_D, false);
+            } else {
+                HostOp &o = emit(OP_UD1);
+                o.hdr.sa = s.code;
+                o.pk = PK_DIAG2;
+                o.factors.push_back(Factor{FK_GATE, s.inv != 0, g.src});
+                note_payload();
+                f_used = true;
+            }
+            break;
+        }
+        case G_D2: {
+            const Src s0 = src_of(g.q0), s1 = src_of(g.q1);
+            if (s0.reg && s1.reg) {
+                flush_nondiag(s0.p);
+                flush_nondiag(s1.p);
+                HostOp &o = emit(OP_D2RR);
+                o.hdr.a = (uint8_t)s0.p;
+                o.hdr.b = (uint8_t)s1.p;
+                o.pk = PK_D4;
+                o.gate = g.src;
+                for (int e = 0; e < 4; ++e) o.perm[e] = d4_index(e >> 1, e & 1, s0.inv, s1.inv);
+                note_payload();
+                f_used = false;
+            } else if (s0.reg || s1.reg) {
+                const Src &r = s0.reg ? s0 : s1;
+                const Src &u = s0.reg ? s1 : s0;
+                flush_nondiag(r.p);
+                HostOp &o = emit(OP_D2RU);
+                o.hdr.a = (uint8_t)r.p;
+                o.hdr.sa = u.code;
+                o.pk = PK_D4;
+                o.gate = g.src;
+                for (int e = 0; e < 4; ++e) {
+                    const int ub = e >> 1, rb = e & 1;
+                    o.perm[e] = s0.reg ? d4_index(rb, ub, r.inv, u.inv) : d4_index(ub, rb, u.inv, r.inv);
+                }
+                note_payload();
+                f_used = false;
+            } else {
+                HostOp &o = emit(OP_UD2);
+                o.hdr.sa = s0.code;
+                o.hdr.sb = s1.code;
+                o.pk = PK_D4;
+                o.gate = g.src;
+                for (int e = 0; e < 4; ++e) o.perm[e] = d4_index(e >> 1, e & 1, s0.inv, s1.inv);
+                note_payload();
+                f_used = true;
+            }
+            break;
+        }
+        case G_MARK: {
+            for (int p = 0; p < opt.R; ++p) flush_nondiag(p);
+            uint64_t qmask = 0;
+            uint32_t lm = 0;
+            for (int l = 0; l < k; ++l) {
+                qmask |= bit(q[l]);
+                if ((g.index >> q[l]) & 1) lm |= 1u << l;
+            }
+            const uint32_t phys = lm ^ xmask;
+            int t = 0, j = 0;
+            for (int s = 0; s < w; ++s) if ((phys >> thr_label[s]) & 1) t |= 1 << s;
+            for (int p = 0; p < opt.R; ++p) if ((phys >> reg_label[p]) & 1) j |= 1 << p;
+            HostOp &o = emit(OP_MARK);
+            o.hdr.a = (uint8_t)j;
+            o.hdr.b = (uint8_t)t;
+            o.hdr.data = g.index & ~qmask;
+            break;
+        }
+        case G_X: {
+            const Src s = src_of(g.q0);
+            if (s.reg) {
+                compose(s.p, Factor{FK_X, false, -1}, PC_A, true);
+            } else {
+                xmask ^= 1u << label_of[g.q0];
+                cur_layout = -1;
+                ++P.n_relabel;
+            }
+            break;
+        }
+        case G_Y: {
+            const Src s = src_of(g.q0);
+            if (s.reg) {
+                compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_A, false);
+            } else {
+                // Y = X diag(i, -i): the phases first, then the label flip
+                HostOp &o = emit(OP_UD1);
+                o.hdr.sa = s.code;
+                o.pk = PK_DIAG2;
+                o.factors.push_back(Factor{FK_YDIAG, s.inv != 0, -1});
+                note_payload();
+                f_used = true;
+                xmask ^= 1u << label_of[g.q0];
+                cur_layout = -1;
+                ++P.n_relabel;
+            }
+            break;
+        }
+        case G_H: {
+            const Src s = src_of(g.q0);
+            compose(s.p, Factor{FK_H, s.inv != 0, -1}, s.inv ? PC_G : PC_H, false);
+            break;
+        }
+        case G_DENSE1: {
+            const Src s = src_of(g.q0);
+            compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_G, false);
+            break;
+        }
+        case G_CX: {
+            const Src t = src_of(g.q1), c = src_of(g.q0);
+            flush(t.p);
+            if (c.reg) {
+                flush_nondiag(c.p);
+                HostOp &o = emit(OP_CXR);
+                o.hdr.a = (uint8_t)t.p;
+                o.hdr.b = (uint8_t)c.p;
+            } else if ((c.code & ~SRC_POS_MASK) == SRC_TILE) {
+                HostOp &o = emit(OP_CXT);
+                o.hdr.a = (uint8_t)t.p;
+                o.hdr.sa = c.code;
+            } else {
+                HostOp &o = emit(OP_CXU);
+                o.hdr.a = (uint8_t)t.p;
+                o.hdr.sa = c.code;
+            }
+            // control acting on bit value 0 of the physical position:
+            // CX_inverted = X_target * CX
+            if (c.inv) compose(t.p, Factor{FK_X, false, -1}, PC_A, true);
+            break;
+        }
+        case G_SWAP: {
+            const int l0 = label_of[g.q0], l1 = label_of[g.q1];
+            const int r0 = pos_reg[l0], r1 = pos_reg[l1], t0 = pos_thr[l0], t1 = pos_thr[l1];
+            if (r0 >= 0) reg_label[r0] = l1; else thr_label[t0] = l1;
+            if (r1 >= 0) reg_label[r1] = l0; else thr_label[t1] = l0;
+            pos_reg[l0] = r1; pos_thr[l0] = t1;
+            pos_reg[l1] = r0; pos_thr[l1] = t0;
+            const uint32_t b0 = (xmask >> l0) & 1, b1 = (xmask >> l1) & 1;
+            if (b0 != b1) xmask ^= (1u << l0) | (1u << l1);
+            cur_layout = -1;
+            ++P.n_relabel;
+            break;
+        }
+        default:
+            --P.gates_applied;
+            break;
+        }
+    }
+};
+
+}  // namespace
 
 Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt) {
     Plan P;
@@ -425,9 +617,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
                 ConstBlock b;
                 b.kind = ck;
                 b.gate = g.src;
-                b.scale = 1.0;
                 b.off = P.cstride;
-                b.swap_bits = false;
                 P.cblocks.push_back(b);
                 P.cstride += (uint64_t)cnt;
                 return b.off;
@@ -442,7 +632,6 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             case G_SWAP: so.code = SOP_SWAP; break;
             case G_H: so.code = SOP_DENSE1; so.data = cblock(CK_HMAT, 8); break;
             case G_DENSE1: so.code = SOP_DENSE1; so.data = cblock(CK_DENSE1, 8); break;
-            case G_DENSE2: so.code = SOP_DENSE2; so.data = cblock(CK_DENSE2, 32); break;
             default: continue;
             }
             P.sops.push_back(so);
@@ -471,19 +660,16 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     std::vector<std::vector<int>> groups = form_passes(cg, order, n, k, opt, c, qsets);
     if (groups.empty() && generate) {
         groups.emplace_back();
-        uint64_t Q = 0;
-        for (int qq = 0; qq < k; ++qq) Q |= bit(qq);
-        qsets.push_back(Q);
+        qsets.push_back(bit(k) - 1);
     }
 
     for (size_t pi = 0; pi < groups.size(); ++pi) {
         PassCtx X(opt, P, cg, n, k, w);
         const uint64_t Q = qsets[pi];
-        int l = 0;
-        for (int qq = 0; qq < 64; ++qq) X.local_of[qq] = -1;
+        for (int qq = 0; qq < 64; ++qq) X.label_of[qq] = -1;
         std::memset(X.q, 0, sizeof X.q);
-        for (int qq = 0; qq < n; ++qq)
-            if ((Q >> qq) & 1) { X.q[l] = (uint8_t)qq; X.local_of[qq] = l; ++l; }
+        for (int qq = 0, l = 0; qq < n; ++qq)
+            if ((Q >> qq) & 1) { X.q[l] = (uint8_t)qq; X.label_of[qq] = l; ++l; }
 
         DevPass dp;
         std::memset(&dp, 0, sizeof dp);
@@ -493,20 +679,26 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         std::memcpy(dp.q, X.q, sizeof dp.q);
         dp.op_begin = (int)P.ops.size();
         dp.layout_begin = (int)P.layouts.size();
-        X.pass_layout_begin = dp.layout_begin;
+        X.layout_begin = dp.layout_begin;
 
         std::vector<int> rem = groups[pi];
-        const uint64_t U = X.U_mask();
+        const uint64_t U = X.U_labels();
         const int ru = opt.R - opt.v;
+        auto labels_of = [&](uint64_t qmask) {
+            uint64_t r = 0;
+            for (int qq = 0; qq < n; ++qq)
+                if ((qmask >> qq) & 1) r |= bit(X.label_of[qq]);
+            return r;
+        };
 
-        // initial (load) layout: register bits from U, first-needed first
+        // load layout: register labels from U, first-needed first
         uint64_t S0 = 0;
         {
             Blocker blk;
             for (int gi : rem) {
                 const CGate &g = cg[gi];
                 if (blk.conflicts(g)) { blk.defer(g); continue; }
-                const uint64_t nl = X.to_local(g.need) & U;
+                const uint64_t nl = labels_of(X.rneed_of(g)) & U;
                 if (popc(S0 | nl) <= ru) S0 |= nl;
                 else blk.defer(g);
                 if (popc(S0) == ru) break;
@@ -514,22 +706,16 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             for (int lb = 0; lb < k && popc(S0) < ru; ++lb)
                 if ((U >> lb) & 1) S0 |= bit(lb);
         }
-        DevLayout L0 = X.storable(S0);
-        X.add_layout(L0);
-        X.set_current(L0);
+        X.storable_state(S0);
+        X.layout_index();
 
-        int h_count = 0;
-        int first_cb = -1;
         while (true) {
-            // absorb every gate that can run in the current layout
-            const uint64_t regs = X.reg_mask(X.cur);
             Blocker blk;
             std::vector<int> left;
             for (int gi : rem) {
                 const CGate &g = cg[gi];
-                if (!blk.conflicts(g) && (X.to_local(g.need) & ~regs) == 0) {
-                    const int cb = X.emit(g, h_count);
-                    if (cb >= 0 && first_cb < 0) first_cb = cb;
+                if (!blk.conflicts(g) && X.absorbable(g)) {
+                    X.apply(g);
                 } else {
                     left.push_back(gi);
                     blk.defer(g);
@@ -537,54 +723,61 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             }
             rem.swap(left);
             if (rem.empty()) break;
-            // next register set: needs of the next gates, in order
+            // next register labels: needs of the next gates, in order
+            const uint64_t regs = X.reg_labels();
             uint64_t S = 0;
             bool all_fit = true;
             Blocker b2;
             for (int gi : rem) {
                 const CGate &g = cg[gi];
                 if (b2.conflicts(g)) { b2.defer(g); all_fit = false; continue; }
-                const uint64_t nl = X.to_local(g.need);
+                const uint64_t nl = labels_of(X.rneed_of(g));
                 if (popc(S | nl) <= opt.R) S |= nl;
                 else { b2.defer(g); all_fit = false; }
             }
-            DevLayout NL;
-            const uint64_t V = X.V_mask();
+            X.flush_all();
+            const int wl = X.layout_index();
+            const uint64_t V = opt.v ? 1ull : 0ull;
             if (all_fit && (S & ~(U | V)) == 0 && popc(S | V) <= opt.R) {
                 uint64_t su = S & U;
                 for (int lb = 0; lb < k && popc(su) < ru; ++lb)   // keep current registers
                     if (((U & regs) >> lb) & 1) su |= bit(lb);
                 for (int lb = 0; lb < k && popc(su) < ru; ++lb)
                     if ((U >> lb) & 1) su |= bit(lb);
-                NL = X.storable(su);
+                X.storable_state(su);
             } else {
                 for (int lb = 0; lb < k && popc(S) < opt.R; ++lb)
                     if ((regs >> lb) & 1) S |= bit(lb);
                 for (int lb = 0; lb < k && popc(S) < opt.R; ++lb) S |= bit(lb);
-                NL = X.general(S);
+                X.general_state(S);
             }
-            DevOp ex;
-            std::memset(&ex, 0, sizeof ex);
-            ex.code = OP_EXCH;
-            ex.a = (uint8_t)X.add_layout(NL);
-            P.ops.push_back(ex);
+            const int rl = X.layout_index();
+            HostOp &ex = X.emit(OP_EXCH);
+            ex.hdr.a = (uint8_t)wl;
+            ex.hdr.b = (uint8_t)rl;
             ++P.n_exch;
-            X.set_current(NL);
         }
-        if (!X.is_storable(X.cur)) {
-            uint64_t su = X.reg_mask(X.cur) & U;
+        X.flush_all();
+        if (!X.is_storable()) {
+            const int wl = X.layout_index();
+            uint64_t su = X.reg_labels() & U;
+            while (popc(su) > ru) su &= su - 1;
             for (int lb = 0; lb < k && popc(su) < ru; ++lb)
                 if ((U >> lb) & 1) su |= bit(lb);
-            while (popc(su) > ru) su &= su - 1;
-            DevLayout NL = X.storable(su);
-            DevOp ex;
-            std::memset(&ex, 0, sizeof ex);
-            ex.code = OP_EXCH;
-            ex.a = (uint8_t)X.add_layout(NL);
-            P.ops.push_back(ex);
+            X.storable_state(su);
+            const int rl = X.layout_index();
+            HostOp &ex = X.emit(OP_EXCH);
+            ex.hdr.a = (uint8_t)wl;
+            ex.hdr.b = (uint8_t)rl;
             ++P.n_exch;
-            X.set_current(NL);
         }
+        dp.store_layout = X.layout_index();
+        // In-place safety: without an exchange, nothing orders one wave's loads
+        // before another wave's stores to the same tile.
+        bool exch_in_pass = false;
+        for (size_t oi = (size_t)dp.op_begin; oi < P.ops.size(); ++oi)
+            if (P.ops[oi].hdr.code == OP_EXCH) exch_in_pass = true;
+        if (!exch_in_pass && dp.store_layout != 0) dp.flags |= PASS_SYNC_STORE;
 
         if (pi == 0 && generate) {
             dp.flags |= PASS_GENERATE;
@@ -592,18 +785,16 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             dp.gen_mask = gen_mask;
             dp.gen_scale = hadamard_magnitude(popc(gen_mask));
         }
-        if (h_count > 0) {
-            const double s = hadamard_magnitude(h_count);
-            if (first_cb >= 0) {
-                P.cblocks[first_cb].scale *= s;
+        if (X.h_count > 0) {
+            const double s = hadamard_magnitude(X.h_count);
+            if (X.first_payload >= 0) {
+                P.ops[X.first_payload].scale *= s;
             } else if (dp.flags & PASS_GENERATE) {
                 dp.gen_scale *= s;
             } else {
-                DevOp so;
-                std::memset(&so, 0, sizeof so);
-                so.code = OP_SCALE;
-                so.data = X.add_const(CK_SCALE, -1, 1, false, s);
-                P.ops.push_back(so);
+                HostOp &so = X.emit(OP_SCALE);
+                so.pk = PK_SCALE;
+                so.scale = s;
             }
         }
         dp.op_end = (int)P.ops.size();
@@ -615,45 +806,125 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
 // ---------------------------------------------------------------------------
 // Gate constants (FP64, host libm), the product's own table.
 
-static void gate_d1(int kind, double t, double *d) {
+static void gate_mat2(int kind, double t, cd m[4]) {
     const double r = 0.70710678118654752440;
-    double v[4] = {1, 0, 1, 0};
+    const cd I(0.0, 1.0);
+    m[0] = 1.0; m[1] = 0.0; m[2] = 0.0; m[3] = 1.0;
     switch (kind) {
-    case SV_GATE_Z: v[2] = -1; break;
-    case SV_GATE_S: v[2] = 0; v[3] = 1; break;
-    case SV_GATE_SDG: v[2] = 0; v[3] = -1; break;
-    case SV_GATE_T: v[2] = r; v[3] = r; break;
-    case SV_GATE_TDG: v[2] = r; v[3] = -r; break;
-    case SV_GATE_RZ: {
+    case SV_GATE_X: m[0] = 0.0; m[1] = 1.0; m[2] = 1.0; m[3] = 0.0; break;
+    case SV_GATE_Y: m[0] = 0.0; m[1] = -I; m[2] = I; m[3] = 0.0; break;
+    case SV_GATE_Z: m[3] = -1.0; break;
+    case SV_GATE_H: m[0] = r; m[1] = r; m[2] = r; m[3] = -r; break;
+    case SV_GATE_S: m[3] = I; break;
+    case SV_GATE_SDG: m[3] = -I; break;
+    case SV_GATE_T: m[3] = cd(r, r); break;
+    case SV_GATE_TDG: m[3] = cd(r, -r); break;
+    case SV_GATE_RX: {
         const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
-        v[0] = c; v[1] = -s; v[2] = c; v[3] = s;
+        m[0] = c; m[1] = cd(0.0, -s); m[2] = cd(0.0, -s); m[3] = c;
         break;
     }
-    case SV_GATE_P: v[2] = std::cos(t); v[3] = std::sin(t); break;
+    case SV_GATE_RY: {
+        const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+        m[0] = c; m[1] = -s; m[2] = s; m[3] = c;
+        break;
+    }
+    case SV_GATE_RZ: {
+        const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
+        m[0] = cd(c, -s); m[3] = cd(c, s);
+        break;
+    }
+    case SV_GATE_P: m[3] = cd(std::cos(t), std::sin(t)); break;
     default: break;
     }
-    std::memcpy(d, v, sizeof v);
 }
 
-static void gate_d2(int kind, double t, double *d) {
-    double v[8] = {1, 0, 1, 0, 1, 0, 1, 0};
-    if (kind == SV_GATE_CZ) v[6] = -1;
-    else if (kind == SV_GATE_CPHASE) { v[6] = std::cos(t); v[7] = std::sin(t); }
-    std::memcpy(d, v, sizeof v);
+static void gate_diag4(int kind, double t, cd d[4]) {
+    d[0] = d[1] = d[2] = d[3] = 1.0;
+    if (kind == SV_GATE_CZ) d[3] = -1.0;
+    else if (kind == SV_GATE_CPHASE) d[3] = cd(std::cos(t), std::sin(t));
 }
 
-static void gate_dense1(int kind, double t, double *m) {
-    const double c = std::cos(0.5 * t), s = std::sin(0.5 * t);
-    double v[8] = {0};
-    if (kind == SV_GATE_RX) {         // [[c, -is], [-is, c]]
-        v[0] = c; v[3] = -s; v[5] = -s; v[6] = c;
-    } else if (kind == SV_GATE_RY) {  // [[c, -s], [s, c]]
-        v[0] = c; v[2] = -s; v[4] = s; v[6] = c;
-    } else if (kind == SV_GATE_H) {
-        const double r = 0.70710678118654752440;
-        v[0] = r; v[2] = r; v[4] = r; v[6] = -r;
+static double gate_angle(const sv_gate &g, const double *params, size_t n_params, int b) {
+    return g.param >= 0 ? params[(size_t)b * n_params + (size_t)g.param] : g.angle;
+}
+
+static void factor_mat(const Factor &f, const sv_gate *gates, const double *params,
+                       size_t n_params, int b, cd m[4]) {
+    const double r = 0.70710678118654752440;
+    switch (f.kind) {
+    case FK_GATE: {
+        const sv_gate &g = gates[f.gate];
+        gate_mat2(g.kind, gate_angle(g, params, n_params, b), m);
+        break;
     }
-    std::memcpy(m, v, sizeof v);
+    case FK_X: m[0] = 0.0; m[1] = 1.0; m[2] = 1.0; m[3] = 0.0; break;
+    case FK_YDIAG: m[0] = cd(0.0, 1.0); m[1] = 0.0; m[2] = 0.0; m[3] = cd(0.0, -1.0); break;
+    case FK_H: m[0] = r; m[1] = r; m[2] = r; m[3] = -r; break;
+    }
+    if (f.conj_x) {  // X M X: swap rows and columns
+        std::swap(m[0], m[3]);
+        std::swap(m[1], m[2]);
+    }
+}
+
+template <typename R>
+static void write_payload(DevOp &rec, const double *v, int count) {
+    R *dst = reinterpret_cast<R *>(rec.payload);
+    for (int i = 0; i < count; ++i) dst[i] = (R)v[i];
+}
+
+void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, size_t n_params,
+                     int batch, bool f32, void *out) {
+    DevOp *o = static_cast<DevOp *>(out);
+    const size_t nops = p.ops.size();
+    for (int b = 0; b < batch; ++b) {
+        for (size_t i = 0; i < nops; ++i) {
+            const HostOp &h = p.ops[i];
+            DevOp rec = h.hdr;
+            std::memset(rec.payload, 0, sizeof rec.payload);
+            double v[8] = {0};
+            int count = 0;
+            switch (h.pk) {
+            case PK_MAT2:
+            case PK_DIAG2: {
+                cd M[4] = {1.0, 0.0, 0.0, 1.0};
+                for (const Factor &f : h.factors) {
+                    cd F[4];
+                    factor_mat(f, gates, params, n_params, b, F);
+                    const cd N[4] = {F[0] * M[0] + F[1] * M[2], F[0] * M[1] + F[1] * M[3],
+                                     F[2] * M[0] + F[3] * M[2], F[2] * M[1] + F[3] * M[3]};
+                    std::copy(N, N + 4, M);
+                }
+                if (h.pk == PK_MAT2) {
+                    for (int e = 0; e < 4; ++e) { v[2 * e] = M[e].real() * h.scale; v[2 * e + 1] = M[e].imag() * h.scale; }
+                    count = 8;
+                } else {
+                    v[0] = M[0].real() * h.scale; v[1] = M[0].imag() * h.scale;
+                    v[2] = M[3].real() * h.scale; v[3] = M[3].imag() * h.scale;
+                    count = 4;
+                }
+                break;
+            }
+            case PK_D4: {
+                const sv_gate &g = gates[h.gate];
+                cd d[4];
+                gate_diag4(g.kind, gate_angle(g, params, n_params, b), d);
+                for (int e = 0; e < 4; ++e) {
+                    v[2 * e] = d[h.perm[e]].real() * h.scale;
+                    v[2 * e + 1] = d[h.perm[e]].imag() * h.scale;
+                }
+                count = 8;
+                break;
+            }
+            case PK_SCALE: v[0] = h.scale; count = 1; break;
+            default: break;
+            }
+            if (f32) write_payload<float>(rec, v, count);
+            else write_payload<double>(rec, v, count);
+            o[(size_t)b * nops + i] = rec;
+        }
+    }
 }
 
 void materialize_consts(const Plan &p, const sv_gate *gates, const double *params,
@@ -663,24 +934,21 @@ void materialize_consts(const Plan &p, const sv_gate *gates, const double *param
         std::fill(row.begin(), row.end(), 0.0);
         for (const ConstBlock &cb : p.cblocks) {
             double *d = row.data() + cb.off;
-            double t = 0.0;
-            int kind = -1;
-            if (cb.gate >= 0) {
-                const sv_gate &g = gates[cb.gate];
-                kind = g.kind;
-                t = g.param >= 0 ? params[(size_t)b * n_params + (size_t)g.param] : g.angle;
+            const sv_gate &g = gates[cb.gate];
+            const double t = gate_angle(g, params, n_params, b);
+            if (cb.kind == CK_D2) {
+                cd e[4];
+                gate_diag4(g.kind, t, e);
+                for (int i = 0; i < 4; ++i) { d[2 * i] = e[i].real(); d[2 * i + 1] = e[i].imag(); }
+            } else {
+                cd m[4];
+                gate_mat2(cb.kind == CK_HMAT ? (int)SV_GATE_H : g.kind, t, m);
+                if (cb.kind == CK_D1) {
+                    d[0] = m[0].real(); d[1] = m[0].imag(); d[2] = m[3].real(); d[3] = m[3].imag();
+                } else {
+                    for (int i = 0; i < 4; ++i) { d[2 * i] = m[i].real(); d[2 * i + 1] = m[i].imag(); }
+                }
             }
-            int cnt = 0;
-            switch (cb.kind) {
-            case CK_D1: gate_d1(kind, t, d); cnt = 4; break;
-            case CK_D2: gate_d2(kind, t, d); cnt = 8; break;
-            case CK_DENSE1: gate_dense1(kind, t, d); cnt = 8; break;
-            case CK_HMAT: gate_dense1(SV_GATE_H, 0.0, d); cnt = 8; break;
-            case CK_SCALE: d[0] = 1.0; cnt = 1; break;
-            case CK_DENSE2: cnt = 32; break;  // no 4x4 dense kind in this gate set yet
-            }
-            if (cb.kind == CK_D2 && cb.swap_bits) std::swap_ranges(d + 2, d + 4, d + 4);
-            for (int i = 0; i < cnt; ++i) d[i] *= cb.scale;
         }
         if (f32) {
             float *o = static_cast<float *>(out) + (size_t)b * p.cstride;

@@ -17,39 +17,60 @@ namespace sv {
 //   X/Y/CX/SWAP  monomial: one non-zero per row, a permutation with phases
 //                (the DAX entry restricted to the gate's own 2^k x 2^k matrix)
 //   H       a Hadamard: one magnitude and on-demand signs (RH)
-//   DENSE1/DENSE2  general 2x2 / 4x4
+//   DENSE1  general 2x2
 enum GClass : uint8_t {
-    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1, G_DENSE2
+    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1
 };
 
 struct CGate {
-    GClass cls;
+    GClass cls = G_NOP;
     int q0 = -1, q1 = -1;   // 2-qubit: q0 is the high local bit (CX: control)
     int src = -1;           // index in the caller's gate list
     uint64_t index = 0;     // MARK basis index
     uint64_t support = 0;   // qubit mask the gate acts on
-    uint64_t need = 0;      // qubits that must be register bits to apply it
+    uint64_t qneed = 0;     // qubits that must be tile qubits of its pass
+    uint64_t rneed = 0;     // qubits that must sit in register bits when applied
     bool diag = false;
 };
 
-// Constant block of one op: `count` reals per batch entry at offset `off`.
-enum ConstKind : uint8_t { CK_D1 = 1, CK_D2, CK_DENSE1, CK_DENSE2, CK_SCALE, CK_HMAT };
+// Small-path constant block: `count` reals per batch entry at offset `off`.
+enum ConstKind : uint8_t { CK_D1 = 1, CK_D2, CK_DENSE1, CK_HMAT };
 struct ConstBlock {
     ConstKind kind;
-    int gate;          // source gate index (for its kind / angle)
-    double scale;      // real factor folded into the block (Hadamard magnitude)
-    uint64_t off;      // offset in reals within a batch entry
-    bool swap_bits;    // DENSE2 / D2 stored with its two local bits exchanged
+    int gate;
+    uint64_t off;
+};
+
+// A 2x2 factor of a composed register-bit operation; conj_x: the factor acts
+// on a label whose XOR bit is set, so its physical matrix is X G X.
+enum FactorKind : uint8_t { FK_GATE = 0, FK_X, FK_YDIAG, FK_H };
+struct Factor {
+    uint8_t kind;
+    bool conj_x;
+    int gate;
+};
+
+enum PayloadKind : uint8_t { PK_NONE = 0, PK_MAT2, PK_DIAG2, PK_D4, PK_SCALE };
+
+// A pass operation plus the recipe of its payload (materialized per batch
+// entry from the gates' angles).
+struct HostOp {
+    DevOp hdr{};
+    uint8_t pk = PK_NONE;
+    std::vector<Factor> factors;   // PK_MAT2 / PK_DIAG2: product, first factor applied first
+    int gate = -1;                 // PK_D4: the 2-qubit diagonal gate
+    uint8_t perm[4] = {0, 1, 2, 3};  // PK_D4: payload entry e takes the gate's diagonal entry perm[e]
+    double scale = 1.0;
 };
 
 struct PlanOptions {
     int R = 4;            // register bits per thread
-    int v = 0;            // vector bits (complex64: 1, local bit 0 in register 0)
+    int v = 0;            // vector bits (complex64: 1, label 0 in register 0 for 16-byte I/O)
     int m = 3;            // swizzle width (3 for 16-byte slots, 4 for 8-byte)
     int c = 6;            // lowest qubits always in the tile
     int w_max = 8;        // thread bits of a full workgroup
     bool fuse = true;     // false: one pass per gate
-    int max_dense = 1 << 20;  // dense ops (DENSE1/DENSE2) per pass
+    int max_dense = 1 << 20;  // dense register operations (DENSE1) per pass
     bool gen_h = true;    // generate leading Hadamards of a basis state
     bool basis_known = false;
     uint64_t basis_j = 0;
@@ -62,13 +83,14 @@ struct Plan {
     int n = 0;
     std::vector<DevPass> passes;
     std::vector<DevLayout> layouts;
-    std::vector<DevOp> ops;
+    std::vector<HostOp> ops;
     std::vector<SmallOp> sops;
-    std::vector<ConstBlock> cblocks;
-    uint64_t cstride = 0;     // reals per batch entry
+    std::vector<ConstBlock> cblocks;   // small path
+    uint64_t cstride = 0;              // small path: reals per batch entry
     int64_t n_exch = 0;
     int64_t n_gen_h = 0;
     int64_t gates_applied = 0;
+    int64_t n_relabel = 0;             // permutation gates absorbed into layouts
 };
 
 // Structural classification of a validated gate (independent of the angle).
@@ -81,7 +103,11 @@ bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params
 // Build the plan. Gates must be validated.
 Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt);
 
-// Fill the constant table [batch][cstride] (double or float).
+// Tiled path: write [batch][ops.size()] DevOp records with their payloads.
+void materialize_ops(const Plan &p, const sv_gate *gates, const double *params,
+                     size_t n_params, int batch, bool f32, void *out);
+
+// Small path: fill the constant table [batch][cstride] (double or float).
 void materialize_consts(const Plan &p, const sv_gate *gates, const double *params,
                         size_t n_params, int batch, bool f32, void *out);
 

@@ -212,7 +212,7 @@ class StateVector:
     def plan_stats(self) -> dict:
         out = np.zeros(8, dtype=np.int64)
         _check(lib().sv_plan_stats(self._h, _ptr(out)))
-        keys = ("passes", "exchanges", "gates", "generated_h", "launches", "hbm_bytes")
+        keys = ("passes", "exchanges", "gates", "generated_h", "launches", "hbm_bytes", "relabels")
         return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def profile_read(self):
@@ -230,14 +230,19 @@ class StateVector:
 PASS_DTYPE = np.dtype([("k", "<i4"), ("w", "<i4"), ("op_begin", "<i4"), ("op_end", "<i4"),
                        ("layout_begin", "<i4"), ("flags", "<u4"), ("tiles", "<u8"),
                        ("gen_j", "<u8"), ("gen_mask", "<u8"), ("gen_scale", "<f8"),
-                       ("q", "u1", (32,)), ("pad", "u1", (8,))])
-LAYOUT_DTYPE = np.dtype([("reg_local", "u1", (8,)), ("thr_local", "u1", (8,))])
+                       ("store_layout", "<i4"), ("q", "u1", (28,)), ("pad", "u1", (8,))])
+LAYOUT_DTYPE = np.dtype([("thr_goff", "<u8", (8,)), ("reg_goff", "<u8", (8,)),
+                         ("thr_slot", "<u4", (8,)), ("reg_slot", "<u4", (8,)),
+                         ("goff_xor", "<u8"), ("slot_xor", "<u4"), ("flags", "<u4"),
+                         ("reg_local", "u1", (8,)), ("thr_local", "u1", (8,)),
+                         ("xor_local", "<u4"), ("pad0", "<u4"), ("reg_goff_xor", "<u8"),
+                         ("pad", "u1", (16,))])
 OP_DTYPE = np.dtype([("code", "u1"), ("a", "u1"), ("b", "u1"), ("sa", "u1"), ("sb", "u1"),
-                     ("pad", "u1", (3,)), ("data", "<u8")])
+                     ("pad", "u1", (3,)), ("data", "<u8"), ("payload", "<f8", (8,))])
 SOP_DTYPE = np.dtype([("code", "u1"), ("q0", "u1"), ("q1", "u1"), ("pad", "u1", (5,)),
                       ("data", "<u8")])
-assert PASS_DTYPE.itemsize == 96 and LAYOUT_DTYPE.itemsize == 16
-assert OP_DTYPE.itemsize == 16 and SOP_DTYPE.itemsize == 16
+assert PASS_DTYPE.itemsize == 96 and LAYOUT_DTYPE.itemsize == 256
+assert OP_DTYPE.itemsize == 80 and SOP_DTYPE.itemsize == 16
 
 
 def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] = None,
@@ -262,7 +267,7 @@ def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] 
     h = buf[:256].view(np.int64)
     out = {"small": bool(h[0]), "k": int(h[9]), "w": int(h[10]), "R": int(h[11]), "m": int(h[12]),
            "exchanges": int(h[6]), "generated_h": int(h[7]), "gates": int(h[8]),
-           "hbm_bytes": int(h[18]), "cstride": int(h[5])}
+           "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19])}
 
     def take(off, count, dt_):
         return buf[off: off + count * dt_.itemsize].view(dt_).copy()

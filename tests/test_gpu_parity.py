@@ -277,3 +277,18 @@ def test_plain_method_at_scale_n28(P):
         sv.apply(layer)
         amp = sv.amplitudes(idx)
     assert np.max(np.abs(amp - ref[idx])) <= 1e-12
+
+
+def test_relabel_passes_race_free_n27(P):
+    """Permutation gates on qubits held by thread bits move amplitudes between
+    waves at store time; repeated runs must agree with the oracle exactly."""
+    n = 27
+    gates = []
+    for q in range(6, n):
+        gates.append(synth.Gate("X" if q % 2 else "Y", q))
+        gates.append(synth.Gate("RY", q % 6, -1, 0.1 * q))
+    ref = O.simulate(n, gates, psi0=None)
+    for _ in range(3):
+        got, st = run(P, n, gates)
+        assert st["relabels"] > 0
+        assert maxdiff(got, ref) <= 1e-12

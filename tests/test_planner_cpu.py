@@ -150,3 +150,16 @@ def test_large_plan_statistics():
     # every gate of a pass lies on its tile qubits or is diagonal
     assert 30 < npass < 200
     assert plan["k"] == 12 and plan["w"] == 8
+
+
+def test_relabel_only_pass_orders_loads_before_stores():
+    # X/Y on tile qubits held by thread bits are applied by relabelling the
+    # store addresses; with no LDS exchange in the pass, the kernel needs a
+    # barrier between the tile's loads and its permuted stores.
+    n = 16
+    gates = [synth.Gate("X", 11), synth.Gate("Y", 10)]
+    plan = P.debug_plan(n, gates)
+    assert plan["relabels"] >= 1 and plan["exchanges"] == 0
+    assert all(int(p["flags"]) & 2 for p in plan["passes"] if int(p["store_layout"]) != 0)
+    plain = P.debug_plan(n, [synth.Gate("Z", 11)])
+    assert not any(int(p["flags"]) & 2 for p in plain["passes"])
