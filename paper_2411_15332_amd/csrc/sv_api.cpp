@@ -84,8 +84,11 @@ struct sv_state_s {
     uint64_t *d_idx = nullptr;
     size_t d_idx_cap = 0;
 
-    // adjoint: second state
-    void *d_lambda = nullptr;
+    // adjoint: work buffer of 2 * batch states (psi then lambda) and gradients
+    void *d_work = nullptr;
+    size_t d_work_cap = 0;
+    double *d_grad = nullptr;
+    size_t d_grad_cap = 0;
 
     int64_t stats[8] = {0};
 
@@ -199,11 +202,11 @@ sv_status check_handle(sv_state s) {
 }
 
 // Upload plan and launch it on the handle's stream, on `state`.
-sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gates,
+sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const sv_gate *gates,
                    const double *params, size_t n_params) {
     const bool f32 = s->dt == SV_C64;
     const size_t real_bytes = f32 ? 4 : 8;
-    const Layout L = plan_sections(p, s->batch, real_bytes);
+    const Layout L = plan_sections(p, batch, real_bytes);
     if (s->upload_pending) {
         SV_HIP(hipEventSynchronize(s->upload_done), "wait for previous plan upload");
         s->upload_pending = false;
@@ -217,7 +220,7 @@ sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gat
         st = ensure_device_buf(&s->d_plan, &s->d_cap, L.total, "hipMalloc(plan)");
         if (st != SV_OK) return st;
     }
-    serialize_plan(p, L, gates, params, n_params, s->batch, f32, static_cast<char *>(s->h_stage));
+    serialize_plan(p, L, gates, params, n_params, batch, f32, static_cast<char *>(s->h_stage));
     SV_HIP(hipMemcpyAsync(s->d_plan, s->h_stage, L.total, hipMemcpyHostToDevice, s->stream),
            "hipMemcpyAsync(plan)");
     if (!s->upload_done) SV_HIP(hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming), "hipEventCreate");
@@ -226,7 +229,7 @@ sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gat
 
     char *d = static_cast<char *>(s->d_plan);
     const uint64_t N = 1ull << s->n;
-    const double io_bytes = 2.0 * (double)N * (double)s->amp_bytes * s->batch;
+    const double io_bytes = 2.0 * (double)N * (double)s->amp_bytes * batch;
     if (p.small) {
         if (p.sops.empty()) return SV_OK;
         hipEvent_t ea = nullptr, eb = nullptr;
@@ -235,7 +238,7 @@ sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gat
             eb = get_event(s);
             if (ea) hipEventRecord(ea, s->stream);
         }
-        SV_HIP(launch_small((int)s->dt, state, s->n, s->batch,
+        SV_HIP(launch_small((int)s->dt, state, s->n, batch,
                             reinterpret_cast<const SmallOp *>(d + L.sops), (int)p.sops.size(),
                             d + L.consts, p.cstride, s->stream),
                "launch k_small");
@@ -253,7 +256,7 @@ sv_status run_plan(sv_state_s *s, void *state, const Plan &p, const sv_gate *gat
             eb = get_event(s);
             if (ea) hipEventRecord(ea, s->stream);
         }
-        SV_HIP(launch_pass((int)s->dt, state, N, s->batch, dpass, (int)i, p.passes[i],
+        SV_HIP(launch_pass((int)s->dt, state, N, batch, dpass, (int)i, p.passes[i],
                            reinterpret_cast<const DevLayout *>(d + L.layouts),
                            reinterpret_cast<const DevOp *>(d + L.ops), (uint64_t)p.ops.size(),
                            s->stream),
@@ -351,7 +354,8 @@ sv_status sv_free(sv_state s) {
     for (hipEvent_t ev : s->event_pool) hipEventDestroy(ev);
     if (s->upload_done) hipEventDestroy(s->upload_done);
     if (s->owned && s->buf) hipFree(s->buf);
-    if (s->d_lambda) hipFree(s->d_lambda);
+    if (s->d_work) hipFree(s->d_work);
+    if (s->d_grad) hipFree(s->d_grad);
     if (s->d_plan) hipFree(s->d_plan);
     if (s->d_red) hipFree(s->d_red);
     if (s->d_idx) hipFree(s->d_idx);
@@ -396,7 +400,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
         return fail(SV_EINVAL, "%s", err.c_str());
     if (n_gates == 0) return SV_OK;
     Plan p = build_plan(s->n, gates, n_gates, plan_options(s));
-    st = run_plan(s, s->buf, p, gates, params, n_params);
+    st = run_plan(s, s->buf, s->batch, p, gates, params, n_params);
     if (st != SV_OK) return st;
     s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
     s->stats[1] = p.n_exch;
@@ -543,10 +547,120 @@ sv_status sv_profile_read(sv_state s, double *total_ms, int64_t *launches, doubl
 
 sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, const double *params,
                               size_t n_params, int qubit, double *expect, double *grad) {
-    (void)gates; (void)n_gates; (void)params; (void)n_params; (void)qubit; (void)expect; (void)grad;
     sv_status st = check_handle(s);
     if (st != SV_OK) return st;
-    return fail(SV_EUNSUPPORTED, "adjoint backward not built yet");
+    if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
+    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+    if (n_params && !grad) return fail(SV_EINVAL, "grad is NULL");
+    std::string err;
+    if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
+        return fail(SV_EINVAL, "%s", err.c_str());
+    for (size_t i = 0; i < n_gates; ++i) {
+        const int k = gates[i].kind;
+        if (gates[i].param >= 0 && k != SV_GATE_RX && k != SV_GATE_RY && k != SV_GATE_RZ)
+            return fail(SV_EUNSUPPORTED, "gate %zu: only RX, RY and RZ may reference parameters", i);
+    }
+    const int B = s->batch;
+    const uint64_t N = 1ull << s->n;
+    const size_t state_bytes = (size_t)N * s->amp_bytes;
+    st = ensure_device_buf(&s->d_work, &s->d_work_cap, 2 * (size_t)B * state_bytes, "hipMalloc(adjoint work)");
+    if (st != SV_OK) return st;
+    const size_t ngrad = std::max<size_t>(1, (size_t)B * n_params);
+    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_grad), &s->d_grad_cap,
+                           ngrad * sizeof(double), "hipMalloc(grad)");
+    if (st != SV_OK) return st;
+    const size_t np = reduce_partials_size(s->n) * (size_t)B + (size_t)B;
+    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap, np * sizeof(double),
+                           "hipMalloc(reduce)");
+    if (st != SV_OK) return st;
+    char *psi = static_cast<char *>(s->d_work);
+    char *lam = psi + (size_t)B * state_bytes;
+    const int dt = (int)s->dt;
+
+    // forward: psi = U |0...0> for every batch entry
+    SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
+    PlanOptions po = plan_options(s);
+    po.basis_known = true;
+    po.basis_j = 0;
+    {
+        Plan p = build_plan(s->n, gates, n_gates, po);
+        st = run_plan(s, psi, B, p, gates, params, n_params);
+        if (st != SV_OK) return st;
+    }
+    SV_HIP(hipMemcpyAsync(s->buf, psi, (size_t)B * state_bytes, hipMemcpyDeviceToDevice, s->stream),
+           "hipMemcpyAsync(final states)");
+    s->basis_known = false;
+    // f = <Z_q> and lambda = Z_q psi
+    double *d_out = s->d_red + reduce_partials_size(s->n) * (size_t)B;
+    SV_HIP(launch_reduce(dt, psi, s->n, B, qubit, s->d_red, d_out, s->stream), "launch reduce");
+    if (expect) {
+        st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, (size_t)B * sizeof(double),
+                             "hipHostMalloc(out)");
+        if (st != SV_OK) return st;
+        SV_HIP(hipMemcpyAsync(s->h_out, d_out, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+               "hipMemcpyAsync(expect)");
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        std::memcpy(expect, s->h_out, (size_t)B * sizeof(double));
+    }
+    SV_HIP(launch_copy_z(dt, psi, lam, N, B, qubit, s->stream), "launch copy_z");
+    SV_HIP(hipMemsetAsync(s->d_grad, 0, ngrad * sizeof(double), s->stream), "hipMemsetAsync(grad)");
+
+    // reverse sweep on the 2B states [psi | lambda] with the inverse gates;
+    // parameter rows are duplicated and negated (U(t)^dagger = U(-t) for rotations)
+    std::vector<double> pneg((size_t)2 * B * std::max<size_t>(n_params, 1), 0.0);
+    for (int b = 0; b < B; ++b)
+        for (size_t p = 0; p < n_params; ++p) {
+            pneg[(size_t)b * n_params + p] = -params[(size_t)b * n_params + p];
+            pneg[(size_t)(B + b) * n_params + p] = -params[(size_t)b * n_params + p];
+        }
+    auto inverse = [](sv_gate g) {
+        switch (g.kind) {
+        case SV_GATE_S: g.kind = SV_GATE_SDG; break;
+        case SV_GATE_SDG: g.kind = SV_GATE_S; break;
+        case SV_GATE_T: g.kind = SV_GATE_TDG; break;
+        case SV_GATE_TDG: g.kind = SV_GATE_T; break;
+        case SV_GATE_RX: case SV_GATE_RY: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CPHASE:
+            if (g.param < 0) g.angle = -g.angle;   // referenced angles come from the negated table
+            break;
+        default: break;   // X, Y, Z, H, CNOT, CZ, SWAP, MARK, I are self-inverse
+        }
+        return g;
+    };
+    PlanOptions pr = plan_options(s);
+    pr.basis_known = false;
+    std::vector<sv_gate> seg;
+    auto flush = [&]() -> sv_status {
+        if (seg.empty()) return SV_OK;
+        Plan p = build_plan(s->n, seg.data(), seg.size(), pr);
+        sv_status r = run_plan(s, psi, 2 * B, p, seg.data(), pneg.data(), n_params);
+        seg.clear();
+        return r;
+    };
+    for (size_t i = n_gates; i-- > 0;) {
+        const sv_gate &g = gates[i];
+        if (g.param >= 0) {
+            st = flush();
+            if (st != SV_OK) return st;
+            const int pauli = g.kind == SV_GATE_RX ? 1 : g.kind == SV_GATE_RY ? 2 : 3;
+            SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, g.q0, pauli, s->d_red, s->d_grad,
+                                              n_params, (uint64_t)g.param, s->stream),
+                   "launch pauli_ip");
+        }
+        seg.push_back(inverse(g));
+    }
+    st = flush();
+    if (st != SV_OK) return st;
+    if (n_params) {
+        std::vector<double> tmp((size_t)B * n_params);
+        SV_HIP(hipMemcpyAsync(tmp.data(), s->d_grad, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                              s->stream),
+               "hipMemcpyAsync(grad)");
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        std::memcpy(grad, tmp.data(), tmp.size() * sizeof(double));
+    } else {
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    }
+    return SV_OK;
 }
 
 // ---------------------------------------------------------------------------

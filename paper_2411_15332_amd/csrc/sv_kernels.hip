@@ -650,6 +650,72 @@ __global__ void k_gather(const cpx<T> *__restrict__ state, const uint64_t *__res
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint differentiation helpers.
+
+// lambda_b = Z_q psi_b for every batch entry (psi at state, lambda at out).
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy_z(const cpx<T> *__restrict__ psi, cpx<T> *__restrict__ lam,
+                                                uint64_t total, uint64_t n_amps, int q) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const cpx<T> v = psi[i];
+        lam[i] = (((i % n_amps) >> q) & 1) ? mk<T>(-v.x, -v.y) : v;
+    }
+}
+
+// Im <lambda_b | P_q | psi_b>, P in {X = 1, Y = 2, Z = 3}, FP64, fixed order:
+// stage 1 per (chunk, batch entry), stage 2 adds the sum to grad[b * stride + p].
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_pauli_ip_partial(const cpx<T> *__restrict__ psi,
+                                                                  const cpx<T> *__restrict__ lam,
+                                                                  uint64_t n_amps, uint64_t chunk,
+                                                                  int q, int pauli,
+                                                                  double *__restrict__ part, int nblk) {
+    __shared__ double sh[kRedThreads];
+    const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
+    const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint64_t m = 1ull << q;
+    double acc = 0.0;
+    for (uint64_t i = lo + threadIdx.x; i < lo + chunk; i += kRedThreads) {
+        const cpx<T> l = lm[i];
+        const double lx = (double)l.x, ly = (double)l.y;
+        double px, py;   // (P psi)_i
+        if (pauli == 3) {
+            const cpx<T> v = ps[i];
+            const double sgn = (i & m) ? -1.0 : 1.0;
+            px = sgn * (double)v.x;
+            py = sgn * (double)v.y;
+        } else {
+            const cpx<T> v = ps[i ^ m];
+            if (pauli == 1) {
+                px = (double)v.x;
+                py = (double)v.y;
+            } else {  // Y: (-i, +i) psi_{i ^ m} for bit 0, 1
+                const double sgn = (i & m) ? 1.0 : -1.0;
+                px = -sgn * (double)v.y;
+                py = sgn * (double)v.x;
+            }
+        }
+        // Im(conj(l) * p) = lx * py - ly * px
+        acc += lx * py - ly * px;
+    }
+    const double sum = block_tree_sum(acc, sh);
+    if (threadIdx.x == 0) part[(uint64_t)blockIdx.y * nblk + blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_accumulate_final(const double *__restrict__ part,
+                                                                  int nblk, double *__restrict__ out,
+                                                                  uint64_t out_stride, uint64_t out_off) {
+    __shared__ double sh[kRedThreads];
+    const double *p = part + (uint64_t)blockIdx.x * nblk;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += p[i];
+    const double s = block_tree_sum(acc, sh);
+    if (threadIdx.x == 0) out[(uint64_t)blockIdx.x * out_stride + out_off] += s;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 
 hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch, uint64_t j,
@@ -732,6 +798,41 @@ hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_
     else
         hipLaunchKernelGGL(k_gather<float>, dim3(blocks), dim3(256), 0, st,
                            (const cpx<float> *)state, d_idx, (uint64_t)k, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, int batch, int q,
+                         hipStream_t st) {
+    const uint64_t total = n_amps * (uint64_t)batch;
+    uint64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (dt == 2)
+        hipLaunchKernelGGL(k_copy_z<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const cpx<double> *)psi, (cpx<double> *)lam, total, n_amps, q);
+    else
+        hipLaunchKernelGGL(k_copy_z<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const cpx<float> *)psi, (cpx<float> *)lam, total, n_amps, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, int n, int batch,
+                                      int q, int pauli, double *d_partials, double *d_grad,
+                                      uint64_t grad_stride, uint64_t grad_off, hipStream_t st) {
+    const uint64_t N = 1ull << n;
+    const int nblk = reduce_blocks(n);
+    const uint64_t chunk = N / (uint64_t)nblk;
+    if (dt == 2)
+        hipLaunchKernelGGL(k_pauli_ip_partial<double>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
+                           (const cpx<double> *)psi, (const cpx<double> *)lam, N, chunk, q, pauli,
+                           d_partials, nblk);
+    else
+        hipLaunchKernelGGL(k_pauli_ip_partial<float>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
+                           (const cpx<float> *)psi, (const cpx<float> *)lam, N, chunk, q, pauli,
+                           d_partials, nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_accumulate_final, dim3(batch), dim3(kRedThreads), 0, st,
+                       (const double *)d_partials, nblk, d_grad, grad_stride, grad_off);
     return hipGetLastError();
 }
 

@@ -44,4 +44,14 @@ hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
 hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_t k,
                          double *d_out, hipStream_t st);
 
+// lambda = Z_q psi for `batch` consecutive states.
+hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, int batch, int q,
+                         hipStream_t st);
+
+// grad[b * grad_stride + grad_off] += Im <lam_b | P_q | psi_b>, P = X (1), Y (2), Z (3),
+// accumulated in FP64 in a fixed order. d_partials: reduce_partials_size(n) * batch.
+hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, int n, int batch,
+                                      int q, int pauli, double *d_partials, double *d_grad,
+                                      uint64_t grad_stride, uint64_t grad_off, hipStream_t st);
+
 }  // namespace sv

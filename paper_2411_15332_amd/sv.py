@@ -195,7 +195,8 @@ class StateVector:
         return out[0::2] + 1j * out[1::2]
 
     def adjoint_expect_z(self, gates, params: np.ndarray, qubit: int = 0):
-        arr = np.ascontiguousarray(gate_array(gates))
+        arr = gates if isinstance(gates, np.ndarray) and gates.dtype == GATE_DTYPE else gate_array(gates)
+        arr = np.ascontiguousarray(arr)
         p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(self.batch, -1))
         expect = np.zeros(self.batch, dtype=np.float64)
         grad = np.zeros(p.shape, dtype=np.float64)

@@ -1,0 +1,101 @@
+"""Adjoint backward (sv_adjoint_expect_z / QNNFunction) against the oracle's
+parameter-shift rule (exact for exp(-i t P / 2)) and central differences."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+TOL_PS = {"c128": 1e-10, "c64": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_15332_amd as pkg
+    return pkg
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,L,B", [(3, 2, 3), (6, 2, 2), (12, 2, 2), (14, 1, 2)])
+def test_adjoint_matches_parameter_shift(P, n, L, B, dtype):
+    gates = synth.qnn_ansatz(n, L)
+    params = synth.qnn_params(n, L, B, 100 + n)
+    with P.StateVector(n, dtype, batch=B) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=0)
+    which = list(range(params.shape[1])) if n <= 6 else list(range(0, params.shape[1], 7))
+    for b in range(B):
+        assert abs(f[b] - O.loss_z(n, gates, params[b])) <= TOL_PS[dtype]
+        ps = O.grad_param_shift(n, gates, params[b], which)
+        assert np.max(np.abs(g[b, which] - ps)) <= TOL_PS[dtype]
+        if b == 0 and dtype == "c128":
+            fd = O.grad_fd(n, gates, params[b], which[:6])
+            assert np.max(np.abs(g[b, which[:6]] - fd)) <= 1e-7
+
+
+def test_adjoint_general_circuit(P):
+    """Rotations on every axis between non-parametric gates of every kind,
+    gradient on a qubit other than 0."""
+    n = 11
+    rng = np.random.default_rng(3)
+    base = synth.random_circuit(n, 3, 9)
+    gates, k = [], 0
+    for g in base:
+        gates.append(g)
+        if g.name in ("RX", "RY", "RZ"):
+            gates[-1] = g._replace(param=k)
+            k += 1
+    params = rng.uniform(-3, 3, size=(2, k))
+    with P.StateVector(n, "c128", batch=2) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=4)
+        final = sv.numpy()
+    for b in range(2):
+        ref = O.simulate(n, gates, params[b])
+        assert np.max(np.abs(final[b] - ref)) <= 1e-12
+        assert abs(f[b] - O.expect_z(ref, 4)) <= 1e-12
+        ps = O.grad_param_shift(n, gates, params[b], list(range(k)), qubit=4)
+        assert np.max(np.abs(g[b] - ps)) <= 1e-10
+
+
+def test_adjoint_rejects_nonrotation_parameters(P):
+    gates = [synth.Gate("P", 0, -1, 0.0, 0)]
+    with P.StateVector(4, "c128") as sv:
+        with pytest.raises(P.SVError) as e:
+            sv.adjoint_expect_z(gates, np.zeros((1, 1)), qubit=0)
+        assert e.value.status == -4
+
+
+def test_qnn_autograd_function(P):
+    import torch
+    n, L, B = 8, 3, 4
+    params = synth.qnn_params(n, L, B, 5)
+    x = torch.tensor(params[:, :n], requires_grad=True)
+    theta = torch.tensor(params[:, n:], requires_grad=True)
+    w = torch.tensor([0.5, -1.0, 2.0, 0.25], dtype=torch.float64)
+    f = P.qnn_expect(theta, x, n, L, "c128")
+    (f * w).sum().backward()
+    gates = synth.qnn_ansatz(n, L)
+    for b in range(B):
+        assert abs(f[b].item() - O.loss_z(n, gates, params[b])) <= 1e-12
+        ps = O.grad_param_shift(n, gates, params[b], list(range(params.shape[1])))
+        got = np.concatenate([x.grad[b].numpy(), theta.grad[b].numpy()])
+        assert np.max(np.abs(got - w[b].item() * ps)) <= 1e-10
+
+
+def test_adjoint_differentiation_config_n20(P):
+    """The differentiation workload: n = 20, 10 layers, 400 rotation angles,
+    256 parameter sets; sampled sets and angles against parameter shift."""
+    n, L, B = 20, 10, 256
+    gates = synth.qnn_ansatz(n, L)
+    params = synth.qnn_params(n, L, B, 0)
+    with P.StateVector(n, "c64", batch=B) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=0)
+    assert g.shape == (B, n + 2 * n * L) and np.all(np.isfinite(g))
+    rng = np.random.default_rng(1)
+    for b in (0, 255):
+        which = sorted(rng.choice(np.arange(n, n + 2 * n * L), size=3, replace=False).tolist())
+        assert abs(f[b] - O.loss_z(n, gates, params[b])) <= 1e-5
+        ps = O.grad_param_shift(n, gates, params[b], which)
+        assert np.max(np.abs(g[b, which] - ps)) <= 1e-4
