@@ -188,6 +188,53 @@ sv_status sv_plan_stats(sv_state s, int64_t out[8]);
 sv_status sv_profile_read(sv_state s, double *total_ms, int64_t *launches,
                           double *bytes);
 
+/* ------------------------------------------------------------------------
+ * Serving engine: continuous batching of independent circuit evaluations.
+ *
+ * A request is an n-qubit circuit applied to |0...0> with its own parameters,
+ * answered with <Z_qubit> (FP64). Queued requests are launched in groups:
+ *   - small states (n <= 13 for SV_C64, n <= 12 for SV_C128) of any circuit
+ *     shape share one launch, one workgroup per request, the state held in
+ *     LDS from start to readout (no HBM state at all);
+ *   - larger states are grouped with queued requests of the same circuit
+ *     (gates and qubit; parameters may differ) and run as one batched set of
+ *     fused passes.
+ * Up to n_streams groups are in flight on separate HIP streams; whenever one
+ * finishes, the oldest queued requests are launched (arrivals do not wait for
+ * a batch to drain). A larger-state group is admitted only when its state
+ * memory (requests * 2^n * amplitude bytes) fits the engine's HBM budget
+ * beside the groups in flight; otherwise it waits. A request's result does
+ * not depend on which requests share its launch.
+ * The engine is driven by sv_engine_poll; it is not thread-safe. */
+typedef struct sv_engine_s *sv_engine;
+
+/* max_batch >= 1: requests per launch group; n_streams in 1..16;
+ * hbm_budget_bytes: state memory the engine may hold (0 = no limit). */
+sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams,
+                           size_t hbm_budget_bytes, sv_engine *out);
+
+/* Waits for the groups in flight, then frees the engine. */
+sv_status sv_engine_free(sv_engine e);
+
+/* Queue one request (gates and params are copied). n_params reals of
+ * parameters (may be 0 with params NULL); qubit: the measured qubit.
+ * Gates are validated as in sv_apply_circuit (SV_EINVAL, nothing queued);
+ * n_qubits above 30 is SV_EUNSUPPORTED. */
+sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate *gates,
+                           size_t n_gates, const double *params, size_t n_params, int qubit);
+
+/* Retire finished groups, launch queued requests as streams and memory
+ * allow, and return up to `cap` finished results (ids[i], values[i]) in
+ * *count. wait_us > 0: wait up to that many microseconds for at least one
+ * result. */
+sv_status sv_engine_poll(sv_engine e, int64_t wait_us, uint64_t *ids, double *values,
+                         size_t cap, size_t *count);
+
+/* out[0] queued, out[1] in flight (requests), out[2] completed,
+ * out[3] groups launched, out[4] state bytes held, out[5] largest group,
+ * out[6] groups refused for memory (deferred), out[7] small-state groups. */
+sv_status sv_engine_stats(sv_engine e, int64_t out[8]);
+
 /* Description of the last error on this thread ("" if none). */
 const char *sv_last_error(void);
 

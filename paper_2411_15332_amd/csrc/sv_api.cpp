@@ -14,10 +14,11 @@
 #include "../../include/sv_debug.h"
 #include "sv_kernels.hpp"
 #include "sv_planner.hpp"
+#include "sv_internal.hpp"
 
 using namespace sv;
 
-namespace {
+namespace sv {
 
 thread_local std::string g_err;
 
@@ -36,68 +37,10 @@ sv_status hip_fail(hipError_t e, const char *what) {
                 hipGetErrorString(e));
 }
 
-#define SV_HIP(call, what)                              \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-}  // namespace
 
-struct sv_state_s {
-    int n = 0;
-    sv_dtype dt = SV_C128;
-    int batch = 1;
-    size_t amp_bytes = 16;
-    size_t bytes = 0;
-    void *buf = nullptr;
-    bool owned = false;
-    int device = 0;
-    hipStream_t stream = nullptr;
 
-    bool basis_known = true;
-    uint64_t basis_j = 0;
-
-    // options
-    bool fuse = true;
-    int min_low = 6;
-    int max_dense = 1 << 20;
-    bool gen_h = true;
-    int small_mode = 1;
-    bool profile = false;
-
-    // plan upload: pinned staging + device copy
-    void *h_stage = nullptr;
-    size_t h_cap = 0;
-    void *d_plan = nullptr;
-    size_t d_cap = 0;
-    hipEvent_t upload_done = nullptr;
-    bool upload_pending = false;
-
-    // readout scratch
-    double *d_red = nullptr;
-    size_t d_red_cap = 0;
-    double *h_out = nullptr;
-    size_t h_out_cap = 0;
-    uint64_t *d_idx = nullptr;
-    size_t d_idx_cap = 0;
-
-    // adjoint: work buffer of 2 * batch states (psi then lambda) and gradients
-    void *d_work = nullptr;
-    size_t d_work_cap = 0;
-    double *d_grad = nullptr;
-    size_t d_grad_cap = 0;
-
-    int64_t stats[8] = {0};
-
-    struct Timed { hipEvent_t a, b; double bytes; };
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> event_pool;
-};
-
-namespace {
 
 PlanOptions plan_options(const sv_state_s *s) {
     PlanOptions o;
@@ -270,6 +213,34 @@ sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const s
     return SV_OK;
 }
 
+void release_handle_buffers(sv_state_s *s) {
+    for (auto &t : s->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    s->timed.clear();
+    for (hipEvent_t ev : s->event_pool) hipEventDestroy(ev);
+    s->event_pool.clear();
+    if (s->upload_done) hipEventDestroy(s->upload_done);
+    s->upload_done = nullptr;
+    if (s->owned && s->buf) hipFree(s->buf);
+    s->buf = nullptr;
+    if (s->d_work) hipFree(s->d_work);
+    if (s->d_grad) hipFree(s->d_grad);
+    if (s->d_plan) hipFree(s->d_plan);
+    if (s->d_red) hipFree(s->d_red);
+    if (s->d_idx) hipFree(s->d_idx);
+    if (s->h_stage) hipHostFree(s->h_stage);
+    if (s->h_out) hipHostFree(s->h_out);
+    s->d_work = nullptr;
+    s->d_grad = nullptr;
+    s->d_plan = nullptr;
+    s->d_red = nullptr;
+    s->d_idx = nullptr;
+    s->h_stage = nullptr;
+    s->h_out = nullptr;
+}
+
 int64_t plan_hbm_bytes(const Plan &p, int n, size_t amp_bytes) {
     const int64_t N = 1ll << n;
     if (p.small) return p.sops.empty() ? 0 : 2 * N * (int64_t)amp_bytes;
@@ -279,7 +250,7 @@ int64_t plan_hbm_bytes(const Plan &p, int n, size_t amp_bytes) {
     return b;
 }
 
-}  // namespace
+}  // namespace sv
 
 extern "C" {
 
@@ -347,20 +318,7 @@ sv_status sv_free(sv_state s) {
     if (!s) return SV_OK;
     hipSetDevice(s->device);
     hipError_t e = hipStreamSynchronize(s->stream);
-    for (auto &t : s->timed) {
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
-    }
-    for (hipEvent_t ev : s->event_pool) hipEventDestroy(ev);
-    if (s->upload_done) hipEventDestroy(s->upload_done);
-    if (s->owned && s->buf) hipFree(s->buf);
-    if (s->d_work) hipFree(s->d_work);
-    if (s->d_grad) hipFree(s->d_grad);
-    if (s->d_plan) hipFree(s->d_plan);
-    if (s->d_red) hipFree(s->d_red);
-    if (s->d_idx) hipFree(s->d_idx);
-    if (s->h_stage) hipHostFree(s->h_stage);
-    if (s->h_out) hipHostFree(s->h_out);
+    release_handle_buffers(s);
     delete s;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize at free");
     return SV_OK;

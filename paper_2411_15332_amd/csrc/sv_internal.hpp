@@ -1,0 +1,90 @@
+// Internal declarations shared by the C-ABI sources (handles, plan upload).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "sv_planner.hpp"
+
+namespace sv {
+
+sv_status fail(sv_status st, const char *fmt, ...);
+sv_status hip_fail(hipError_t e, const char *what);
+size_t align_up(size_t x, size_t a);
+
+#define SV_HIP(call, what)                               \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return sv::hip_fail(e_, what); \
+    } while (0)
+
+}  // namespace sv
+
+// A state handle (opaque to callers): state memory, stream, options, and the
+// buffers used to upload pass plans.
+struct sv_state_s {
+    int n = 0;
+    sv_dtype dt = SV_C128;
+    int batch = 1;
+    size_t amp_bytes = 16;
+    size_t bytes = 0;
+    void *buf = nullptr;
+    bool owned = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    bool basis_known = true;
+    uint64_t basis_j = 0;
+
+    // options
+    bool fuse = true;
+    int min_low = 6;
+    int max_dense = 1 << 20;
+    bool gen_h = true;
+    int small_mode = 1;
+    bool profile = false;
+
+    // plan upload: pinned staging + device copy
+    void *h_stage = nullptr;
+    size_t h_cap = 0;
+    void *d_plan = nullptr;
+    size_t d_cap = 0;
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
+
+    // readout scratch
+    double *d_red = nullptr;
+    size_t d_red_cap = 0;
+    double *h_out = nullptr;
+    size_t h_out_cap = 0;
+    uint64_t *d_idx = nullptr;
+    size_t d_idx_cap = 0;
+
+    // adjoint: work buffer of 2 * batch states (psi then lambda) and gradients
+    void *d_work = nullptr;
+    size_t d_work_cap = 0;
+    double *d_grad = nullptr;
+    size_t d_grad_cap = 0;
+
+    int64_t stats[8] = {0};
+
+    struct Timed { hipEvent_t a, b; double bytes; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace sv {
+
+PlanOptions plan_options(const sv_state_s *s);
+sv_status ensure_device_buf(void **p, size_t *cap, size_t need, const char *what);
+sv_status ensure_host_buf(void **p, size_t *cap, size_t need, const char *what);
+// Upload plan `p` and launch it on `state` (`batch` states) on the handle's stream.
+sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const sv_gate *gates,
+                   const double *params, size_t n_params);
+// Release every buffer the handle owns or caches (not the handle itself).
+void release_handle_buffers(sv_state_s *s);
+
+}  // namespace sv

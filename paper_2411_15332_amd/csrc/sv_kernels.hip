@@ -650,6 +650,111 @@ __global__ void k_gather(const cpx<T> *__restrict__ state, const uint64_t *__res
 }
 
 // ---------------------------------------------------------------------------
+// Serving: many independent small circuits in one launch, one workgroup per
+// request; the state never leaves LDS and the result is <Z_qubit> in FP64.
+
+template <typename T>
+__device__ __forceinline__ void small_apply(cpx<T> *s, uint32_t N, const SmallOp &op, const T *c,
+                                            int tid, int nt) {
+    const int q0 = op.q0, q1 = op.q1;
+    switch (op.code) {
+    case SOP_D1:
+        for (uint32_t i = tid; i < N; i += nt) s[i] = cmul(s[i], ldc(c + 2 * ((i >> q0) & 1)));
+        break;
+    case SOP_D2:
+        for (uint32_t i = tid; i < N; i += nt)
+            s[i] = cmul(s[i], ldc(c + 2 * ((((i >> q0) & 1) << 1) | ((i >> q1) & 1))));
+        break;
+    case SOP_MARK:
+        if (tid == 0) {
+            const uint32_t m = (uint32_t)op.data;
+            s[m] = mk<T>(-s[m].x, -s[m].y);
+        }
+        break;
+    case SOP_DENSE1: {
+        const cpx<T> g00 = ldc(c), g01 = ldc(c + 2), g10 = ldc(c + 4), g11 = ldc(c + 6);
+        for (uint32_t p = tid; p < N / 2; p += nt) {
+            const uint32_t i0 = ins0(p, q0), i1 = i0 | (1u << q0);
+            const cpx<T> x0 = s[i0], x1 = s[i1];
+            s[i0] = cmul2(g00, x0, g01, x1);
+            s[i1] = cmul2(g10, x0, g11, x1);
+        }
+        break;
+    }
+    case SOP_X:
+        for (uint32_t p = tid; p < N / 2; p += nt) {
+            const uint32_t i0 = ins0(p, q0), i1 = i0 | (1u << q0);
+            const cpx<T> t = s[i0];
+            s[i0] = s[i1];
+            s[i1] = t;
+        }
+        break;
+    case SOP_Y:
+        for (uint32_t p = tid; p < N / 2; p += nt) {
+            const uint32_t i0 = ins0(p, q0), i1 = i0 | (1u << q0);
+            const cpx<T> x0 = s[i0], x1 = s[i1];
+            s[i0] = mk<T>(x1.y, -x1.x);
+            s[i1] = mk<T>(-x0.y, x0.x);
+        }
+        break;
+    case SOP_CX: {
+        const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+        for (uint32_t p = tid; p < N / 4; p += nt) {
+            const uint32_t b = ins0(ins0(p, lo), hi) | (1u << q0);
+            const uint32_t i1 = b | (1u << q1);
+            const cpx<T> t = s[b];
+            s[b] = s[i1];
+            s[i1] = t;
+        }
+        break;
+    }
+    case SOP_SWAP: {
+        const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+        for (uint32_t p = tid; p < N / 4; p += nt) {
+            const uint32_t b = ins0(ins0(p, lo), hi);
+            const uint32_t i01 = b | (1u << q1), i10 = b | (1u << q0);
+            const cpx<T> t = s[i01];
+            s[i01] = s[i10];
+            s[i10] = t;
+        }
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_small_jobs(const SmallJob *__restrict__ jobs,
+                                                    const SmallOp *__restrict__ ops,
+                                                    const T *__restrict__ consts,
+                                                    double *__restrict__ out) {
+    constexpr int kCap = sizeof(T) == 8 ? (1 << kSmallMaxQubitsC128) : (1 << kSmallMaxQubitsC64);
+    __shared__ cpx<T> s[kCap];
+    __shared__ double red[kRedThreads];
+    const SmallJob J = jobs[blockIdx.x];
+    const uint32_t N = 1u << J.n;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (uint32_t i = tid; i < N; i += nt) s[i] = mk<T>(i == 0 ? (T)1 : (T)0, (T)0);
+    __syncthreads();
+    const T *cst = consts + J.const_begin;
+    for (int oi = 0; oi < J.n_ops; ++oi) {
+        const SmallOp op = ops[J.op_begin + oi];
+        small_apply<T>(s, N, op, cst + op.data, tid, nt);
+        __syncthreads();
+    }
+    // <Z_qubit> in FP64: each thread in index order, then a fixed tree
+    double acc = 0.0;
+    for (uint32_t i = tid; i < N; i += nt) {
+        const double re = (double)s[i].x, im = (double)s[i].y;
+        const double p = re * re + im * im;
+        acc += ((i >> J.qubit) & 1) ? -p : p;
+    }
+    const double z = block_tree_sum(acc, red);
+    if (tid == 0) out[blockIdx.x] = z;
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint differentiation helpers.
 
 // lambda_b = Z_q psi_b for every batch entry (psi at state, lambda at out).
@@ -833,6 +938,18 @@ hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_accumulate_final, dim3(batch), dim3(kRedThreads), 0, st,
                        (const double *)d_partials, nblk, d_grad, grad_stride, grad_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_jobs(int dt, const SmallJob *d_jobs, int n_jobs, const SmallOp *d_ops,
+                             const void *d_consts, double *d_out, hipStream_t st) {
+    if (n_jobs <= 0) return hipSuccess;
+    if (dt == 2)
+        hipLaunchKernelGGL(k_small_jobs<double>, dim3(n_jobs), dim3(kRedThreads), 0, st, d_jobs, d_ops,
+                           (const double *)d_consts, d_out);
+    else
+        hipLaunchKernelGGL(k_small_jobs<float>, dim3(n_jobs), dim3(kRedThreads), 0, st, d_jobs, d_ops,
+                           (const float *)d_consts, d_out);
     return hipGetLastError();
 }
 

@@ -54,4 +54,8 @@ hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, 
                                       int q, int pauli, double *d_partials, double *d_grad,
                                       uint64_t grad_stride, uint64_t grad_off, hipStream_t st);
 
+// One workgroup per job: |0...0> in LDS, the job's small ops, out[j] = <Z_qubit>.
+hipError_t launch_small_jobs(int dt, const SmallJob *d_jobs, int n_jobs, const SmallOp *d_ops,
+                             const void *d_consts, double *d_out, hipStream_t st);
+
 }  // namespace sv

@@ -134,4 +134,17 @@ struct SmallOp {      // 16 bytes
 };
 static_assert(sizeof(SmallOp) == 16, "SmallOp layout");
 
+// One request of a heterogeneous small-state group (serving): the workgroup
+// with this index builds |0...0> in LDS, runs n_ops small ops starting at
+// op_begin with constants at const_begin (reals), and writes <Z_qubit>.
+struct SmallJob {     // 32 bytes
+    int32_t n;
+    int32_t qubit;
+    int32_t op_begin;
+    int32_t n_ops;
+    uint64_t const_begin;
+    uint64_t pad;
+};
+static_assert(sizeof(SmallJob) == 32, "SmallJob layout");
+
 }  // namespace sv
