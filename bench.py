@@ -167,6 +167,42 @@ def grover_section(P, synth):
             "success_probability": abs(amp) ** 2}
 
 
+def capacity_section(P, synth):
+    """Capacity configurations, one timed application each (host planning
+    included): n = 33 complex128 and n = 34 complex64, 128 GiB in place; an H
+    layer generated on demand, then 200 seeded layers (10% dense RX/RY)."""
+    import gc
+    import torch
+    out = {}
+    for n, dt in ((33, "c128"), (34, "c64")):
+        gates = synth.capacity_circuit(n, 200, 0)
+        arr = P.gate_array(gates)
+        sv = P.StateVector(n, dt)
+        try:
+            sv.set_option(P.sv.OPT_PROFILE, 1)
+            sv.profile_read()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv.apply(arr)
+            sv.sync()
+            dtm = time.perf_counter() - t0
+            k_ms, k_launches, k_bytes = sv.profile_read()
+            st = sv.plan_stats()
+            nrm = float(sv.norm()[0])
+        finally:
+            sv.close()
+            del sv
+            gc.collect()
+            torch.cuda.empty_cache()
+        gbs = k_bytes / (k_ms * 1e-3) / 1e9
+        out[f"n{n}_{dt}"] = {
+            "gates": len(gates), "passes": st["passes"], "seconds": dtm,
+            "amplitude_gate_updates_per_s": len(gates) * float(1 << n) / dtm,
+            "k_pass_avg_ms": k_ms / max(k_launches, 1), "k_pass_algorithmic_GBps": gbs,
+            "frac_hbm_peak": gbs / HBM_PEAK_GBS, "norm": nrm}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +307,7 @@ def main():
         out["serving"] = serving_section(P, synth)
         out["differentiation"] = adjoint_section(P, synth)
         out["grover_n20"] = grover_section(P, synth)
+        out["capacity"] = capacity_section(P, synth)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, gates)
     print(json.dumps(out), flush=True)

@@ -196,6 +196,57 @@ def grad_fd(n: int, gates: Sequence, params: np.ndarray, which: Sequence[int],
     return out
 
 
+def _row_nonzero(mat: np.ndarray):
+    """For a matrix with exactly one non-zero per row: (column, value) per row."""
+    cols = np.empty(mat.shape[0], dtype=np.int64)
+    vals = np.empty(mat.shape[0], dtype=np.complex128)
+    for r in range(mat.shape[0]):
+        nz = np.flatnonzero(mat[r])
+        if len(nz) != 1:
+            raise ValueError("gate is not monomial (one non-zero per row)")
+        cols[r] = nz[0]
+        vals[r] = mat[r, nz[0]]
+    return cols, vals
+
+
+def monomial_amplitudes(n: int, gates: Sequence, indices: Sequence[int], initial="uniform",
+                        params: Optional[np.ndarray] = None) -> np.ndarray:
+    """Selected amplitudes <i|U_m ... U_1|psi_in> of a circuit of monomial gates
+    (one non-zero per row: diagonal, permutation or permutation-with-phase,
+    the gates the paper's DAX form stores as one value and one index per row,
+    Sec. III-A), computed one index at a time without the state.
+
+    For a monomial U, (U psi)[i] = U[i, c(i)] psi[c(i)] with c(i) the column of
+    row i's non-zero, so the amplitude is the product of the visited entries
+    times psi_in at the index reached after walking the gates from last to
+    first. The embedded U = I..(x) G (x)..I has U[i, c] = G[r(i), r(c)] where i
+    and c agree off the gate's qubits (r = the local row, (b_q0 << 1) | b_q1).
+    initial: "uniform" (psi_in = 2^(-n/2) everywhere, i.e. H^n|0>) or a basis
+    index j (psi_in = |j>). Returns complex128 [len(indices)]."""
+    idx = np.array(indices, dtype=np.int64).copy()
+    amp = np.ones(len(idx), dtype=np.complex128)
+    for g in reversed(list(gates)):
+        if g.name == "MARK":
+            amp = np.where(idx == np.int64(g.index), -amp, amp)
+            continue
+        mat = G.matrix(g.name, _angle(g, params))
+        cols, vals = _row_nonzero(mat)
+        if G.arity(g.name) == 1:
+            r = (idx >> g.q0) & 1
+            c = cols[r]
+            idx = (idx & ~np.int64(1 << g.q0)) | (c << g.q0)
+        else:
+            r = (((idx >> g.q0) & 1) << 1) | ((idx >> g.q1) & 1)
+            c = cols[r]
+            idx = (idx & ~np.int64((1 << g.q0) | (1 << g.q1))) | ((c >> 1) << g.q0) | ((c & 1) << g.q1)
+        amp = amp * vals[r]
+    if isinstance(initial, str):
+        if initial != "uniform":
+            raise ValueError("initial must be 'uniform' or a basis index")
+        return amp * (2.0 ** (-0.5 * n))
+    return np.where(idx == np.int64(initial), amp, 0.0 + 0.0j)
+
+
 def grover_closed_form(n: int, k: int):
     """Textbook Grover amplitudes after k iterations of D*O from H^n|0>, with
     D = 2|s><s| - I: (marked, unmarked, success probability), where

@@ -83,16 +83,17 @@ def random_circuit(n: int, depth: int, seed: int) -> List[Gate]:
     return gates
 
 
-def capacity_circuit(n: int, layers: int, seed: int) -> List[Gate]:
+def capacity_circuit(n: int, layers: int, seed: int, p_dense: float = 0.1) -> List[Gate]:
     """Capacity workload: an H layer on every qubit, then ``layers`` layers in
-    which each qubit gets, with probability 0.1, a dense gate from
+    which each qubit gets, with probability p_dense (0.1), a dense gate from
     CAPACITY_DENSE_POOL and otherwise a gate from CAPACITY_SPARSE_POOL, followed
-    by random disjoint pairs (probability 0.5) from CAPACITY_2Q_POOL."""
+    by random disjoint pairs (probability 0.5) from CAPACITY_2Q_POOL.
+    p_dense = 0 gives the same draw sequence with only sparse gates."""
     rng = np.random.default_rng(seed)
     gates: List[Gate] = [Gate("H", q) for q in range(n)]
     for _ in range(layers):
         for q in range(n):
-            if rng.random() < 0.1:
+            if rng.random() < p_dense:
                 name = CAPACITY_DENSE_POOL[int(rng.integers(len(CAPACITY_DENSE_POOL)))]
             else:
                 name = CAPACITY_SPARSE_POOL[int(rng.integers(len(CAPACITY_SPARSE_POOL)))]

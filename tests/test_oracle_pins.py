@@ -327,3 +327,70 @@ def test_gradients_ps_fd_kron_agree():
             dpsi = U @ dpsi
         d = 2 * np.real(np.vdot(psi, Zn @ dpsi))
         assert abs(d - ps[k]) < 1e-12
+
+
+# ------------------------------------------------ one-at-a-time monomial amplitudes
+
+_MONO_1Q = ("X", "Y", "Z", "S", "SDG", "T", "TDG", "RZ", "P", "I")
+_MONO_2Q = ("CNOT", "CZ", "SWAP", "CPHASE")
+
+
+def _random_monomial_circuit(n, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        if rng.random() < 0.6:
+            name = _MONO_1Q[int(rng.integers(len(_MONO_1Q)))]
+            out.append(synth.Gate(name, int(rng.integers(n)), -1, float(rng.uniform(0, 2 * math.pi))))
+        else:
+            q0, q1 = (int(x) for x in rng.choice(n, 2, replace=False))
+            name = _MONO_2Q[int(rng.integers(len(_MONO_2Q)))]
+            out.append(synth.Gate(name, q0, q1, float(rng.uniform(0, 2 * math.pi))))
+    return out
+
+
+@pytest.mark.parametrize("n,seed", [(6, 0), (8, 1), (9, 2)])
+def test_monomial_amplitudes_vs_kronecker(n, seed):
+    """Every amplitude of a random monomial circuit, walked one index at a
+    time, equals the Kronecker-operator product applied to H^n|0> and to a
+    basis state."""
+    gates = _random_monomial_circuit(n, 60, seed)
+    U = K.circuit_operator(n, gates)
+    idx = np.arange(1 << n)
+    uni = np.full(1 << n, 2.0 ** (-0.5 * n), dtype=complex)
+    assert np.max(np.abs(O.monomial_amplitudes(n, gates, idx) - U @ uni)) < 1e-14
+    j = 37 % (1 << n)
+    e = np.zeros(1 << n, dtype=complex)
+    e[j] = 1.0
+    assert np.max(np.abs(O.monomial_amplitudes(n, gates, idx, initial=j) - U @ e)) < 1e-14
+
+
+def test_monomial_amplitudes_capacity_mix_vs_state_oracle():
+    """The capacity mix without dense gates at n = 12, after its H layer:
+    sampled one-index amplitudes equal the full-state oracle's."""
+    n = 12
+    g = synth.capacity_circuit(n, 30, 3, p_dense=0.0)
+    assert all(x.name == "H" for x in g[:n])
+    psi = O.simulate(n, g)
+    idx = np.random.default_rng(0).integers(0, 1 << n, 500)
+    assert np.max(np.abs(O.monomial_amplitudes(n, g[n:], idx) - psi[idx])) < 1e-14
+
+
+def test_monomial_amplitudes_closed_forms():
+    n = 11
+    allx = [synth.Gate("X", q) for q in range(n)]
+    # X on every qubit maps |0> to |2^n - 1>.
+    a = O.monomial_amplitudes(n, allx, [0, (1 << n) - 1, 5], initial=0)
+    assert np.array_equal(a, np.array([0, 1, 0], dtype=complex))
+    # A CNOT chain is the classical map b_{q+1} ^= b_q (ascending q) on basis states.
+    chain = [synth.Gate("CNOT", q, q + 1) for q in range(n - 1)]
+    j = 0b10110011101
+    x = j
+    for q in range(n - 1):
+        x ^= ((x >> q) & 1) << (q + 1)
+    assert O.monomial_amplitudes(n, chain, [x], initial=j)[0] == 1
+    # Z on qubit 0 of the uniform state: sign (-1)^{b_0}.
+    z = O.monomial_amplitudes(3, [synth.Gate("Z", 0)], range(8))
+    assert np.allclose(z, 2 ** -1.5 * np.array([1, -1] * 4))
+    with pytest.raises(ValueError):
+        O.monomial_amplitudes(3, [synth.Gate("H", 0)], [0])
