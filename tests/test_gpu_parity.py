@@ -235,6 +235,15 @@ def test_batched_parameters(P, n, dtype):
         ref = O.simulate(n, gates, params[b])
         assert maxdiff(got[b], ref) <= TOL[dtype]
         assert abs(z[b] - O.expect_z(ref, 0)) <= TOL[dtype]
+    # Batch composition does not change a state's result: entry b run alone
+    # gives bitwise the same amplitudes and <Z_0> (fixed reduction tree).
+    for b in (0, B - 1):
+        with P.StateVector(n, dtype, 1) as sv:
+            sv.apply(gates, params[b:b + 1])
+            alone = sv.numpy()[0]
+            z_alone = sv.expect_z(0)[0]
+        assert np.array_equal(alone, got[b].astype(alone.dtype))
+        assert z_alone == z[b]
 
 
 def test_empty_identity_and_errors(P):
