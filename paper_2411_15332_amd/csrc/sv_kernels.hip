@@ -66,13 +66,42 @@ __device__ __forceinline__ cpx<T> ldc(const T *p) {
 // update), which keeps the register tile in fixed VGPRs across the
 // interpreter's dispatch merge.
 
-// a *= d, with one temporary product
+// a *= d
 template <typename T>
 __device__ __forceinline__ void cmul_ip(cpx<T> &a, cpx<T> d) {
-    const T t = a.x * d.y;
-    const T u = a.y * d.y;
-    a.x = __builtin_fma(a.x, d.x, -u);
-    a.y = __builtin_fma(a.y, d.x, t);
+    a = cmul(a, d);
+}
+
+// Exchange two register values without renaming them: each asm output is
+// tied to its input VGPR, so a permutation of the register tile is a
+// physical exchange and the tile keeps fixed VGPRs across the interpreter's
+// dispatch merge (a renamed permutation there costs a whole-tile copy on
+// every operation).
+__device__ __forceinline__ void vswap32(uint32_t &x, uint32_t &y) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(x), "+v"(y));
+}
+template <typename T>
+__device__ __forceinline__ void vswap(T &x, T &y);
+template <>
+__device__ __forceinline__ void vswap<double>(double &x, double &y) {
+    const uint64_t a = __builtin_bit_cast(uint64_t, x), b = __builtin_bit_cast(uint64_t, y);
+    uint32_t al = (uint32_t)a, ah = (uint32_t)(a >> 32), bl = (uint32_t)b, bh = (uint32_t)(b >> 32);
+    vswap32(al, bl);
+    vswap32(ah, bh);
+    x = __builtin_bit_cast(double, ((uint64_t)ah << 32) | al);
+    y = __builtin_bit_cast(double, ((uint64_t)bh << 32) | bl);
+}
+template <>
+__device__ __forceinline__ void vswap<float>(float &x, float &y) {
+    uint32_t a = __builtin_bit_cast(uint32_t, x), b = __builtin_bit_cast(uint32_t, y);
+    vswap32(a, b);
+    x = __builtin_bit_cast(float, a);
+    y = __builtin_bit_cast(float, b);
+}
+template <typename T>
+__device__ __forceinline__ void cswap(cpx<T> &p, cpx<T> &q) {
+    vswap(p.x, q.x);
+    vswap(p.y, q.y);
 }
 
 // Hadamard butterfly (x0 + x1, x0 - x1) as x0 <- x0 + x1, x1 <- x0' - 2 x1
@@ -114,10 +143,7 @@ __device__ __forceinline__ void r_x(cpx<T> (&a)[NR]) {
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << P)) continue;
-        const int j1 = j | (1 << P);
-        const cpx<T> t = a[j];
-        a[j] = a[j1];
-        a[j1] = t;
+        cswap(a[j], a[j | (1 << P)]);
     }
 }
 
@@ -128,10 +154,7 @@ __device__ __forceinline__ void r_cx_reg(cpx<T> (&a)[NR]) {
     for (int j = 0; j < NR; ++j) {
         if (j & (1 << P)) continue;
         if (!(j & (1 << PC))) continue;
-        const int j1 = j | (1 << P);
-        const cpx<T> t = a[j];
-        a[j] = a[j1];
-        a[j1] = t;
+        cswap(a[j], a[j | (1 << P)]);
     }
 }
 
@@ -232,11 +255,14 @@ struct PassTraits<float> {
 };
 
 // Thread part of a layout: global-index bits and byte address of the LDS slot.
-__device__ __forceinline__ void thr_part(const DevLayout &L, int w, int tid, int slot_shift,
+// Entries of thread bits at or above the workgroup's width are zero, so the
+// loop runs over every possible bit without a data-dependent trip count.
+__device__ __forceinline__ void thr_part(const DevLayout &L, int tid, int slot_shift,
                                          uint64_t &g, uint32_t &s) {
     g = L.goff_xor;
     uint32_t sl = L.slot_xor;
-    for (int b = 0; b < w; ++b) {
+#pragma unroll
+    for (int b = 0; b < kMaxThreadBits; ++b) {
         const bool on = (tid >> b) & 1;
         g ^= on ? L.thr_goff[b] : 0ull;
         sl ^= on ? L.thr_slot[b] : 0u;
@@ -276,7 +302,6 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
 
     const DevPass &P = passes[pass_idx];
     const int tid = threadIdx.x;
-    const int w = P.w;
     const int k = P.k;
     const DevLayout *LB = layouts + P.layout_begin;
     cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
@@ -295,7 +320,7 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
         const DevLayout &L = LB[0];
         uint64_t gthr;
         uint32_t sdummy;
-        thr_part(L, w, tid, SH, gthr, sdummy);
+        thr_part(L, tid, SH, gthr, sdummy);
         uint64_t greg[NR];
         reg_goff<R>(L, greg);
         const cpx<T> *tp = st + (base | gthr);
@@ -335,14 +360,14 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
             case OP_EXCH: {
                 uint64_t gd;
                 uint32_t sthr, sreg[NR];
-                thr_part(LB[op.a], w, tid, SH, gd, sthr);
+                thr_part(LB[op.a], tid, SH, gd, sthr);
                 reg_slot<R>(LB[op.a], SH, sreg);
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
                     *reinterpret_cast<cpx<T> *>(ldsb + (sthr ^ sreg[j])) = a[j];
                 __syncthreads();
-                thr_part(LB[op.b], w, tid, SH, gd, sthr);
+                thr_part(LB[op.b], tid, SH, gd, sthr);
                 reg_slot<R>(LB[op.b], SH, sreg);
 #pragma unroll
                 for (int j = 0; j < NR; ++j)
@@ -442,7 +467,7 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
         const DevLayout &L = LB[P.store_layout];
         uint64_t gthr;
         uint32_t sdummy;
-        thr_part(L, w, tid, SH, gthr, sdummy);
+        thr_part(L, tid, SH, gthr, sdummy);
         uint64_t greg[NR];
         reg_goff<R>(L, greg);
         cpx<T> *tp = st + (base | gthr);

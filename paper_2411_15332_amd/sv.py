@@ -47,6 +47,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one. Load PyTorch first so that libsv.so binds to the runtime
+        # that owns the tensors and streams it is handed; loaded the other way
+        # round, the two disagree about devices.
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         P, I, U64, SZ, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
         I64 = ctypes.c_int64
