@@ -56,7 +56,7 @@ PlanOptions plan_options(const sv_state_s *s) {
         o.small_max = kSmallMaxQubitsC64;
     }
     o.c = s->min_low;
-    o.w_max = kMaxThreadBits;
+    o.w_max = s->dt == SV_C128 ? kThreadBitsC128 : kThreadBitsC64;
     o.fuse = s->fuse;
     o.max_dense = s->max_dense;
     o.gen_h = s->gen_h;
@@ -260,115 +260,127 @@ const char *sv_version(void) { return "sv-gfx950 0.1"; }
 
 sv_status sv_alloc(int n_qubits, sv_dtype dtype, int batch, void *dev_buf, size_t buf_bytes,
                    void *hip_stream, sv_state *out) {
-    if (!out) return fail(SV_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
-    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
-    if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch %d outside 1..65535", batch);
-    const size_t amp = dtype == SV_C128 ? 16 : 8;
-    const size_t bytes = ((size_t)1 << n_qubits) * amp * (size_t)batch;
-    if (dev_buf) {
-        if (buf_bytes < bytes)
-            return fail(SV_EINVAL, "buffer of %zu bytes is smaller than the %zu needed", buf_bytes, bytes);
-        if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
-            return fail(SV_EINVAL, "device buffer is not 256-byte aligned");
-    }
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    sv_state_s *s = new (std::nothrow) sv_state_s();
-    if (!s) return fail(SV_ENOMEM, "host allocation failed");
-    s->n = n_qubits;
-    s->dt = dtype;
-    s->batch = batch;
-    s->amp_bytes = amp;
-    s->bytes = bytes;
-    s->device = dev;
-    s->stream = static_cast<hipStream_t>(hip_stream);
-    if (const char *fail_alloc = std::getenv("SV_DEBUG_FAIL_ALLOC")) {
-        if (std::atoi(fail_alloc) != 0 && !dev_buf) {
-            delete s;
-            return fail(SV_ENOMEM, "allocation failure injected by SV_DEBUG_FAIL_ALLOC");
+    return guarded([&]() -> sv_status {
+        if (!out) return fail(SV_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
+        if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
+        if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch %d outside 1..65535", batch);
+        const size_t amp = dtype == SV_C128 ? 16 : 8;
+        const size_t bytes = ((size_t)1 << n_qubits) * amp * (size_t)batch;
+        if (dev_buf) {
+            if (buf_bytes < bytes)
+                return fail(SV_EINVAL, "buffer of %zu bytes is smaller than the %zu needed", buf_bytes, bytes);
+            if (reinterpret_cast<uintptr_t>(dev_buf) % 256 != 0)
+                return fail(SV_EINVAL, "device buffer is not 256-byte aligned");
         }
-    }
-    if (dev_buf) {
-        s->buf = dev_buf;
-        s->owned = false;
-    } else {
-        e = hipMalloc(&s->buf, bytes);
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        sv_state_s *s = new (std::nothrow) sv_state_s();
+        if (!s) return fail(SV_ENOMEM, "host allocation failed");
+        s->n = n_qubits;
+        s->dt = dtype;
+        s->batch = batch;
+        s->amp_bytes = amp;
+        s->bytes = bytes;
+        s->device = dev;
+        s->stream = static_cast<hipStream_t>(hip_stream);
+        if (const char *fail_alloc = std::getenv("SV_DEBUG_FAIL_ALLOC")) {
+            if (std::atoi(fail_alloc) != 0 && !dev_buf) {
+                delete s;
+                return fail(SV_ENOMEM, "allocation failure injected by SV_DEBUG_FAIL_ALLOC");
+            }
+        }
+        if (dev_buf) {
+            s->buf = dev_buf;
+            s->owned = false;
+        } else {
+            e = hipMalloc(&s->buf, bytes);
+            if (e != hipSuccess) {
+                delete s;
+                return hip_fail(e, "hipMalloc(state)");
+            }
+            s->owned = true;
+        }
+        e = launch_fill_basis((int)dtype, s->buf, 1ull << n_qubits, batch, 0, s->stream);
         if (e != hipSuccess) {
+            if (s->owned) hipFree(s->buf);
             delete s;
-            return hip_fail(e, "hipMalloc(state)");
+            return hip_fail(e, "launch fill");
         }
-        s->owned = true;
-    }
-    e = launch_fill_basis((int)dtype, s->buf, 1ull << n_qubits, batch, 0, s->stream);
-    if (e != hipSuccess) {
-        if (s->owned) hipFree(s->buf);
-        delete s;
-        return hip_fail(e, "launch fill");
-    }
-    s->basis_known = true;
-    s->basis_j = 0;
-    *out = s;
-    return SV_OK;
+        s->basis_known = true;
+        s->basis_j = 0;
+        *out = s;
+        return SV_OK;
+    });
 }
 
 sv_status sv_free(sv_state s) {
-    if (!s) return SV_OK;
-    hipSetDevice(s->device);
-    hipError_t e = hipStreamSynchronize(s->stream);
-    release_handle_buffers(s);
-    delete s;
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize at free");
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!s) return SV_OK;
+        hipSetDevice(s->device);
+        hipError_t e = hipStreamSynchronize(s->stream);
+        release_handle_buffers(s);
+        delete s;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize at free");
+        return SV_OK;
+    });
 }
 
 sv_status sv_set_stream(sv_state s, void *hip_stream) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    s->stream = static_cast<hipStream_t>(hip_stream);
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        s->stream = static_cast<hipStream_t>(hip_stream);
+        return SV_OK;
+    });
 }
 
 sv_status sv_set_basis(sv_state s, uint64_t j) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (j >= (1ull << s->n)) return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)j, s->n);
-    SV_HIP(launch_fill_basis((int)s->dt, s->buf, 1ull << s->n, s->batch, j, s->stream), "launch fill");
-    s->basis_known = true;
-    s->basis_j = j;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        if (j >= (1ull << s->n)) return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)j, s->n);
+        SV_HIP(launch_fill_basis((int)s->dt, s->buf, 1ull << s->n, s->batch, j, s->stream), "launch fill");
+        s->basis_known = true;
+        s->basis_j = j;
+        return SV_OK;
+    });
 }
 
 sv_status sv_mark_modified(sv_state s) {
-    if (!s) return fail(SV_EINVAL, "null handle");
-    s->basis_known = false;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!s) return fail(SV_EINVAL, "null handle");
+        s->basis_known = false;
+        return SV_OK;
+    });
 }
 
 sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, const double *params,
                            size_t n_params) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
-    std::string err;
-    if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
-        return fail(SV_EINVAL, "%s", err.c_str());
-    if (n_gates == 0) return SV_OK;
-    Plan p = build_plan(s->n, gates, n_gates, plan_options(s));
-    st = run_plan(s, s->buf, s->batch, p, gates, params, n_params);
-    if (st != SV_OK) return st;
-    s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
-    s->stats[1] = p.n_exch;
-    s->stats[2] = p.gates_applied;
-    s->stats[3] = p.n_gen_h;
-    s->stats[4] = p.small ? (p.sops.empty() ? 0 : 1) : (int64_t)p.passes.size();
-    s->stats[5] = plan_hbm_bytes(p, s->n, s->amp_bytes);
-    s->stats[6] = p.n_relabel;
-    if (p.gates_applied > 0) s->basis_known = false;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+        std::string err;
+        if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
+            return fail(SV_EINVAL, "%s", err.c_str());
+        if (n_gates == 0) return SV_OK;
+        Plan p = build_plan(s->n, gates, n_gates, plan_options(s));
+        st = run_plan(s, s->buf, s->batch, p, gates, params, n_params);
+        if (st != SV_OK) return st;
+        s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
+        s->stats[1] = p.n_exch;
+        s->stats[2] = p.gates_applied;
+        s->stats[3] = p.n_gen_h;
+        s->stats[4] = p.small ? (p.sops.empty() ? 0 : 1) : (int64_t)p.passes.size();
+        s->stats[5] = plan_hbm_bytes(p, s->n, s->amp_bytes);
+        s->stats[6] = p.n_relabel;
+        if (p.gates_applied > 0) s->basis_known = false;
+        return SV_OK;
+    });
 }
 
 static sv_status reduce(sv_state s, int qubit, double *out) {
@@ -391,241 +403,272 @@ static sv_status reduce(sv_state s, int qubit, double *out) {
 }
 
 sv_status sv_expect_z(sv_state s, int qubit, double *out) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (!out) return fail(SV_EINVAL, "out is NULL");
-    if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
-    return reduce(s, qubit, out);
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        if (!out) return fail(SV_EINVAL, "out is NULL");
+        if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
+        return reduce(s, qubit, out);
+    });
 }
 
 sv_status sv_norm(sv_state s, double *out) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (!out) return fail(SV_EINVAL, "out is NULL");
-    return reduce(s, -1, out);
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        if (!out) return fail(SV_EINVAL, "out is NULL");
+        return reduce(s, -1, out);
+    });
 }
 
 sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double *out) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (b < 0 || b >= s->batch) return fail(SV_EINVAL, "batch entry %d out of range", b);
-    if (k == 0) return SV_OK;
-    if (!idx || !out) return fail(SV_EINVAL, "idx or out is NULL");
-    const uint64_t N = 1ull << s->n;
-    for (size_t i = 0; i < k; ++i)
-        if (idx[i] >= N) return fail(SV_EINVAL, "index %llu >= 2^%d", (unsigned long long)idx[i], s->n);
-    const size_t need_host = std::max(k * sizeof(uint64_t), 2 * k * sizeof(double));
-    st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, need_host, "hipHostMalloc");
-    if (st != SV_OK) return st;
-    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_idx), &s->d_idx_cap,
-                           k * sizeof(uint64_t) + 2 * k * sizeof(double), "hipMalloc(idx)");
-    if (st != SV_OK) return st;
-    // the pinned buffer may still feed an earlier copy only after a sync, which
-    // every readout performs; safe to reuse here
-    std::memcpy(s->h_out, idx, k * sizeof(uint64_t));
-    SV_HIP(hipMemcpyAsync(s->d_idx, s->h_out, k * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream),
-           "hipMemcpyAsync(idx)");
-    double *d_vals = reinterpret_cast<double *>(s->d_idx + k);
-    const char *base = static_cast<const char *>(s->buf) + (size_t)b * N * s->amp_bytes;
-    SV_HIP(launch_gather((int)s->dt, base, s->d_idx, k, d_vals, s->stream), "launch gather");
-    SV_HIP(hipMemcpyAsync(s->h_out, d_vals, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s->stream),
-           "hipMemcpyAsync(amplitudes)");
-    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    std::memcpy(out, s->h_out, 2 * k * sizeof(double));
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        if (b < 0 || b >= s->batch) return fail(SV_EINVAL, "batch entry %d out of range", b);
+        if (k == 0) return SV_OK;
+        if (!idx || !out) return fail(SV_EINVAL, "idx or out is NULL");
+        const uint64_t N = 1ull << s->n;
+        for (size_t i = 0; i < k; ++i)
+            if (idx[i] >= N) return fail(SV_EINVAL, "index %llu >= 2^%d", (unsigned long long)idx[i], s->n);
+        const size_t need_host = std::max(k * sizeof(uint64_t), 2 * k * sizeof(double));
+        st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, need_host, "hipHostMalloc");
+        if (st != SV_OK) return st;
+        st = ensure_device_buf(reinterpret_cast<void **>(&s->d_idx), &s->d_idx_cap,
+                               k * sizeof(uint64_t) + 2 * k * sizeof(double), "hipMalloc(idx)");
+        if (st != SV_OK) return st;
+        // the pinned buffer may still feed an earlier copy only after a sync, which
+        // every readout performs; safe to reuse here
+        std::memcpy(s->h_out, idx, k * sizeof(uint64_t));
+        SV_HIP(hipMemcpyAsync(s->d_idx, s->h_out, k * sizeof(uint64_t), hipMemcpyHostToDevice, s->stream),
+               "hipMemcpyAsync(idx)");
+        double *d_vals = reinterpret_cast<double *>(s->d_idx + k);
+        const char *base = static_cast<const char *>(s->buf) + (size_t)b * N * s->amp_bytes;
+        SV_HIP(launch_gather((int)s->dt, base, s->d_idx, k, d_vals, s->stream), "launch gather");
+        SV_HIP(hipMemcpyAsync(s->h_out, d_vals, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+               "hipMemcpyAsync(amplitudes)");
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        std::memcpy(out, s->h_out, 2 * k * sizeof(double));
+        return SV_OK;
+    });
 }
 
 sv_status sv_sync(sv_state s) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        return SV_OK;
+    });
 }
 
 void *sv_device_ptr(sv_state s) { return s ? s->buf : nullptr; }
 
 sv_status sv_set_option(sv_state s, int option, int64_t value) {
-    if (!s) return fail(SV_EINVAL, "null handle");
-    switch (option) {
-    case SV_OPT_FUSE:
-        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_FUSE takes 0 or 1");
-        s->fuse = value != 0;
-        return SV_OK;
-    case SV_OPT_MIN_LOW_QUBITS:
-        if (value < 3 || value > 7) return fail(SV_EINVAL, "SV_OPT_MIN_LOW_QUBITS takes 3..7");
-        s->min_low = (int)value;
-        return SV_OK;
-    case SV_OPT_MAX_DENSE:
-        if (value < 1 || value > (1 << 20)) return fail(SV_EINVAL, "SV_OPT_MAX_DENSE takes >= 1");
-        s->max_dense = (int)value;
-        return SV_OK;
-    case SV_OPT_ON_DEMAND_H:
-        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_ON_DEMAND_H takes 0 or 1");
-        s->gen_h = value != 0;
-        return SV_OK;
-    case SV_OPT_SMALL_PATH:
-        if (value != 1 && value != 2) return fail(SV_EINVAL, "SV_OPT_SMALL_PATH takes 1 or 2");
-        s->small_mode = (int)value;
-        return SV_OK;
-    case SV_OPT_PROFILE:
-        if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_PROFILE takes 0 or 1");
-        s->profile = value != 0;
-        return SV_OK;
-    default:
-        return fail(SV_EINVAL, "unknown option %d", option);
-    }
+    return guarded([&]() -> sv_status {
+        if (!s) return fail(SV_EINVAL, "null handle");
+        switch (option) {
+        case SV_OPT_FUSE:
+            if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_FUSE takes 0 or 1");
+            s->fuse = value != 0;
+            return SV_OK;
+        case SV_OPT_MIN_LOW_QUBITS:
+            if (value < 3 || value > 7) return fail(SV_EINVAL, "SV_OPT_MIN_LOW_QUBITS takes 3..7");
+            s->min_low = (int)value;
+            return SV_OK;
+        case SV_OPT_MAX_DENSE:
+            if (value < 1 || value > (1 << 20)) return fail(SV_EINVAL, "SV_OPT_MAX_DENSE takes >= 1");
+            s->max_dense = (int)value;
+            return SV_OK;
+        case SV_OPT_ON_DEMAND_H:
+            if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_ON_DEMAND_H takes 0 or 1");
+            s->gen_h = value != 0;
+            return SV_OK;
+        case SV_OPT_SMALL_PATH:
+            if (value != 1 && value != 2) return fail(SV_EINVAL, "SV_OPT_SMALL_PATH takes 1 or 2");
+            s->small_mode = (int)value;
+            return SV_OK;
+        case SV_OPT_PROFILE:
+            if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_PROFILE takes 0 or 1");
+            s->profile = value != 0;
+            return SV_OK;
+        default:
+            return fail(SV_EINVAL, "unknown option %d", option);
+        }
+    });
 }
 
 sv_status sv_plan_stats(sv_state s, int64_t out[8]) {
-    if (!s || !out) return fail(SV_EINVAL, "null argument");
-    std::memcpy(out, s->stats, sizeof s->stats);
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!s || !out) return fail(SV_EINVAL, "null argument");
+        std::memcpy(out, s->stats, sizeof s->stats);
+        return SV_OK;
+    });
 }
 
 sv_status sv_profile_read(sv_state s, double *total_ms, int64_t *launches, double *bytes) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    double tot = 0.0, by = 0.0;
-    for (auto &t : s->timed) {
-        float ms = 0.f;
-        hipError_t e = hipEventElapsedTime(&ms, t.a, t.b);
-        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-        tot += ms;
-        by += t.bytes;
-        s->event_pool.push_back(t.a);
-        s->event_pool.push_back(t.b);
-    }
-    if (total_ms) *total_ms = tot;
-    if (launches) *launches = (int64_t)s->timed.size();
-    if (bytes) *bytes = by;
-    s->timed.clear();
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
+        if (st != SV_OK) return st;
+        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        double tot = 0.0, by = 0.0;
+        for (auto &t : s->timed) {
+            float ms = 0.f;
+            hipError_t e = hipEventElapsedTime(&ms, t.a, t.b);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            tot += ms;
+            by += t.bytes;
+            s->event_pool.push_back(t.a);
+            s->event_pool.push_back(t.b);
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = (int64_t)s->timed.size();
+        if (bytes) *bytes = by;
+        s->timed.clear();
+        return SV_OK;
+    });
 }
 
 sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, const double *params,
                               size_t n_params, int qubit, double *expect, double *grad) {
-    sv_status st = check_handle(s);
-    if (st != SV_OK) return st;
-    if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
-    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
-    if (n_params && !grad) return fail(SV_EINVAL, "grad is NULL");
-    std::string err;
-    if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
-        return fail(SV_EINVAL, "%s", err.c_str());
-    for (size_t i = 0; i < n_gates; ++i) {
-        const int k = gates[i].kind;
-        if (gates[i].param >= 0 && k != SV_GATE_RX && k != SV_GATE_RY && k != SV_GATE_RZ)
-            return fail(SV_EUNSUPPORTED, "gate %zu: only RX, RY and RZ may reference parameters", i);
-    }
-    const int B = s->batch;
-    const uint64_t N = 1ull << s->n;
-    const size_t state_bytes = (size_t)N * s->amp_bytes;
-    st = ensure_device_buf(&s->d_work, &s->d_work_cap, 2 * (size_t)B * state_bytes, "hipMalloc(adjoint work)");
-    if (st != SV_OK) return st;
-    const size_t ngrad = std::max<size_t>(1, (size_t)B * n_params);
-    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_grad), &s->d_grad_cap,
-                           ngrad * sizeof(double), "hipMalloc(grad)");
-    if (st != SV_OK) return st;
-    const size_t np = reduce_partials_size(s->n) * (size_t)B + (size_t)B;
-    st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap, np * sizeof(double),
-                           "hipMalloc(reduce)");
-    if (st != SV_OK) return st;
-    char *psi = static_cast<char *>(s->d_work);
-    char *lam = psi + (size_t)B * state_bytes;
-    const int dt = (int)s->dt;
-
-    // forward: psi = U |0...0> for every batch entry
-    SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
-    PlanOptions po = plan_options(s);
-    po.basis_known = true;
-    po.basis_j = 0;
-    {
-        Plan p = build_plan(s->n, gates, n_gates, po);
-        st = run_plan(s, psi, B, p, gates, params, n_params);
+    return guarded([&]() -> sv_status {
+        sv_status st = check_handle(s);
         if (st != SV_OK) return st;
-    }
-    SV_HIP(hipMemcpyAsync(s->buf, psi, (size_t)B * state_bytes, hipMemcpyDeviceToDevice, s->stream),
-           "hipMemcpyAsync(final states)");
-    s->basis_known = false;
-    // f = <Z_q> and lambda = Z_q psi
-    double *d_out = s->d_red + reduce_partials_size(s->n) * (size_t)B;
-    SV_HIP(launch_reduce(dt, psi, s->n, B, qubit, s->d_red, d_out, s->stream), "launch reduce");
-    if (expect) {
-        st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, (size_t)B * sizeof(double),
-                             "hipHostMalloc(out)");
+        if (qubit < 0 || qubit >= s->n) return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, s->n);
+        if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+        if (n_params && !grad) return fail(SV_EINVAL, "grad is NULL");
+        std::string err;
+        if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
+            return fail(SV_EINVAL, "%s", err.c_str());
+        for (size_t i = 0; i < n_gates; ++i) {
+            const int k = gates[i].kind;
+            if (gates[i].param >= 0 && k != SV_GATE_RX && k != SV_GATE_RY && k != SV_GATE_RZ)
+                return fail(SV_EUNSUPPORTED, "gate %zu: only RX, RY and RZ may reference parameters", i);
+        }
+        const int B = s->batch;
+        const uint64_t N = 1ull << s->n;
+        const size_t state_bytes = (size_t)N * s->amp_bytes;
+        st = ensure_device_buf(&s->d_work, &s->d_work_cap, 2 * (size_t)B * state_bytes, "hipMalloc(adjoint work)");
         if (st != SV_OK) return st;
-        SV_HIP(hipMemcpyAsync(s->h_out, d_out, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s->stream),
-               "hipMemcpyAsync(expect)");
-        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-        std::memcpy(expect, s->h_out, (size_t)B * sizeof(double));
-    }
-    SV_HIP(launch_copy_z(dt, psi, lam, N, B, qubit, s->stream), "launch copy_z");
-    SV_HIP(hipMemsetAsync(s->d_grad, 0, ngrad * sizeof(double), s->stream), "hipMemsetAsync(grad)");
+        const size_t ngrad = std::max<size_t>(1, (size_t)B * n_params);
+        st = ensure_device_buf(reinterpret_cast<void **>(&s->d_grad), &s->d_grad_cap,
+                               ngrad * sizeof(double), "hipMalloc(grad)");
+        if (st != SV_OK) return st;
+        const size_t np = reduce_partials_size(s->n) * (size_t)B + (size_t)B;
+        st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap, np * sizeof(double),
+                               "hipMalloc(reduce)");
+        if (st != SV_OK) return st;
+        char *psi = static_cast<char *>(s->d_work);
+        char *lam = psi + (size_t)B * state_bytes;
+        const int dt = (int)s->dt;
 
-    // reverse sweep on the 2B states [psi | lambda] with the inverse gates;
-    // parameter rows are duplicated and negated (U(t)^dagger = U(-t) for rotations)
-    std::vector<double> pneg((size_t)2 * B * std::max<size_t>(n_params, 1), 0.0);
-    for (int b = 0; b < B; ++b)
-        for (size_t p = 0; p < n_params; ++p) {
-            pneg[(size_t)b * n_params + p] = -params[(size_t)b * n_params + p];
-            pneg[(size_t)(B + b) * n_params + p] = -params[(size_t)b * n_params + p];
-        }
-    auto inverse = [](sv_gate g) {
-        switch (g.kind) {
-        case SV_GATE_S: g.kind = SV_GATE_SDG; break;
-        case SV_GATE_SDG: g.kind = SV_GATE_S; break;
-        case SV_GATE_T: g.kind = SV_GATE_TDG; break;
-        case SV_GATE_TDG: g.kind = SV_GATE_T; break;
-        case SV_GATE_RX: case SV_GATE_RY: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CPHASE:
-            if (g.param < 0) g.angle = -g.angle;   // referenced angles come from the negated table
-            break;
-        default: break;   // X, Y, Z, H, CNOT, CZ, SWAP, MARK, I are self-inverse
-        }
-        return g;
-    };
-    PlanOptions pr = plan_options(s);
-    pr.basis_known = false;
-    std::vector<sv_gate> seg;
-    auto flush = [&]() -> sv_status {
-        if (seg.empty()) return SV_OK;
-        Plan p = build_plan(s->n, seg.data(), seg.size(), pr);
-        sv_status r = run_plan(s, psi, 2 * B, p, seg.data(), pneg.data(), n_params);
-        seg.clear();
-        return r;
-    };
-    for (size_t i = n_gates; i-- > 0;) {
-        const sv_gate &g = gates[i];
-        if (g.param >= 0) {
-            st = flush();
+        // forward: psi = U |0...0> for every batch entry
+        SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
+        PlanOptions po = plan_options(s);
+        po.basis_known = true;
+        po.basis_j = 0;
+        {
+            Plan p = build_plan(s->n, gates, n_gates, po);
+            st = run_plan(s, psi, B, p, gates, params, n_params);
             if (st != SV_OK) return st;
-            const int pauli = g.kind == SV_GATE_RX ? 1 : g.kind == SV_GATE_RY ? 2 : 3;
-            SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, g.q0, pauli, s->d_red, s->d_grad,
-                                              n_params, (uint64_t)g.param, s->stream),
-                   "launch pauli_ip");
         }
-        seg.push_back(inverse(g));
-    }
-    st = flush();
-    if (st != SV_OK) return st;
-    if (n_params) {
-        std::vector<double> tmp((size_t)B * n_params);
-        SV_HIP(hipMemcpyAsync(tmp.data(), s->d_grad, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,
-                              s->stream),
-               "hipMemcpyAsync(grad)");
-        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-        std::memcpy(grad, tmp.data(), tmp.size() * sizeof(double));
-    } else {
-        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-    }
-    return SV_OK;
+        SV_HIP(hipMemcpyAsync(s->buf, psi, (size_t)B * state_bytes, hipMemcpyDeviceToDevice, s->stream),
+               "hipMemcpyAsync(final states)");
+        s->basis_known = false;
+        // f = <Z_q> and lambda = Z_q psi
+        double *d_out = s->d_red + reduce_partials_size(s->n) * (size_t)B;
+        SV_HIP(launch_reduce(dt, psi, s->n, B, qubit, s->d_red, d_out, s->stream), "launch reduce");
+        if (expect) {
+            st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, (size_t)B * sizeof(double),
+                                 "hipHostMalloc(out)");
+            if (st != SV_OK) return st;
+            SV_HIP(hipMemcpyAsync(s->h_out, d_out, (size_t)B * sizeof(double), hipMemcpyDeviceToHost, s->stream),
+                   "hipMemcpyAsync(expect)");
+            SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+            std::memcpy(expect, s->h_out, (size_t)B * sizeof(double));
+        }
+        SV_HIP(launch_copy_z(dt, psi, lam, N, B, qubit, s->stream), "launch copy_z");
+        SV_HIP(hipMemsetAsync(s->d_grad, 0, ngrad * sizeof(double), s->stream), "hipMemsetAsync(grad)");
+
+        // reverse sweep on the 2B states [psi | lambda] with the inverse gates;
+        // parameter rows are duplicated and negated (U(t)^dagger = U(-t) for rotations)
+        std::vector<double> pneg((size_t)2 * B * std::max<size_t>(n_params, 1), 0.0);
+        for (int b = 0; b < B; ++b)
+            for (size_t p = 0; p < n_params; ++p) {
+                pneg[(size_t)b * n_params + p] = -params[(size_t)b * n_params + p];
+                pneg[(size_t)(B + b) * n_params + p] = -params[(size_t)b * n_params + p];
+            }
+        auto inverse = [](sv_gate g) {
+            switch (g.kind) {
+            case SV_GATE_S: g.kind = SV_GATE_SDG; break;
+            case SV_GATE_SDG: g.kind = SV_GATE_S; break;
+            case SV_GATE_T: g.kind = SV_GATE_TDG; break;
+            case SV_GATE_TDG: g.kind = SV_GATE_T; break;
+            case SV_GATE_RX: case SV_GATE_RY: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CPHASE:
+                if (g.param < 0) g.angle = -g.angle;   // referenced angles come from the negated table
+                break;
+            default: break;   // X, Y, Z, H, CNOT, CZ, SWAP, MARK, I are self-inverse
+            }
+            return g;
+        };
+        PlanOptions pr = plan_options(s);
+        pr.basis_known = false;
+        std::vector<sv_gate> seg;
+        auto flush = [&]() -> sv_status {
+            if (seg.empty()) return SV_OK;
+            Plan p = build_plan(s->n, seg.data(), seg.size(), pr);
+            sv_status r = run_plan(s, psi, 2 * B, p, seg.data(), pneg.data(), n_params);
+            seg.clear();
+            return r;
+        };
+        for (size_t i = n_gates; i-- > 0;) {
+            const sv_gate &g = gates[i];
+            if (g.param >= 0) {
+                st = flush();
+                if (st != SV_OK) return st;
+                const int pauli = g.kind == SV_GATE_RX ? 1 : g.kind == SV_GATE_RY ? 2 : 3;
+                SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, g.q0, pauli, s->d_red, s->d_grad,
+                                                  n_params, (uint64_t)g.param, s->stream),
+                       "launch pauli_ip");
+            }
+            seg.push_back(inverse(g));
+        }
+        st = flush();
+        if (st != SV_OK) return st;
+        if (n_params) {
+            std::vector<double> tmp((size_t)B * n_params);
+            SV_HIP(hipMemcpyAsync(tmp.data(), s->d_grad, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                  s->stream),
+                   "hipMemcpyAsync(grad)");
+            SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+            std::memcpy(grad, tmp.data(), tmp.size() * sizeof(double));
+        } else {
+            SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+        }
+        return SV_OK;
+    });
 }
 
 // ---------------------------------------------------------------------------
 // Diagnostics (include/sv_debug.h)
 
+static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_gates,
+                               const double *params, size_t n_params, const int64_t *opts,
+                               void *out, size_t cap);
+
 int64_t sv_debug_plan(int n, int dtype, const sv_gate *gates, size_t n_gates, const double *params,
                       size_t n_params, const int64_t *opts, void *out, size_t cap) {
+    int64_t r = 0;
+    const sv_status st = guarded([&]() -> sv_status {
+        r = debug_plan_impl(n, dtype, gates, n_gates, params, n_params, opts, out, cap);
+        return SV_OK;
+    });
+    return st == SV_OK ? r : (int64_t)st;
+}
+
+static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_gates,
+                               const double *params, size_t n_params, const int64_t *opts,
+                               void *out, size_t cap) {
     if (n < 1 || n > 34 || (dtype != SV_C64 && dtype != SV_C128)) {
         fail(SV_EINVAL, "bad n or dtype");
         return SV_EINVAL;

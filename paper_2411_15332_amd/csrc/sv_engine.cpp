@@ -290,136 +290,146 @@ extern "C" {
 
 sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams, size_t hbm_budget_bytes,
                            sv_engine *out) {
-    if (!out) return fail(SV_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
-    if (max_batch < 1 || max_batch > 65535) return fail(SV_EINVAL, "max_batch %d outside 1..65535", max_batch);
-    if (n_streams < 1 || n_streams > 16) return fail(SV_EINVAL, "n_streams %d outside 1..16", n_streams);
-    auto *e = new (std::nothrow) sv_engine_s();
-    if (!e) return fail(SV_ENOMEM, "host allocation failed");
-    e->dt = dtype;
-    e->max_batch = max_batch;
-    e->n_streams = n_streams;
-    e->budget = hbm_budget_bytes;
-    e->amp_bytes = dtype == SV_C128 ? 16 : 8;
-    e->small_max = dtype == SV_C128 ? kSmallMaxQubitsC128 : kSmallMaxQubitsC64;
-    hipError_t err = hipGetDevice(&e->device);
-    for (int i = 0; i < n_streams && err == hipSuccess; ++i) {
-        auto s = std::make_unique<Slot>();
-        err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
-        if (err == hipSuccess) err = hipEventCreateWithFlags(&s->done, hipEventDisableTiming);
-        e->slots.push_back(std::move(s));
-    }
-    if (err != hipSuccess) {
-        sv_engine_free(e);
-        return hip_fail(err, "engine streams");
-    }
-    *out = e;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!out) return fail(SV_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
+        if (max_batch < 1 || max_batch > 65535) return fail(SV_EINVAL, "max_batch %d outside 1..65535", max_batch);
+        if (n_streams < 1 || n_streams > 16) return fail(SV_EINVAL, "n_streams %d outside 1..16", n_streams);
+        auto *e = new (std::nothrow) sv_engine_s();
+        if (!e) return fail(SV_ENOMEM, "host allocation failed");
+        e->dt = dtype;
+        e->max_batch = max_batch;
+        e->n_streams = n_streams;
+        e->budget = hbm_budget_bytes;
+        e->amp_bytes = dtype == SV_C128 ? 16 : 8;
+        e->small_max = dtype == SV_C128 ? kSmallMaxQubitsC128 : kSmallMaxQubitsC64;
+        hipError_t err = hipGetDevice(&e->device);
+        for (int i = 0; i < n_streams && err == hipSuccess; ++i) {
+            auto s = std::make_unique<Slot>();
+            err = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&s->done, hipEventDisableTiming);
+            e->slots.push_back(std::move(s));
+        }
+        if (err != hipSuccess) {
+            sv_engine_free(e);
+            return hip_fail(err, "engine streams");
+        }
+        *out = e;
+        return SV_OK;
+    });
 }
 
 sv_status sv_engine_free(sv_engine e) {
-    if (!e) return SV_OK;
-    hipSetDevice(e->device);
-    hipError_t first = hipSuccess;
-    for (auto &sp : e->slots) {
-        Slot &s = *sp;
-        if (s.stream) {
-            hipError_t r = hipStreamSynchronize(s.stream);
-            if (first == hipSuccess) first = r;
+    return guarded([&]() -> sv_status {
+        if (!e) return SV_OK;
+        hipSetDevice(e->device);
+        hipError_t first = hipSuccess;
+        for (auto &sp : e->slots) {
+            Slot &s = *sp;
+            if (s.stream) {
+                hipError_t r = hipStreamSynchronize(s.stream);
+                if (first == hipSuccess) first = r;
+            }
+            if (s.d_state) hipFree(s.d_state);
+            if (s.d_stage) hipFree(s.d_stage);
+            if (s.d_res) hipFree(s.d_res);
+            if (s.h_stage) hipHostFree(s.h_stage);
+            if (s.h_res) hipHostFree(s.h_res);
+            s.h.buf = nullptr;
+            s.h.owned = false;
+            release_handle_buffers(&s.h);
+            if (s.done) hipEventDestroy(s.done);
+            if (s.stream) hipStreamDestroy(s.stream);
         }
-        if (s.d_state) hipFree(s.d_state);
-        if (s.d_stage) hipFree(s.d_stage);
-        if (s.d_res) hipFree(s.d_res);
-        if (s.h_stage) hipHostFree(s.h_stage);
-        if (s.h_res) hipHostFree(s.h_res);
-        s.h.buf = nullptr;
-        s.h.owned = false;
-        release_handle_buffers(&s.h);
-        if (s.done) hipEventDestroy(s.done);
-        if (s.stream) hipStreamDestroy(s.stream);
-    }
-    delete e;
-    if (first != hipSuccess) return hip_fail(first, "engine shutdown");
-    return SV_OK;
+        delete e;
+        if (first != hipSuccess) return hip_fail(first, "engine shutdown");
+        return SV_OK;
+    });
 }
 
 sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate *gates, size_t n_gates,
                            const double *params, size_t n_params, int qubit) {
-    if (!e) return fail(SV_EINVAL, "null engine");
-    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
-    if (n_qubits > 30) return fail(SV_EUNSUPPORTED, "serving requests are limited to 30 qubits");
-    if (qubit < 0 || qubit >= n_qubits) return fail(SV_EINVAL, "qubit %d out of range", qubit);
-    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
-    if (n_params && !params) return fail(SV_EINVAL, "params is NULL");
-    std::string err;
-    if (!validate_gates(n_qubits, gates, n_gates, n_params, params != nullptr || n_params == 0, err))
-        return fail(SV_EINVAL, "%s", err.c_str());
-    const std::string key = template_key(n_qubits, qubit, n_params, gates, n_gates);
-    auto it = e->templates.find(key);
-    if (it == e->templates.end()) {
-        auto t = std::make_shared<Template>();
-        t->n = n_qubits;
-        t->qubit = qubit;
-        t->gates.assign(gates, gates + n_gates);
-        t->n_params = n_params;
-        t->small = n_qubits <= e->small_max;
-        t->plan = build_plan(n_qubits, t->gates.data(), n_gates, engine_plan_options(e, t->small));
-        it = e->templates.emplace(key, std::move(t)).first;
-    }
-    Request r;
-    r.id = id;
-    r.t = it->second;
-    r.params.assign(params, params + n_params);
-    e->queue.push_back(std::move(r));
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!e) return fail(SV_EINVAL, "null engine");
+        if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
+        if (n_qubits > 30) return fail(SV_EUNSUPPORTED, "serving requests are limited to 30 qubits");
+        if (qubit < 0 || qubit >= n_qubits) return fail(SV_EINVAL, "qubit %d out of range", qubit);
+        if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+        if (n_params && !params) return fail(SV_EINVAL, "params is NULL");
+        std::string err;
+        if (!validate_gates(n_qubits, gates, n_gates, n_params, params != nullptr || n_params == 0, err))
+            return fail(SV_EINVAL, "%s", err.c_str());
+        const std::string key = template_key(n_qubits, qubit, n_params, gates, n_gates);
+        auto it = e->templates.find(key);
+        if (it == e->templates.end()) {
+            auto t = std::make_shared<Template>();
+            t->n = n_qubits;
+            t->qubit = qubit;
+            t->gates.assign(gates, gates + n_gates);
+            t->n_params = n_params;
+            t->small = n_qubits <= e->small_max;
+            t->plan = build_plan(n_qubits, t->gates.data(), n_gates, engine_plan_options(e, t->small));
+            it = e->templates.emplace(key, std::move(t)).first;
+        }
+        Request r;
+        r.id = id;
+        r.t = it->second;
+        r.params.assign(params, params + n_params);
+        e->queue.push_back(std::move(r));
+        return SV_OK;
+    });
 }
 
 sv_status sv_engine_poll(sv_engine e, int64_t wait_us, uint64_t *ids, double *values, size_t cap,
                          size_t *count) {
-    if (!e || !count) return fail(SV_EINVAL, "null argument");
-    *count = 0;
-    if (cap && (!ids || !values)) return fail(SV_EINVAL, "ids or values is NULL");
-    hipSetDevice(e->device);
-    const auto t0 = std::chrono::steady_clock::now();
-    for (;;) {
-        sv_status st = retire(e);
-        if (st != SV_OK) return st;
-        st = launch_ready(e);
-        if (st != SV_OK) return st;
-        if (!e->finished.empty() || wait_us <= 0) break;
-        bool busy = false;
-        for (auto &s : e->slots) busy = busy || s->busy;
-        if (!busy && e->queue.empty()) break;
-        const auto el = std::chrono::duration_cast<std::chrono::microseconds>(
-            std::chrono::steady_clock::now() - t0).count();
-        if (el >= wait_us) break;
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
-    }
-    size_t c = 0;
-    while (c < cap && !e->finished.empty()) {
-        ids[c] = e->finished.front().first;
-        values[c] = e->finished.front().second;
-        e->finished.pop_front();
-        ++c;
-    }
-    *count = c;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!e || !count) return fail(SV_EINVAL, "null argument");
+        *count = 0;
+        if (cap && (!ids || !values)) return fail(SV_EINVAL, "ids or values is NULL");
+        hipSetDevice(e->device);
+        const auto t0 = std::chrono::steady_clock::now();
+        for (;;) {
+            sv_status st = retire(e);
+            if (st != SV_OK) return st;
+            st = launch_ready(e);
+            if (st != SV_OK) return st;
+            if (!e->finished.empty() || wait_us <= 0) break;
+            bool busy = false;
+            for (auto &s : e->slots) busy = busy || s->busy;
+            if (!busy && e->queue.empty()) break;
+            const auto el = std::chrono::duration_cast<std::chrono::microseconds>(
+                std::chrono::steady_clock::now() - t0).count();
+            if (el >= wait_us) break;
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        size_t c = 0;
+        while (c < cap && !e->finished.empty()) {
+            ids[c] = e->finished.front().first;
+            values[c] = e->finished.front().second;
+            e->finished.pop_front();
+            ++c;
+        }
+        *count = c;
+        return SV_OK;
+    });
 }
 
 sv_status sv_engine_stats(sv_engine e, int64_t out[8]) {
-    if (!e || !out) return fail(SV_EINVAL, "null argument");
-    int64_t inflight = 0;
-    for (auto &s : e->slots) inflight += (int64_t)s->ids.size();
-    out[0] = (int64_t)e->queue.size();
-    out[1] = inflight;
-    out[2] = e->completed;
-    out[3] = e->groups;
-    out[4] = (int64_t)e->bytes_held;
-    out[5] = e->largest;
-    out[6] = e->deferred;
-    out[7] = e->small_groups;
-    return SV_OK;
+    return guarded([&]() -> sv_status {
+        if (!e || !out) return fail(SV_EINVAL, "null argument");
+        int64_t inflight = 0;
+        for (auto &s : e->slots) inflight += (int64_t)s->ids.size();
+        out[0] = (int64_t)e->queue.size();
+        out[1] = inflight;
+        out[2] = e->completed;
+        out[3] = e->groups;
+        out[4] = (int64_t)e->bytes_held;
+        out[5] = e->largest;
+        out[6] = e->deferred;
+        out[7] = e->small_groups;
+        return SV_OK;
+    });
 }
 
 }  // extern "C"

@@ -1,6 +1,9 @@
 // Internal declarations shared by the C-ABI sources (handles, plan upload).
 #pragma once
 
+#include <exception>
+#include <new>
+
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -12,6 +15,22 @@
 namespace sv {
 
 sv_status fail(sv_status st, const char *fmt, ...);
+
+// Runs an entry point's body so that no C++ exception crosses the C ABI: a
+// failed host allocation is SV_ENOMEM, a broken internal invariant
+// SV_EUNSUPPORTED (with the reason in sv_last_error).
+template <class F>
+sv_status guarded(F &&body) noexcept {
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(SV_ENOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(SV_EUNSUPPORTED, "internal error: %s", e.what());
+    } catch (...) {
+        return fail(SV_EUNSUPPORTED, "internal error");
+    }
+}
 sv_status hip_fail(hipError_t e, const char *what);
 size_t align_up(size_t x, size_t a);
 

@@ -248,26 +248,28 @@ struct PassTraits;
 template <>
 struct PassTraits<double> {
     static constexpr int R = kRegBitsC128;
+    static constexpr int W = kThreadBitsC128;
 };
 template <>
 struct PassTraits<float> {
     static constexpr int R = kRegBitsC64;
+    static constexpr int W = kThreadBitsC64;
 };
 
-// Thread part of a layout: global-index bits and byte address of the LDS slot.
-// Entries of thread bits at or above the workgroup's width are zero, so the
-// loop runs over every possible bit without a data-dependent trip count.
-__device__ __forceinline__ void thr_part(const DevLayout &L, int tid, int slot_shift,
-                                         uint64_t &g, uint32_t &s) {
+// Thread part of a layout: global-index bits and LDS slot index. Entries of
+// thread bits at or above the workgroup's width are zero, so the loop runs
+// over every possible bit without a data-dependent trip count.
+template <int W>
+__device__ __forceinline__ void thr_part(const DevLayout &L, int tid, uint64_t &g, uint32_t &s) {
     g = L.goff_xor;
     uint32_t sl = L.slot_xor;
 #pragma unroll
-    for (int b = 0; b < kMaxThreadBits; ++b) {
+    for (int b = 0; b < W; ++b) {
         const bool on = (tid >> b) & 1;
         g ^= on ? L.thr_goff[b] : 0ull;
         sl ^= on ? L.thr_slot[b] : 0u;
     }
-    s = sl << slot_shift;
+    s = sl;
 }
 
 // Register part: one value per slot j, XOR of the per-bit entries of j.
@@ -278,10 +280,56 @@ __device__ __forceinline__ void reg_goff(const DevLayout &L, uint64_t (&g)[1 << 
     for (int j = 1; j < (1 << R); ++j) g[j] = g[j & (j - 1)] ^ L.reg_goff[__builtin_ctz(j)];
 }
 template <int R>
-__device__ __forceinline__ void reg_slot(const DevLayout &L, int slot_shift, uint32_t (&s)[1 << R]) {
+__device__ __forceinline__ void reg_slot(const DevLayout &L, uint32_t (&s)[1 << R]) {
     s[0] = 0;
 #pragma unroll
-    for (int j = 1; j < (1 << R); ++j) s[j] = s[j & (j - 1)] ^ (L.reg_slot[__builtin_ctz(j)] << slot_shift);
+    for (int j = 1; j < (1 << R); ++j) s[j] = s[j & (j - 1)] ^ L.reg_slot[__builtin_ctz(j)];
+}
+
+// Slot index with bit `lo`-position removed (lo = 2^b - 1): the half-tile
+// address of a slot whose bit b is fixed by the half being exchanged.
+__device__ __forceinline__ uint32_t drop_bit(uint32_t x, uint32_t lo) {
+    return (x & lo) | ((x >> 1) & ~lo);
+}
+
+// Half-tile exchange, halves chosen by register bit P: every thread takes
+// part in both halves with half of its registers.
+template <int P, typename T, int NR>
+__device__ __forceinline__ void exch_reg_halves(cpx<T> (&a)[NR], char *ldsb, uint32_t tw,
+                                                const uint32_t (&sw)[NR], uint32_t tr,
+                                                const uint32_t (&sr)[NR]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (((j >> P) & 1) == h) *reinterpret_cast<cpx<T> *>(ldsb + (tw ^ sw[j])) = a[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (((j >> P) & 1) == h) a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (tr ^ sr[j]));
+    }
+}
+
+// Half-tile exchange, halves chosen by a thread bit: the threads whose bit is
+// h move all of their registers in half h.
+template <typename T, int NR>
+__device__ __forceinline__ void exch_thr_halves(cpx<T> (&a)[NR], char *ldsb, uint32_t tw,
+                                                const uint32_t (&sw)[NR], uint32_t tr,
+                                                const uint32_t (&sr)[NR], int mine) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();
+        if (mine == h) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) *reinterpret_cast<cpx<T> *>(ldsb + (tw ^ sw[j])) = a[j];
+        }
+        __syncthreads();
+        if (mine == h) {
+#pragma unroll
+            for (int j = 0; j < NR; ++j) a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (tr ^ sr[j]));
+        }
+    }
 }
 
 __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
@@ -290,14 +338,15 @@ __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
+__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
                                               const DevPass *__restrict__ passes, int pass_idx,
                                               const DevLayout *__restrict__ layouts,
                                               const DevOp *__restrict__ ops, uint64_t ops_stride) {
     constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
     constexpr int NR = 1 << R;
     constexpr int SH = sizeof(T) == 8 ? 4 : 3;   // log2 of the slot size in bytes
-    __shared__ cpx<T> lds[NR << kMaxThreadBits];
+    __shared__ cpx<T> lds[(NR << W) / 2];        // half a tile
     char *const ldsb = reinterpret_cast<char *>(lds);
 
     const DevPass &P = passes[pass_idx];
@@ -320,7 +369,7 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
         const DevLayout &L = LB[0];
         uint64_t gthr;
         uint32_t sdummy;
-        thr_part(L, tid, SH, gthr, sdummy);
+        thr_part<W>(L, tid, gthr, sdummy);
         uint64_t greg[NR];
         reg_goff<R>(L, greg);
         const cpx<T> *tp = st + (base | gthr);
@@ -358,20 +407,25 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
             const DevOp nxt = opb[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
             switch (op.code) {
             case OP_EXCH: {
+                const uint32_t lo = (1u << op.sb) - 1u;
                 uint64_t gd;
-                uint32_t sthr, sreg[NR];
-                thr_part(LB[op.a], tid, SH, gd, sthr);
-                reg_slot<R>(LB[op.a], SH, sreg);
-                __syncthreads();
+                uint32_t tw, tr, sw[NR], sr[NR];
+                thr_part<W>(LB[op.a], tid, gd, tw);
+                thr_part<W>(LB[op.b], tid, gd, tr);
+                reg_slot<R>(LB[op.a], sw);
+                reg_slot<R>(LB[op.b], sr);
+                tw = drop_bit(tw, lo) << SH;
+                tr = drop_bit(tr, lo) << SH;
 #pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    *reinterpret_cast<cpx<T> *>(ldsb + (sthr ^ sreg[j])) = a[j];
-                __syncthreads();
-                thr_part(LB[op.b], tid, SH, gd, sthr);
-                reg_slot<R>(LB[op.b], SH, sreg);
-#pragma unroll
-                for (int j = 0; j < NR; ++j)
-                    a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (sthr ^ sreg[j]));
+                for (int j = 0; j < NR; ++j) {
+                    sw[j] = drop_bit(sw[j], lo) << SH;
+                    sr[j] = drop_bit(sr[j], lo) << SH;
+                }
+                if ((op.sa & ~SRC_POS_MASK) == SRC_REG) {
+                    SV_SWITCH_A(op.sa & SRC_POS_MASK, exch_reg_halves<PA>(a, ldsb, tw, sw, tr, sr))
+                } else {
+                    exch_thr_halves(a, ldsb, tw, sw, tr, sr, (tid >> (op.sa & SRC_POS_MASK)) & 1);
+                }
                 break;
             }
             case OP_D1R: {
@@ -467,7 +521,7 @@ __global__ __launch_bounds__(256) void k_pass(cpx<T> *__restrict__ state, uint64
         const DevLayout &L = LB[P.store_layout];
         uint64_t gthr;
         uint32_t sdummy;
-        thr_part(L, tid, SH, gthr, sdummy);
+        thr_part<W>(L, tid, gthr, sdummy);
         uint64_t greg[NR];
         reg_goff<R>(L, greg);
         cpx<T> *tp = st + (base | gthr);
@@ -865,6 +919,13 @@ hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch, ui
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const DevPass *d_passes,
                        int pass_idx, const DevPass &h_pass, const DevLayout *d_layouts,
                        const DevOp *d_ops, uint64_t ops_stride, hipStream_t st) {
+    // The kernel is compiled for one tile geometry per precision; a pass that
+    // does not match it is refused before launch.
+    const int R = dt == 2 ? kRegBitsC128 : kRegBitsC64;
+    const int W = dt == 2 ? kThreadBitsC128 : kThreadBitsC64;
+    if (h_pass.w < kMinThreadBits || h_pass.w > W || h_pass.k != h_pass.w + R ||
+        h_pass.tiles != (n_amps >> h_pass.k) || (h_pass.tiles << h_pass.k) != n_amps)
+        return hipErrorInvalidValue;
     const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
     const dim3 block(1u << h_pass.w);
     if (dt == 2)

@@ -10,12 +10,18 @@
 
 namespace sv {
 
-// Register bits per thread of the tiled pass kernel, per precision.
-// complex128: 16 amplitudes (64 VGPRs); complex64: 32 amplitudes (64 VGPRs).
+// Tile geometry of the pass kernel, per precision: 2^R amplitudes in the
+// registers of each of 2^W threads, a tile of 2^(R+W) amplitudes, exchanged
+// through a half-tile LDS buffer.
+//   complex128: R = 4, W = 8: 4096 amplitudes, 32 KiB of LDS per workgroup
+//   complex64:  R = 5, W = 8: 8192 amplitudes, 32 KiB of LDS per workgroup
 constexpr int kRegBitsC128 = 4;
+constexpr int kThreadBitsC128 = 8;
 constexpr int kRegBitsC64 = 5;
-constexpr int kMaxThreadBits = 8;    // 256 threads per workgroup
+constexpr int kThreadBitsC64 = 8;
 constexpr int kMinThreadBits = 6;    // at least one full 64-lane wave
+static_assert(kThreadBitsC128 <= kLayoutThreadBits && kThreadBitsC64 <= kLayoutThreadBits, "");
+static_assert(kRegBitsC128 <= kLayoutRegBits && kRegBitsC64 <= kLayoutRegBits, "");
 
 // Largest state (qubits) the one-workgroup kernel keeps in 64 KiB of LDS.
 constexpr int kSmallMaxQubitsC128 = 12;

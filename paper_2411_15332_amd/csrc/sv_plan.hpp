@@ -31,7 +31,11 @@ enum : uint8_t {
 };
 
 enum OpCode : uint8_t {
-    OP_EXCH = 1,     // write tile to LDS in layout a, read it back in layout b (pass-relative)
+    OP_EXCH = 1,     // write the tile to LDS in layout a, read it back in layout b
+                     // (pass-relative), in two halves through a half-tile buffer: the
+                     // half is the value of label sb, held at the same position (source
+                     // sa: SRC_REG | p or SRC_THR | s) with the same XOR bit in both
+                     // layouts; slots drop bit sb
     OP_D1R = 2,      // amp *= f d[bit p of j], f = 1; a = p; payload d0, d1
     OP_UD1 = 3,      // per-thread factor f *= d[bit]; sa = THR/TILE source; payload d0, d1
     OP_UD2 = 4,      // f *= d[(bit sa << 1) | bit sb]; payload d[4]
@@ -62,25 +66,29 @@ struct DevOp {
     uint64_t payload[8];
 };
 
+// Largest tile geometry the plan records describe.
+constexpr int kLayoutThreadBits = 10;
+constexpr int kLayoutRegBits = 6;
+
 // Per-layout tables, precomputed on the host. The global index of the
 // amplitude in (t, j) is  tile_base | gthr(t) | greg(j)  (disjoint bits) with
 //   gthr(t) = goff_xor ^ XOR_{s: t_s = 1} thr_goff[s],
 //   greg(j) = reg_goff_xor ^ XOR_{p: j_p = 1} reg_goff[p],
 // and its LDS slot (swizzled) is  sthr(t) ^ sreg(j), built the same way.
-struct DevLayout {
-    uint64_t thr_goff[8];
-    uint64_t reg_goff[8];
-    uint32_t thr_slot[8];
-    uint32_t reg_slot[8];
+// Entries of thread bits at or above the workgroup's width are zero.
+struct DevLayout {                           // 256 bytes
+    uint64_t thr_goff[kLayoutThreadBits];
+    uint64_t reg_goff[kLayoutRegBits];
     uint64_t goff_xor;       // global offset of the XOR-mask labels held by thread bits
+    uint64_t reg_goff_xor;   // global offset of the XOR-mask labels held by register bits
+    uint32_t thr_slot[kLayoutThreadBits];
+    uint32_t reg_slot[kLayoutRegBits];
     uint32_t slot_xor;       // LDS slot contribution of the whole XOR mask
     uint32_t flags;          // LAYOUT_PAIR_IO: slots j, j^1 are adjacent in HBM (complex64 16-byte I/O)
-    uint8_t reg_local[8];    // label held by register bit p
-    uint8_t thr_local[8];    // label held by thread bit s
     uint32_t xor_local;      // XOR mask c on the labels
-    uint32_t pad0;
-    uint64_t reg_goff_xor;   // global offset of the XOR-mask labels held by register bits
-    uint8_t pad[16];
+    uint8_t thr_local[kLayoutThreadBits];    // label held by thread bit s
+    uint8_t reg_local[kLayoutRegBits];       // label held by register bit p
+    uint8_t pad[20];
 };
 
 enum : uint32_t { LAYOUT_PAIR_IO = 1u };

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <stdexcept>
 
 #include "sv_swizzle.hpp"
 
@@ -227,12 +228,12 @@ struct PassCtx {
     uint8_t q[32];
     int label_of[64];
     // layout state: position of every label and the XOR mask
-    int reg_label[8], thr_label[8];
+    int reg_label[kLayoutRegBits], thr_label[kLayoutThreadBits];
     int pos_reg[32], pos_thr[32];   // register / thread bit holding label l, or -1
     uint32_t xmask = 0;
     int layout_begin = 0;
     int cur_layout = -1;            // pass-relative index of the materialized state, -1: not yet
-    Pending pend[8];
+    Pending pend[kLayoutRegBits];
     bool f_used = false;
     int h_count = 0;
     int first_payload = -1;
@@ -246,30 +247,57 @@ struct PassCtx {
         return u;
     }
 
-    void set_state(const int *regl, const int *thrl, uint32_t xm) {
+    // A layout state: the label of every register and thread bit, and the
+    // XOR mask. `fixed_thr`: thread bits below it are pinned by the layout's
+    // kind (lanes of a storable layout hold labels v..v+5; the first m lanes of
+    // a general layout hold labels with independent swizzle images).
+    struct LState {
+        int reg[kLayoutRegBits];
+        int thr[kLayoutThreadBits];
+        uint32_t xmask;
+        int fixed_thr;
+        bool storable;
+    };
+
+    LState save() const {
+        LState st{};
+        for (int p = 0; p < opt.R; ++p) st.reg[p] = reg_label[p];
+        for (int t = 0; t < w; ++t) st.thr[t] = thr_label[t];
+        st.xmask = xmask;
+        st.fixed_thr = w;
+        st.storable = false;
+        return st;
+    }
+
+    void load(const LState &st) {
         for (int l = 0; l < 32; ++l) pos_reg[l] = pos_thr[l] = -1;
-        for (int p = 0; p < opt.R; ++p) { reg_label[p] = regl[p]; pos_reg[regl[p]] = p; }
-        for (int s = 0; s < w; ++s) { thr_label[s] = thrl[s]; pos_thr[thrl[s]] = s; }
-        xmask = xm;
+        for (int p = 0; p < opt.R; ++p) { reg_label[p] = st.reg[p]; pos_reg[st.reg[p]] = p; }
+        for (int t = 0; t < w; ++t) { thr_label[t] = st.thr[t]; pos_thr[st.thr[t]] = t; }
+        xmask = st.xmask;
         cur_layout = -1;
     }
 
     // regs_u: R - v labels from U_labels(); lanes hold labels v..v+5.
-    void storable_state(uint64_t regs_u) {
-        int regl[8], thrl[8], p = 0, s = 0;
-        for (int l = 0; l < opt.v; ++l) regl[p++] = l;
-        for (int l = 0; l < k; ++l) if ((regs_u >> l) & 1) regl[p++] = l;
-        for (int l = opt.v; l < opt.v + 6; ++l) thrl[s++] = l;
+    LState storable(uint64_t regs_u) const {
+        LState st{};
+        int p = 0, t = 0;
+        for (int l = 0; l < opt.v; ++l) st.reg[p++] = l;
+        for (int l = 0; l < k; ++l) if ((regs_u >> l) & 1) st.reg[p++] = l;
+        for (int l = opt.v; l < opt.v + 6; ++l) st.thr[t++] = l;
         const uint64_t rest = U_labels() & ~regs_u;
-        for (int l = 0; l < k; ++l) if ((rest >> l) & 1) thrl[s++] = l;
-        set_state(regl, thrl, 0);
+        for (int l = 0; l < k; ++l) if ((rest >> l) & 1) st.thr[t++] = l;
+        st.xmask = 0;
+        st.fixed_thr = 6;
+        st.storable = true;
+        return st;
     }
 
     // regs: R labels; lanes 0..m-1 get labels whose swizzle images are
     // linearly independent (conflict-free LDS rows).
-    void general_state(uint64_t regs) {
-        int regl[8], thrl[8], p = 0;
-        for (int l = 0; l < k; ++l) if ((regs >> l) & 1) regl[p++] = l;
+    LState general(uint64_t regs) const {
+        LState st{};
+        int p = 0;
+        for (int l = 0; l < k; ++l) if ((regs >> l) & 1) st.reg[p++] = l;
         std::vector<int> lanes, others;
         uint32_t basis[8] = {0};
         for (int l = 0; l < k; ++l) {
@@ -283,10 +311,113 @@ struct PassCtx {
             if (x && (int)lanes.size() < opt.m) lanes.push_back(l);
             else others.push_back(l);
         }
-        int s = 0;
-        for (int l : lanes) thrl[s++] = l;
-        for (int l : others) thrl[s++] = l;
-        set_state(regl, thrl, 0);
+        int t = 0;
+        for (int l : lanes) st.thr[t++] = l;
+        for (int l : others) st.thr[t++] = l;
+        st.xmask = 0;
+        st.fixed_thr = opt.m;
+        st.storable = false;
+        return st;
+    }
+
+    static int find_in(const int *arr, int cnt, int l) {
+        for (int i = 0; i < cnt; ++i) if (arr[i] == l) return i;
+        return -1;
+    }
+
+    // Register position p of state b may be re-assigned (a storable complex64
+    // layout keeps label 0 in register 0 for its paired 16-byte accesses).
+    bool reg_free(const LState &b, int p) const { return !(b.storable && opt.v && p == 0); }
+
+    // Half-tile exchange from a to b: find a label l >= m (its LDS slot bit is
+    // outside the swizzle bits, so dropping it keeps slots distinct and
+    // conflict-free) held at the same register position, or failing that the
+    // same thread bit, in both layouts. b may be permuted to make that true and
+    // takes a's XOR bit of l. Returns the split source and label.
+    bool find_split(const LState &a, LState &b, uint8_t &src, int &lab) const {
+        for (int p = 0; p < opt.R; ++p) {
+            const int l = a.reg[p];
+            if (l < opt.m) continue;
+            const int pb = find_in(b.reg, opt.R, l);
+            if (pb < 0) continue;
+            if (pb != p) {
+                if (!reg_free(b, p) || !reg_free(b, pb)) continue;
+                std::swap(b.reg[p], b.reg[pb]);
+            }
+            b.xmask = (b.xmask & ~(1u << l)) | (a.xmask & (1u << l));
+            src = (uint8_t)(SRC_REG | p);
+            lab = l;
+            return true;
+        }
+        for (int t = w - 1; t >= 0; --t) {   // high thread bits first: whole waves per half
+            const int l = a.thr[t];
+            if (l < opt.m) continue;
+            const int tb = find_in(b.thr, w, l);
+            if (tb < 0) continue;
+            if (tb != t) {
+                if (t < b.fixed_thr || tb < b.fixed_thr) continue;
+                std::swap(b.thr[t], b.thr[tb]);
+            }
+            b.xmask = (b.xmask & ~(1u << l)) | (a.xmask & (1u << l));
+            src = (uint8_t)(SRC_THR | t);
+            lab = l;
+            return true;
+        }
+        return false;
+    }
+
+    void emit_exch(int wl, int rl, uint8_t src, int lab) {
+        HostOp &ex = emit(OP_EXCH);
+        ex.hdr.a = (uint8_t)wl;
+        ex.hdr.b = (uint8_t)rl;
+        ex.hdr.sa = src;
+        ex.hdr.sb = (uint8_t)lab;
+        ++P.n_exch;
+    }
+
+    // Re-distribute the tile (pending register products already flushed) from
+    // the current layout into b. When no label can split the exchange, go
+    // through an intermediate layout M: b with one of a's register labels
+    // l >= m moved into the register position it has in a (R > m guarantees
+    // one). a -> M splits on that register; M -> b splits on a register or
+    // thread position the two share (all but one or two of them).
+    void exchange_to(LState b) {
+        const LState a = save();
+        const int wl = layout_index();
+        uint8_t src = 0;
+        int lab = -1;
+        if (find_split(a, b, src, lab)) {
+            load(b);
+            emit_exch(wl, layout_index(), src, lab);
+            return;
+        }
+        int pk = -1;
+        for (int p = 0; p < opt.R; ++p)
+            if (a.reg[p] >= opt.m) { pk = p; break; }
+        if (pk < 0) throw std::logic_error("layout exchange: no register label to split on");
+        const int keep = a.reg[pk];
+        LState M = b;
+        M.storable = false;
+        M.fixed_thr = w;
+        const int pb = find_in(b.reg, opt.R, keep);
+        if (pb >= 0) {
+            std::swap(M.reg[pk], M.reg[pb]);
+        } else {
+            const int tk = find_in(b.thr, w, keep);
+            M.thr[tk] = b.reg[pk];
+            M.reg[pk] = keep;
+        }
+        M.xmask = a.xmask & (1u << keep);
+        uint8_t s1 = 0, s2 = 0;
+        int l1 = -1, l2 = -1;
+        if (!find_split(a, M, s1, l1)) throw std::logic_error("layout exchange via M: first half");
+        load(M);
+        const int ml = layout_index();
+        emit_exch(wl, ml, s1, l1);
+        const LState m2 = save();
+        if (!find_split(m2, b, s2, l2)) throw std::logic_error("layout exchange via M: second half");
+        load(b);
+        emit_exch(ml, layout_index(), s2, l2);
     }
 
     bool is_storable() const {
@@ -706,7 +837,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             for (int lb = 0; lb < k && popc(S0) < ru; ++lb)
                 if ((U >> lb) & 1) S0 |= bit(lb);
         }
-        X.storable_state(S0);
+        X.load(X.storable(S0));
         X.layout_index();
 
         while (true) {
@@ -736,7 +867,6 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
                 else { b2.defer(g); all_fit = false; }
             }
             X.flush_all();
-            const int wl = X.layout_index();
             const uint64_t V = opt.v ? 1ull : 0ull;
             if (all_fit && (S & ~(U | V)) == 0 && popc(S | V) <= opt.R) {
                 uint64_t su = S & U;
@@ -744,32 +874,21 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
                     if (((U & regs) >> lb) & 1) su |= bit(lb);
                 for (int lb = 0; lb < k && popc(su) < ru; ++lb)
                     if ((U >> lb) & 1) su |= bit(lb);
-                X.storable_state(su);
+                X.exchange_to(X.storable(su));
             } else {
                 for (int lb = 0; lb < k && popc(S) < opt.R; ++lb)
                     if ((regs >> lb) & 1) S |= bit(lb);
                 for (int lb = 0; lb < k && popc(S) < opt.R; ++lb) S |= bit(lb);
-                X.general_state(S);
+                X.exchange_to(X.general(S));
             }
-            const int rl = X.layout_index();
-            HostOp &ex = X.emit(OP_EXCH);
-            ex.hdr.a = (uint8_t)wl;
-            ex.hdr.b = (uint8_t)rl;
-            ++P.n_exch;
         }
         X.flush_all();
         if (!X.is_storable()) {
-            const int wl = X.layout_index();
             uint64_t su = X.reg_labels() & U;
             while (popc(su) > ru) su &= su - 1;
             for (int lb = 0; lb < k && popc(su) < ru; ++lb)
                 if ((U >> lb) & 1) su |= bit(lb);
-            X.storable_state(su);
-            const int rl = X.layout_index();
-            HostOp &ex = X.emit(OP_EXCH);
-            ex.hdr.a = (uint8_t)wl;
-            ex.hdr.b = (uint8_t)rl;
-            ++P.n_exch;
+            X.exchange_to(X.storable(su));
         }
         dp.store_layout = X.layout_index();
         // In-place safety: without an exchange, nothing orders one wave's loads

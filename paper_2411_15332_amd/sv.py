@@ -237,12 +237,13 @@ PASS_DTYPE = np.dtype([("k", "<i4"), ("w", "<i4"), ("op_begin", "<i4"), ("op_end
                        ("layout_begin", "<i4"), ("flags", "<u4"), ("tiles", "<u8"),
                        ("gen_j", "<u8"), ("gen_mask", "<u8"), ("gen_scale", "<f8"),
                        ("store_layout", "<i4"), ("q", "u1", (28,)), ("pad", "u1", (8,))])
-LAYOUT_DTYPE = np.dtype([("thr_goff", "<u8", (8,)), ("reg_goff", "<u8", (8,)),
-                         ("thr_slot", "<u4", (8,)), ("reg_slot", "<u4", (8,)),
-                         ("goff_xor", "<u8"), ("slot_xor", "<u4"), ("flags", "<u4"),
-                         ("reg_local", "u1", (8,)), ("thr_local", "u1", (8,)),
-                         ("xor_local", "<u4"), ("pad0", "<u4"), ("reg_goff_xor", "<u8"),
-                         ("pad", "u1", (16,))])
+LAYOUT_DTYPE = np.dtype([("thr_goff", "<u8", (10,)), ("reg_goff", "<u8", (6,)),
+                         ("goff_xor", "<u8"), ("reg_goff_xor", "<u8"),
+                         ("thr_slot", "<u4", (10,)), ("reg_slot", "<u4", (6,)),
+                         ("slot_xor", "<u4"), ("flags", "<u4"), ("xor_local", "<u4"),
+                         ("thr_local", "u1", (10,)), ("reg_local", "u1", (6,)),
+                         ("pad", "u1", (20,))])
+assert LAYOUT_DTYPE.itemsize == 256
 OP_DTYPE = np.dtype([("code", "u1"), ("a", "u1"), ("b", "u1"), ("sa", "u1"), ("sb", "u1"),
                      ("pad", "u1", (3,)), ("data", "<u8"), ("payload", "<f8", (8,))])
 SOP_DTYPE = np.dtype([("code", "u1"), ("q0", "u1"), ("q1", "u1"), ("pad", "u1", (5,)),

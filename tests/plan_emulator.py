@@ -125,15 +125,41 @@ def run_plan(plan, psi, n):
             pl = op["payload"]
             d = pl[0::2] + 1j * pl[1::2]
             if code == OP_EXCH:
-                lds = np.full((tiles, 1 << k), np.nan, dtype=np.complex128)
+                # Two halves through a half-tile buffer: the half is the value
+                # of label sb, taken from the same register bit or thread bit
+                # (source sa) on both sides; slots drop bit sb.
+                lab = sb
+                assert lab >= plan["m"], "split label inside the swizzle bits"
+                kind, pos = sa >> 6, sa & 63
+                shape = (tiles, NT, NR)
+                half = np.broadcast_to(((j_idx >> pos) & 1) if kind == SRC_REG else ((t_idx >> pos) & 1),
+                                       shape)
+                assert kind in (SRC_REG, SRC_THR)
                 _, sw = tables(oa)
-                sw = np.broadcast_to(sw, a.shape).reshape(tiles, -1)
-                assert np.all(np.sort(sw[0]) == np.arange(1 << k))
-                np.put_along_axis(lds, sw, a.reshape(tiles, -1), axis=1)
                 _, sr = tables(ob)
-                sr = np.broadcast_to(sr, a.shape).reshape(tiles, -1)
-                a = np.take_along_axis(lds, sr, axis=1).reshape(a.shape)
-                assert not np.any(np.isnan(a))
+                sw = np.broadcast_to(sw, shape)
+                sr = np.broadcast_to(sr, shape)
+                assert np.all(np.sort(sw[0].ravel()) == np.arange(1 << k))
+                assert np.all(np.sort(sr[0].ravel()) == np.arange(1 << k))
+                # the buffer half is one value of the label on both sides
+                cw = ((sw >> lab) & 1) ^ half
+                cr = ((sr >> lab) & 1) ^ half
+                assert np.all(cw == cw.flat[0]) and np.all(cr == cw.flat[0])
+                lo = (1 << lab) - 1
+                cw_slot = (sw & lo) | ((sw >> 1) & ~lo)
+                cr_slot = (sr & lo) | ((sr >> 1) & ~lo)
+                out = np.full(shape, np.nan, dtype=np.complex128)
+                for h in (0, 1):
+                    lds = np.full((tiles, 1 << (k - 1)), np.nan, dtype=np.complex128)
+                    wm = half == h
+                    ws = cw_slot[wm].reshape(tiles, -1)
+                    assert np.all(np.sort(ws[0]) == np.arange(1 << (k - 1)))
+                    np.put_along_axis(lds, ws, a[wm].reshape(tiles, -1), axis=1)
+                    rs = cr_slot[half == h].reshape(tiles, -1)
+                    vals = np.take_along_axis(lds, rs, axis=1)
+                    assert not np.any(np.isnan(vals))
+                    out[half == h] = vals.ravel()
+                a = out
             elif code == OP_D1R:
                 a = a * f * d[:2][(j_idx >> oa) & 1]
                 f = np.ones_like(f)
