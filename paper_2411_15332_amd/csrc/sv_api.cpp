@@ -49,11 +49,13 @@ PlanOptions plan_options(const sv_state_s *s) {
         o.v = 0;
         o.m = 3;
         o.small_max = kSmallMaxQubitsC128;
+        o.ud_max = kMaxUdTermsC128;
     } else {
         o.R = kRegBitsC64;
         o.v = 1;
         o.m = 4;
         o.small_max = kSmallMaxQubitsC64;
+        o.ud_max = kMaxUdTerms;
     }
     o.c = s->min_low;
     o.w_max = s->dt == SV_C128 ? kThreadBitsC128 : kThreadBitsC64;
@@ -692,7 +694,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     }
     const PlanOptions po = plan_options(&tmp);
     Plan p = build_plan(n, gates, n_gates, po);
-    const size_t real_bytes = 8;  // constants reported in FP64
+    const size_t real_bytes = dtype == SV_C64 ? 4 : 8;  // constants in the state's precision
     const Layout L = plan_sections(p, 1, real_bytes);
     const size_t header = 256;
     const size_t total = header + L.total;
@@ -722,7 +724,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     h[17] = (int64_t)(header + L.consts);
     h[18] = plan_hbm_bytes(p, n, dtype == SV_C128 ? 16 : 8);
     h[19] = p.n_relabel;
-    serialize_plan(p, L, gates, params, n_params, 1, false, o + header);
+    serialize_plan(p, L, gates, params, n_params, 1, dtype == SV_C64, o + header);
     return (int64_t)total;
 }
 

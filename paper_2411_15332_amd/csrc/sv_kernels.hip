@@ -180,6 +180,14 @@ __device__ __forceinline__ void r_d1_reg(cpx<T> (&a)[NR], cpx<T> d0, cpx<T> d1) 
     for (int j = 0; j < NR; ++j) cmul_ip(a[j], (j & (1 << P)) ? d1 : d0);
 }
 
+// amp *= d for the slots whose register bit P equals V
+template <int P, int V, typename T, int NR>
+__device__ __forceinline__ void r_d1_half(cpx<T> (&a)[NR], cpx<T> d) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (((j >> P) & 1) == V) cmul_ip(a[j], d);
+}
+
 template <int PA, int PB, typename T, int NR>
 __device__ __forceinline__ void r_d2_regreg(cpx<T> (&a)[NR], const cpx<T> (&d)[4]) {
 #pragma unroll
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         }
     }
 
-    cpx<T> f = mk<T>((T)1, (T)0);   // per-thread diagonal factor (OP_UD1/OP_UD2)
+    cpx<T> f = mk<T>((T)1, (T)0);   // per-thread diagonal factor (OP_UDN)
     const int oe = P.op_end;
     int oi = P.op_begin;
     if (oi < oe) {
@@ -428,22 +436,59 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 }
                 break;
             }
+            case OP_D1H: {
+                const cpx<T> d = plc<T>(op, 0);
+                if (op.b) {
+                    SV_SWITCH_A(op.a, r_d1_half<PA, 1>(a, d))
+                } else {
+                    SV_SWITCH_A(op.a, r_d1_half<PA, 0>(a, d))
+                }
+                break;
+            }
+            case OP_D2Q: {
+                // rare (both qubits of a CZ / CPHASE in registers): selects
+                // keep the code small instead of one body per bit pair
+                const cpx<T> d = plc<T>(op, 0), one = mk<T>((T)1, (T)0);
+                const int xa = op.sa & 1, xb = (op.sa >> 1) & 1;
+#pragma unroll
+                for (int j = 0; j < NR; ++j) {
+                    const bool hit = ((j >> op.a) & 1) == xa && ((j >> op.b) & 1) == xb;
+                    cmul_ip(a[j], hit ? d : one);
+                }
+                break;
+            }
+            case OP_D1HU: {
+                const cpx<T> d = plc<T>(op, 0);
+                const bool on = src_bit(op.sa, tid, base) == ((op.b >> 1) & 1);
+                const cpx<T> e = on ? d : mk<T>((T)1, (T)0);
+                if (op.b & 1) {
+                    SV_SWITCH_A(op.a, r_d1_half<PA, 1>(a, e))
+                } else {
+                    SV_SWITCH_A(op.a, r_d1_half<PA, 0>(a, e))
+                }
+                break;
+            }
             case OP_D1R: {
                 const cpx<T> d0 = cmul(f, plc<T>(op, 0)), d1 = cmul(f, plc<T>(op, 1));
                 f = mk<T>((T)1, (T)0);
                 SV_SWITCH_A(op.a, r_d1_reg<PA>(a, d0, d1))
                 break;
             }
-            case OP_UD1: {
-                const int b = src_bit(op.sa, tid, base);
-                f = cmul(f, b ? plc<T>(op, 1) : plc<T>(op, 0));
-                break;
-            }
-            case OP_UD2: {
-                const int e = (src_bit(op.sa, tid, base) << 1) | src_bit(op.sb, tid, base);
-                const cpx<T> d01 = (e & 1) ? plc<T>(op, 1) : plc<T>(op, 0);
-                const cpx<T> d23 = (e & 1) ? plc<T>(op, 3) : plc<T>(op, 2);
-                f = cmul(f, (e & 2) ? d23 : d01);
+            case OP_UDN: {
+                // merged diagonals on thread / tile-base bits: C times the
+                // ratio of every term whose bit (or bit pair) is set
+                cpx<T> g = plc<T>(op, 0);
+                constexpr int UDT = sizeof(T) == 8 ? kMaxUdTermsC128 : kMaxUdTerms;
+#pragma unroll
+                for (int i = 0; i < UDT; ++i) {
+                    if (i >= (int)op.a) break;
+                    const uint8_t s1 = i < 4 ? (uint8_t)(op.data >> (16 * i)) : op.sa;
+                    const uint8_t s2 = i < 4 ? (uint8_t)(op.data >> (16 * i + 8)) : op.sb;
+                    const int on = src_bit(s1, tid, base) & (s2 == kNoSource ? 1 : src_bit(s2, tid, base));
+                    const cpx<T> r = plc<T>(op, i + 1);
+                    g = on ? cmul(g, r) : g;
+                }
+                f = cmul(f, g);
                 break;
             }
             case OP_APPLYF: {

@@ -37,8 +37,10 @@ enum OpCode : uint8_t {
                      // sa: SRC_REG | p or SRC_THR | s) with the same XOR bit in both
                      // layouts; slots drop bit sb
     OP_D1R = 2,      // amp *= f d[bit p of j], f = 1; a = p; payload d0, d1
-    OP_UD1 = 3,      // per-thread factor f *= d[bit]; sa = THR/TILE source; payload d0, d1
-    OP_UD2 = 4,      // f *= d[(bit sa << 1) | bit sb]; payload d[4]
+    OP_UDN = 3,      // per-thread factor f *= C * prod_{i < a} (term i holds ? r_i : 1);
+                     // term i is the bit of source s1, or the AND of sources s1 and s2
+                     // (s2 != 0xFF); (s1, s2) of terms 0..3 in the bytes of `data`,
+                     // of term 4 in (sa, sb); payload C, r_0 .. r_{a-1}
     OP_APPLYF = 5,   // amp *= f for every slot; f = 1
     OP_D2RR = 6,     // amp *= f d[(bit a of j << 1) | bit b of j], f = 1; payload d[4]
     OP_D2RU = 7,     // amp *= f e[u][bit a of j], u = bit of source sa, f = 1; payload e[2][2]
@@ -51,7 +53,15 @@ enum OpCode : uint8_t {
     OP_SCALE = 14,   // amp *= s; payload s (one real)
     OP_CXT = 15,     // swap the pairs of register bit a when tile-base bit `sa` (a qubit
                      // outside the tile, the same for the whole workgroup) is 1
+    OP_D1H = 16,     // amp *= d for the slots whose register bit a equals b (f untouched)
+    OP_D2Q = 17,     // amp *= d for the slots whose register bits a, b equal bits 0, 1 of sa
+    OP_D1HU = 18,    // amp *= d for the slots whose register bit a equals bit 0 of b, when
+                     // the bit of source sa equals bit 1 of b (f untouched)
 };
+
+constexpr uint8_t kNoSource = 0xFF;
+constexpr int kMaxUdTerms = 5;       // OP_UDN terms (term descriptors in the header)
+constexpr int kMaxUdTermsC128 = 3;   // complex128: C and 3 ratios fill the payload
 
 // One operation: 16-byte header and 64-byte payload (8 doubles or 16 floats:
 // the constants in the precision of the state). Stored per batch entry.

@@ -237,6 +237,10 @@ struct PassCtx {
     bool f_used = false;
     int h_count = 0;
     int first_payload = -1;
+    // Pending uniform diagonals (thread / tile-base bits), merged into one
+    // OP_UDN emitted before the next operation that consumes f.
+    std::vector<UContrib> ud;
+    std::vector<uint16_t> uterm;   // (s1 | s2 << 8)
 
     PassCtx(const PlanOptions &o, Plan &p, const std::vector<CGate> &g, int n_, int k_, int w_)
         : opt(o), P(p), cg(g), n(n_), k(k_), w(w_) {}
@@ -503,24 +507,63 @@ struct PassCtx {
         pd.f.push_back(f);
     }
 
+    // Which halves of register bit p a pending diagonal product touches:
+    // bit 0 = the slots with bit value 0, bit 1 = value 1. Gates with a unit
+    // first entry (Z, S, SDG, T, TDG, P) touch one half; X factors in the run
+    // swap halves for the factors after them.
+    int diag_sides(const Pending &pd) const {
+        int sides = 0, flip = 0;
+        for (const Factor &f : pd.f) {
+            if (f.kind == FK_X) { flip ^= 1; continue; }
+            if (f.kind == FK_GATE) {
+                const int kd = cg_kind(f.gate);
+                if (kd == SV_GATE_I) continue;
+                if (kd == SV_GATE_Z || kd == SV_GATE_S || kd == SV_GATE_SDG || kd == SV_GATE_T ||
+                    kd == SV_GATE_TDG || kd == SV_GATE_P) {
+                    sides |= 1 << (1 ^ (f.conj_x ? 1 : 0) ^ flip);
+                    continue;
+                }
+            }
+            sides = 3;
+        }
+        return sides;
+    }
+
     void flush(int p) {
         Pending &pd = pend[p];
         if (pd.cls == PC_I) { pd = Pending(); return; }
         if (pd.cls == PC_D) {
-            HostOp &o = emit(OP_D1R);
-            o.hdr.a = (uint8_t)p;
-            o.pk = PK_DIAG2;
-            o.factors = pd.f;
-            note_payload();
-            f_used = false;   // the op multiplies by the pending per-thread factor
+            const int sides = diag_sides(pd);
+            if (sides == 1 || sides == 2) {
+                HostOp &o = emit(OP_D1H);
+                o.hdr.a = (uint8_t)p;
+                o.hdr.b = (uint8_t)(sides == 2 ? 1 : 0);
+                o.pk = PK_SIDE;
+                o.factors = pd.f;
+            } else if (sides == 3) {
+                emit_ud();
+                HostOp &o = emit(OP_D1R);
+                o.hdr.a = (uint8_t)p;
+                o.pk = PK_DIAG2;
+                o.factors = pd.f;
+                note_payload();
+                f_used = false;   // the op multiplies by the pending per-thread factor
+            }
         } else if (pd.cls == PC_A && pd.pure_x) {
-            HostOp &o = emit(OP_X);
-            o.hdr.a = (uint8_t)p;
+            if (opt.v && reg_label[p] == 0) {   // keeps label 0 unflipped for paired 16-byte I/O
+                HostOp &o = emit(OP_X);
+                o.hdr.a = (uint8_t)p;
+            } else {
+                xmask ^= 1u << reg_label[p];     // relabel: no data moves
+                cur_layout = -1;
+                ++P.n_relabel;
+            }
         } else if (pd.cls == PC_H) {
             HostOp &o = emit(OP_H);
             o.hdr.a = (uint8_t)p;
             ++h_count;
         } else {
+            emit_ud();
             HostOp &o = emit(OP_DENSE1);
             o.hdr.a = (uint8_t)p;
             o.pk = PK_MAT2;
@@ -535,10 +578,92 @@ struct PassCtx {
     }
     void flush_all() {
         for (int p = 0; p < opt.R; ++p) flush(p);
+        emit_ud();
         if (f_used) {
             emit(OP_APPLYF);
             f_used = false;
         }
+    }
+
+    int cg_kind(int src) const { return gkinds ? gkinds[src] : -1; }
+    const int *gkinds = nullptr;   // sv_gate kind of every source gate
+
+    // Term slot of the pending OP_UDN for the bit of s1 (s2 = kNoSource) or
+    // the AND of two bits; -1 when the operation is full.
+    int term_slot(uint8_t s1, uint8_t s2) {
+        if (s2 != kNoSource && s2 < s1) std::swap(s1, s2);
+        const uint16_t key = (uint16_t)(s1 | (s2 << 8));
+        for (size_t i = 0; i < uterm.size(); ++i) if (uterm[i] == key) return (int)i;
+        if ((int)uterm.size() >= opt.ud_max) return -1;
+        uterm.push_back(key);
+        return (int)uterm.size() - 1;
+    }
+    bool term_fits(const uint16_t *keys, int cnt) const {
+        int fresh = 0;
+        for (int i = 0; i < cnt; ++i) {
+            bool found = false;
+            for (uint16_t t : uterm) if (t == keys[i]) found = true;
+            for (int j = 0; j < i; ++j) if (keys[j] == keys[i]) found = true;
+            if (!found) ++fresh;
+        }
+        return (int)uterm.size() + fresh <= opt.ud_max;
+    }
+    static uint16_t tkey(uint8_t s1, uint8_t s2) {
+        if (s2 != kNoSource && s2 < s1) std::swap(s1, s2);
+        return (uint16_t)(s1 | (s2 << 8));
+    }
+
+    void emit_ud() {
+        if (ud.empty()) return;
+        HostOp &o = emit(OP_UDN);
+        o.hdr.a = (uint8_t)uterm.size();
+        uint64_t data = 0;
+        for (size_t i = 0; i < uterm.size(); ++i) {
+            if (i < 4) data |= (uint64_t)uterm[i] << (16 * i);
+            else { o.hdr.sa = (uint8_t)(uterm[i] & 0xFF); o.hdr.sb = (uint8_t)(uterm[i] >> 8); }
+        }
+        o.hdr.data = data;
+        o.pk = PK_UDN;
+        o.ucon = ud;
+        o.n_terms = (int)uterm.size();
+        note_payload();
+        f_used = true;
+        ud.clear();
+        uterm.clear();
+    }
+
+    // A 1-qubit diagonal (or the phases of Y) on a thread / tile-base bit.
+    void add_ud1(const Src &s, int gate, uint8_t kind) {
+        const uint16_t k1 = tkey(s.code, kNoSource);
+        if (!term_fits(&k1, 1)) emit_ud();
+        UContrib u;
+        u.gate = gate;
+        u.kind = kind;
+        u.inv = s.inv != 0;
+        u.t0 = (int8_t)term_slot(s.code, kNoSource);
+        ud.push_back(u);
+    }
+
+    // A 2-qubit diagonal (CZ / CPHASE: one non-trivial entry) on two thread /
+    // tile-base bits; only the terms its non-trivial entry needs are used.
+    void add_ud2(const Src &s0, const Src &s1, int gate) {
+        UContrib u;
+        u.gate = gate;
+        u.kind = UC_D2;
+        for (int e = 0; e < 4; ++e) u.perm[e] = d4_index(e >> 1, e & 1, s0.inv, s1.inv);
+        int es = 0;   // physical (x << 1) | y of the entry holding the gate's entry 3
+        for (int e = 0; e < 4; ++e) if (u.perm[e] == 3) es = e;
+        const bool need0 = es == 2 || es == 0, need1 = es == 1 || es == 0;
+        uint16_t keys[3];
+        int cnt = 0;
+        if (need0) keys[cnt++] = tkey(s0.code, kNoSource);
+        if (need1) keys[cnt++] = tkey(s1.code, kNoSource);
+        keys[cnt++] = tkey(s0.code, s1.code);
+        if (!term_fits(keys, cnt)) emit_ud();
+        if (need0) u.t0 = (int8_t)term_slot(s0.code, kNoSource);
+        if (need1) u.t1 = (int8_t)term_slot(s1.code, kNoSource);
+        u.t01 = (int8_t)term_slot(s0.code, s1.code);
+        ud.push_back(u);
     }
 
     // Register needs in this pass: a CNOT's control inside the tile is asked
@@ -574,52 +699,45 @@ struct PassCtx {
             if (s.reg) {
                 compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_D, false);
             } else {
-                HostOp &o = emit(OP_UD1);
-                o.hdr.sa = s.code;
-                o.pk = PK_DIAG2;
-                o.factors.push_back(Factor{FK_GATE, s.inv != 0, g.src});
-                note_payload();
-                f_used = true;
+                add_ud1(s, g.src, UC_D1);
             }
             break;
         }
         case G_D2: {
-            const Src s0 = src_of(g.q0), s1 = src_of(g.q1);
+            Src s0 = src_of(g.q0), s1 = src_of(g.q1);
+            if (s0.reg) flush_nondiag(s0.p);   // may relabel: read the sources again
+            if (s1.reg) flush_nondiag(s1.p);
+            s0 = src_of(g.q0);
+            s1 = src_of(g.q1);
             if (s0.reg && s1.reg) {
-                flush_nondiag(s0.p);
-                flush_nondiag(s1.p);
-                HostOp &o = emit(OP_D2RR);
+                // one non-trivial entry: a quarter of the slots
+                int es = 0;
+                for (int e = 0; e < 4; ++e)
+                    if (d4_index(e >> 1, e & 1, s0.inv, s1.inv) == 3) es = e;
+                HostOp &o = emit(OP_D2Q);
                 o.hdr.a = (uint8_t)s0.p;
                 o.hdr.b = (uint8_t)s1.p;
-                o.pk = PK_D4;
+                o.hdr.sa = (uint8_t)(((es >> 1) & 1) | ((es & 1) << 1));
+                o.pk = PK_G3;
                 o.gate = g.src;
-                for (int e = 0; e < 4; ++e) o.perm[e] = d4_index(e >> 1, e & 1, s0.inv, s1.inv);
-                note_payload();
-                f_used = false;
             } else if (s0.reg || s1.reg) {
                 const Src &r = s0.reg ? s0 : s1;
                 const Src &u = s0.reg ? s1 : s0;
-                flush_nondiag(r.p);
-                HostOp &o = emit(OP_D2RU);
-                o.hdr.a = (uint8_t)r.p;
-                o.hdr.sa = u.code;
-                o.pk = PK_D4;
-                o.gate = g.src;
+                // e = (ub << 1) | rb; the gate's entry 3 sits at one e
+                int es = 0;
                 for (int e = 0; e < 4; ++e) {
                     const int ub = e >> 1, rb = e & 1;
-                    o.perm[e] = s0.reg ? d4_index(rb, ub, r.inv, u.inv) : d4_index(ub, rb, u.inv, r.inv);
+                    const int gl = s0.reg ? d4_index(rb, ub, r.inv, u.inv) : d4_index(ub, rb, u.inv, r.inv);
+                    if (gl == 3) es = e;
                 }
-                note_payload();
-                f_used = false;
-            } else {
-                HostOp &o = emit(OP_UD2);
-                o.hdr.sa = s0.code;
-                o.hdr.sb = s1.code;
-                o.pk = PK_D4;
+                HostOp &o = emit(OP_D1HU);
+                o.hdr.a = (uint8_t)r.p;
+                o.hdr.b = (uint8_t)((es & 1) | (((es >> 1) & 1) << 1));
+                o.hdr.sa = u.code;
+                o.pk = PK_G3;
                 o.gate = g.src;
-                for (int e = 0; e < 4; ++e) o.perm[e] = d4_index(e >> 1, e & 1, s0.inv, s1.inv);
-                note_payload();
-                f_used = true;
+            } else {
+                add_ud2(s0, s1, g.src);
             }
             break;
         }
@@ -658,12 +776,7 @@ struct PassCtx {
                 compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_A, false);
             } else {
                 // Y = X diag(i, -i): the phases first, then the label flip
-                HostOp &o = emit(OP_UD1);
-                o.hdr.sa = s.code;
-                o.pk = PK_DIAG2;
-                o.factors.push_back(Factor{FK_YDIAG, s.inv != 0, -1});
-                note_payload();
-                f_used = true;
+                add_ud1(s, -1, UC_YDIAG);
                 xmask ^= 1u << label_of[g.q0];
                 cur_layout = -1;
                 ++P.n_relabel;
@@ -681,10 +794,14 @@ struct PassCtx {
             break;
         }
         case G_CX: {
-            const Src t = src_of(g.q1), c = src_of(g.q0);
+            // flushing a pending pure X relabels (flips an XOR bit), so the
+            // sources are read again after every flush
+            const Src t = src_of(g.q1);
             flush(t.p);
+            Src c = src_of(g.q0);
             if (c.reg) {
                 flush_nondiag(c.p);
+                c = src_of(g.q0);
                 HostOp &o = emit(OP_CXR);
                 o.hdr.a = (uint8_t)t.p;
                 o.hdr.b = (uint8_t)c.p;
@@ -729,6 +846,8 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     P.n = n;
     std::vector<CGate> cg;
     cg.reserve(n_gates);
+    std::vector<int> kinds(n_gates);
+    for (size_t i = 0; i < n_gates; ++i) kinds[i] = gates[i].kind;
     for (size_t i = 0; i < n_gates; ++i) {
         CGate c = classify(gates[i], n, (int)i);
         if (c.cls != G_NOP) cg.push_back(c);
@@ -796,6 +915,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
 
     for (size_t pi = 0; pi < groups.size(); ++pi) {
         PassCtx X(opt, P, cg, n, k, w);
+        X.gkinds = kinds.data();
         const uint64_t Q = qsets[pi];
         for (int qq = 0; qq < 64; ++qq) X.label_of[qq] = -1;
         std::memset(X.q, 0, sizeof X.q);
@@ -989,6 +1109,8 @@ static void factor_mat(const Factor &f, const sv_gate *gates, const double *para
 
 template <typename R>
 static void write_payload(DevOp &rec, const double *v, int count) {
+    if ((size_t)count * sizeof(R) > sizeof rec.payload)
+        throw std::logic_error("operation payload larger than its record");
     R *dst = reinterpret_cast<R *>(rec.payload);
     for (int i = 0; i < count; ++i) dst[i] = (R)v[i];
 }
@@ -1002,7 +1124,7 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
             const HostOp &h = p.ops[i];
             DevOp rec = h.hdr;
             std::memset(rec.payload, 0, sizeof rec.payload);
-            double v[8] = {0};
+            double v[2 + 2 * kMaxUdTerms] = {0};
             int count = 0;
             switch (h.pk) {
             case PK_MAT2:
@@ -1037,6 +1159,56 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
                 break;
             }
             case PK_SCALE: v[0] = h.scale; count = 1; break;
+            case PK_SIDE: {
+                cd M[4] = {1.0, 0.0, 0.0, 1.0};
+                for (const Factor &f : h.factors) {
+                    cd F[4];
+                    factor_mat(f, gates, params, n_params, b, F);
+                    const cd N[4] = {F[0] * M[0] + F[1] * M[2], F[0] * M[1] + F[1] * M[3],
+                                     F[2] * M[0] + F[3] * M[2], F[2] * M[1] + F[3] * M[3]};
+                    std::copy(N, N + 4, M);
+                }
+                const cd d = h.hdr.b ? M[3] : M[0];
+                v[0] = d.real(); v[1] = d.imag();
+                count = 2;
+                break;
+            }
+            case PK_G3: {
+                const sv_gate &g = gates[h.gate];
+                cd d[4];
+                gate_diag4(g.kind, gate_angle(g, params, n_params, b), d);
+                v[0] = d[3].real(); v[1] = d[3].imag();
+                count = 2;
+                break;
+            }
+            case PK_UDN: {
+                cd C = h.scale;
+                cd r[kMaxUdTerms];
+                for (int t = 0; t < kMaxUdTerms; ++t) r[t] = 1.0;
+                for (const UContrib &u : h.ucon) {
+                    cd P00, P01, P10, P11;
+                    if (u.kind == UC_D2) {
+                        const sv_gate &g = gates[u.gate];
+                        cd d[4];
+                        gate_diag4(g.kind, gate_angle(g, params, n_params, b), d);
+                        P00 = d[u.perm[0]]; P01 = d[u.perm[1]]; P10 = d[u.perm[2]]; P11 = d[u.perm[3]];
+                    } else {
+                        cd m[4];
+                        const Factor f{(uint8_t)(u.kind == UC_YDIAG ? FK_YDIAG : FK_GATE), u.inv, u.gate};
+                        factor_mat(f, gates, params, n_params, b, m);
+                        P00 = P01 = m[0];
+                        P10 = P11 = m[3];
+                    }
+                    C *= P00;
+                    if (u.t0 >= 0) r[u.t0] *= P10 / P00;
+                    if (u.t1 >= 0) r[u.t1] *= P01 / P00;
+                    if (u.t01 >= 0) r[u.t01] *= P11 * P00 / (P10 * P01);
+                }
+                v[0] = C.real(); v[1] = C.imag();
+                for (int t = 0; t < h.n_terms; ++t) { v[2 + 2 * t] = r[t].real(); v[3 + 2 * t] = r[t].imag(); }
+                count = 2 + 2 * h.n_terms;
+                break;
+            }
             default: break;
             }
             if (f32) write_payload<float>(rec, v, count);

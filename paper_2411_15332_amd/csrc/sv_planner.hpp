@@ -50,16 +50,40 @@ struct Factor {
     int gate;
 };
 
-enum PayloadKind : uint8_t { PK_NONE = 0, PK_MAT2, PK_DIAG2, PK_D4, PK_SCALE };
+enum PayloadKind : uint8_t {
+    PK_NONE = 0,
+    PK_MAT2,    // the 2x2 product of `factors`
+    PK_DIAG2,   // its two diagonal entries
+    PK_D4,      // the 2-qubit diagonal gate's entries, permuted by perm
+    PK_SCALE,   // one real
+    PK_SIDE,    // one diagonal entry of the product of `factors` (hdr.b: 0 or 1)
+    PK_G3,      // entry 3 of the 2-qubit diagonal gate (its one non-trivial entry)
+    PK_UDN,     // C and the term ratios of the merged uniform diagonals `ucon`
+};
+
+// One diagonal gate on thread or tile-base bits inside a merged OP_UDN.
+// With P(x, y) its value at source bits (x, y) (1-qubit gates: y = 0),
+// C *= P(0, 0) and the ratios P(1,0)/P(0,0) (term t0), P(0,1)/P(0,0) (t1)
+// and P(1,1) P(0,0) / (P(1,0) P(0,1)) (t01) multiply their terms.
+enum UContribKind : uint8_t { UC_D1 = 1, UC_D2, UC_YDIAG };
+struct UContrib {
+    int gate = -1;
+    uint8_t kind = UC_D1;
+    bool inv = false;                // 1-qubit: the label's XOR bit (values swapped)
+    uint8_t perm[4] = {0, 1, 2, 3};  // 2-qubit: (x << 1) | y -> gate-local index
+    int8_t t0 = -1, t1 = -1, t01 = -1;
+};
 
 // A pass operation plus the recipe of its payload (materialized per batch
 // entry from the gates' angles).
 struct HostOp {
     DevOp hdr{};
     uint8_t pk = PK_NONE;
-    std::vector<Factor> factors;   // PK_MAT2 / PK_DIAG2: product, first factor applied first
-    int gate = -1;                 // PK_D4: the 2-qubit diagonal gate
+    std::vector<Factor> factors;   // PK_MAT2 / PK_DIAG2 / PK_SIDE: product, first factor applied first
+    int gate = -1;                 // PK_D4 / PK_G3: the 2-qubit diagonal gate
     uint8_t perm[4] = {0, 1, 2, 3};  // PK_D4: payload entry e takes the gate's diagonal entry perm[e]
+    std::vector<UContrib> ucon;    // PK_UDN
+    int n_terms = 0;               // PK_UDN
     double scale = 1.0;
 };
 
@@ -74,6 +98,7 @@ struct PlanOptions {
     bool gen_h = true;    // generate leading Hadamards of a basis state
     bool basis_known = false;
     uint64_t basis_j = 0;
+    int ud_max = 3;       // terms of a merged uniform-diagonal operation
     int small_max = 12;   // largest n of the one-workgroup path
     int small_mode = 1;   // 1: use it below the tiled minimum; 2: whenever n allows
 };

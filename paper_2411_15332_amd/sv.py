@@ -283,5 +283,10 @@ def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] 
     out["layouts"] = take(int(h[14]), int(h[2]), LAYOUT_DTYPE)
     out["ops"] = take(int(h[15]), int(h[3]), OP_DTYPE)
     out["sops"] = take(int(h[16]), int(h[4]), SOP_DTYPE)
-    out["consts"] = buf[int(h[17]): int(h[17]) + 8 * int(h[5])].view(np.float64).copy()
+    # constants and op payloads are in the state's precision
+    f32 = dtype == "c64"
+    rb = 4 if f32 else 8
+    out["f32"] = f32
+    out["consts"] = buf[int(h[17]): int(h[17]) + rb * int(h[5])].view(
+        np.float32 if f32 else np.float64).astype(np.float64)
     return out

@@ -10,8 +10,9 @@ from __future__ import annotations
 
 import numpy as np
 
-(OP_EXCH, OP_D1R, OP_UD1, OP_UD2, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
- OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT) = range(1, 16)
+(OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
+ OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU) = range(1, 19)
+NO_SOURCE = 0xFF
 SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE = range(1, 11)
 SRC_REG, SRC_THR, SRC_TILE = 0, 1, 2
 PASS_GENERATE = 1
@@ -122,7 +123,7 @@ def run_plan(plan, psi, n):
         for op in plan["ops"][int(P["op_begin"]): int(P["op_end"])]:
             code, oa, ob, sa, sb, data = (int(op["code"]), int(op["a"]), int(op["b"]),
                                           int(op["sa"]), int(op["sb"]), int(op["data"]))
-            pl = op["payload"]
+            pl = op["payload"].view(np.float32).astype(np.float64) if plan.get("f32") else op["payload"]
             d = pl[0::2] + 1j * pl[1::2]
             if code == OP_EXCH:
                 # Two halves through a half-tile buffer: the half is the value
@@ -163,10 +164,25 @@ def run_plan(plan, psi, n):
             elif code == OP_D1R:
                 a = a * f * d[:2][(j_idx >> oa) & 1]
                 f = np.ones_like(f)
-            elif code == OP_UD1:
-                f = f * d[:2][src_bit(sa)]
-            elif code == OP_UD2:
-                f = f * d[:4][(src_bit(sa) << 1) | src_bit(sb)]
+            elif code == OP_UDN:
+                g = np.full((tiles, NT, 1), d[0], dtype=np.complex128)
+                for i in range(oa):
+                    if i < 4:
+                        s1, s2 = (data >> (16 * i)) & 0xFF, (data >> (16 * i + 8)) & 0xFF
+                    else:
+                        s1, s2 = sa, sb
+                    on = src_bit(s1) & (1 if s2 == NO_SOURCE else src_bit(s2))
+                    g = np.where(on == 1, g * d[i + 1], g)
+                f = f * g
+            elif code == OP_D1H:
+                sel = ((j_idx >> oa) & 1) == ob
+                a = np.where(sel, a * d[0], a)
+            elif code == OP_D2Q:
+                sel = (((j_idx >> oa) & 1) == (sa & 1)) & (((j_idx >> ob) & 1) == ((sa >> 1) & 1))
+                a = np.where(sel, a * d[0], a)
+            elif code == OP_D1HU:
+                sel = (((j_idx >> oa) & 1) == (ob & 1)) & (src_bit(sa) == ((ob >> 1) & 1))
+                a = np.where(sel, a * d[0], a)
             elif code == OP_APPLYF:
                 a = a * f
                 f = np.ones_like(f)

@@ -57,6 +57,12 @@ def test_validation_rejects(bad):
     assert P.last_error()
 
 
+# The emulation runs in FP64 with the plan's constants, which a complex64 plan
+# holds in FP32 (as the kernel receives them): its tolerance is the complex64
+# parity bound.
+EMU_TOL = {"c128": 1e-12, "c64": 1e-5}
+
+
 def _emulate(n, gates, dtype="c128", psi0=None, basis=0, **kw):
     plan = P.debug_plan(n, gates, dtype=dtype, basis=basis if psi0 is None else None, **kw)
     psi = O.basis_state(n, basis) if psi0 is None else psi0.copy()
@@ -72,7 +78,7 @@ def test_plan_emulation_random_circuits(n, depth, seed, dtype):
     gates = synth.random_circuit(n, depth, seed)
     ref = O.simulate(n, gates)
     got, plan = _emulate(n, gates, dtype)
-    assert np.max(np.abs(got - ref)) < 1e-12
+    assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
     if not plan["small"]:
         assert plan["gates"] == len([g for g in gates if g.name != "I"])
 
@@ -105,7 +111,7 @@ def test_every_gate_kind_every_position():
     ref = O.simulate(n, gates, psi0=psi0)
     for dt in ("c128", "c64"):
         got, _ = _emulate(n, gates, dt, psi0=psi0)
-        assert np.max(np.abs(got - ref)) < 1e-12
+        assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
 
 
 @pytest.mark.parametrize("j", [0, 5, 1023])
@@ -163,3 +169,30 @@ def test_relabel_only_pass_orders_loads_before_stores():
     assert all(int(p["flags"]) & 2 for p in plan["passes"] if int(p["store_layout"]) != 0)
     plain = P.debug_plan(n, [synth.Gate("Z", 11)])
     assert not any(int(p["flags"]) & 2 for p in plain["passes"])
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(13, 0), (14, 1)])
+def test_diagonal_heavy_mix(n, seed, dtype):
+    """Runs of phases on every kind of position (register, thread and
+    tile-base bits), with X and Y relabels in between, so that merged uniform
+    diagonals with single and AND terms, half- and quarter-slot diagonals and
+    register relabels all occur; results against the oracle."""
+    rng = np.random.default_rng(seed)
+    one = ("Z", "S", "SDG", "T", "TDG", "P", "RZ", "X", "Y", "H")
+    two = ("CZ", "CPHASE", "CNOT")
+    gates = [synth.Gate("H", q) for q in range(n)]
+    for _ in range(6):
+        for q in range(n):
+            name = one[int(rng.integers(len(one)))]
+            gates.append(synth.Gate(name, q, -1, float(rng.uniform(0, 2 * math.pi))))
+        for _ in range(n):
+            q0, q1 = (int(x) for x in rng.choice(n, 2, replace=False))
+            name = two[int(rng.integers(len(two)))]
+            gates.append(synth.Gate(name, q0, q1, float(rng.uniform(0, 2 * math.pi))))
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates, dtype)
+    assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
+    codes = set(int(c) for c in plan["ops"]["code"])
+    assert {3, 16, 17, 18} <= codes, codes          # UDN, D1H, D2Q, D1HU
+    assert plan["relabels"] > 0
