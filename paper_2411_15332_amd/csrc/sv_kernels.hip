@@ -542,7 +542,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 break;
             }
             case OP_MARK: {
-                if (base == op.data && tid == (int)op.b) {
+                if (base == op.data && tid == (int)(op.sa | (op.sb << 8))) {
 #pragma unroll
                     for (int j = 0; j < NR; ++j)
                         if (j == (int)op.a) a[j] = mk<T>(-a[j].x, -a[j].y);

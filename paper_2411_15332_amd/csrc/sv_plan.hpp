@@ -49,7 +49,7 @@ enum OpCode : uint8_t {
     OP_X = 10,       // swap the pairs of register bit a
     OP_CXR = 11,     // swap the pairs of register bit a where register bit b is 1
     OP_CXU = 12,     // swap the pairs of register bit a when the bit of source sa is 1
-    OP_MARK = 13,    // amp(slot a, thread b) *= -1 in the tile whose base equals `data`
+    OP_MARK = 13,    // amp(slot a, thread sa | sb << 8) *= -1 in the tile whose base equals `data`
     OP_SCALE = 14,   // amp *= s; payload s (one real)
     OP_CXT = 15,     // swap the pairs of register bit a when tile-base bit `sa` (a qubit
                      // outside the tile, the same for the whole workgroup) is 1

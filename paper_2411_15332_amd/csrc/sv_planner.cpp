@@ -398,18 +398,37 @@ struct PassCtx {
         int pk = -1;
         for (int p = 0; p < opt.R; ++p)
             if (a.reg[p] >= opt.m) { pk = p; break; }
-        if (pk < 0) throw std::logic_error("layout exchange: no register label to split on");
-        const int keep = a.reg[pk];
         LState M = b;
         M.storable = false;
         M.fixed_thr = w;
-        const int pb = find_in(b.reg, opt.R, keep);
-        if (pb >= 0) {
-            std::swap(M.reg[pk], M.reg[pb]);
+        int keep = -1;
+        if (pk >= 0) {
+            // M: b with a's register label `keep` at its register position in a
+            keep = a.reg[pk];
+            const int pb = find_in(b.reg, opt.R, keep);
+            if (pb >= 0) {
+                std::swap(M.reg[pk], M.reg[pb]);
+            } else {
+                const int tk = find_in(b.thr, w, keep);
+                M.thr[tk] = b.reg[pk];
+                M.reg[pk] = keep;
+            }
         } else {
-            const int tk = find_in(b.thr, w, keep);
-            M.thr[tk] = b.reg[pk];
-            M.reg[pk] = keep;
+            // every register label of a is below m: M is b with one of a's
+            // thread labels >= m at its thread position in a
+            int tk = -1;
+            for (int t = w - 1; t >= 0 && tk < 0; --t)
+                if (a.thr[t] >= opt.m) tk = t;
+            if (tk < 0) throw std::logic_error("layout exchange: no label to split on");
+            keep = a.thr[tk];
+            const int tb = find_in(b.thr, w, keep);
+            if (tb >= 0) {
+                std::swap(M.thr[tk], M.thr[tb]);
+            } else {
+                const int pb = find_in(b.reg, opt.R, keep);
+                M.reg[pb] = b.thr[tk];
+                M.thr[tk] = keep;
+            }
         }
         M.xmask = a.xmask & (1u << keep);
         uint8_t s1 = 0, s2 = 0;
@@ -755,7 +774,8 @@ struct PassCtx {
             for (int p = 0; p < opt.R; ++p) if ((phys >> reg_label[p]) & 1) j |= 1 << p;
             HostOp &o = emit(OP_MARK);
             o.hdr.a = (uint8_t)j;
-            o.hdr.b = (uint8_t)t;
+            o.hdr.sa = (uint8_t)(t & 0xFF);   // thread index: up to 2^10 threads
+            o.hdr.sb = (uint8_t)(t >> 8);
             o.hdr.data = g.index & ~qmask;
             break;
         }

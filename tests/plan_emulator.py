@@ -219,7 +219,7 @@ def run_plan(plan, psi, n):
                 x0, x1 = a[:, :, lo], a[:, :, hi]
                 a[:, :, lo], a[:, :, hi] = np.where(cb, x1, x0), np.where(cb, x0, x1)
             elif code == OP_MARK:
-                hit = (base == data) & (t_idx == ob) & (j_idx == oa)
+                hit = (base == data) & (t_idx == (sa | (sb << 8))) & (j_idx == oa)
                 a = np.where(hit, -a, a)
             elif code == OP_SCALE:
                 a = a * pl[0]

@@ -93,8 +93,8 @@ def test_plan_options(opts):
     assert np.max(np.abs(got - ref)) < 1e-12
 
 
-def test_every_gate_kind_every_position():
-    n = 11
+@pytest.mark.parametrize("n", [11, 14, 15])
+def test_every_gate_kind_every_position(n):
     rng = np.random.default_rng(0)
     gates = []
     for name in synth.GATE_NAMES:
@@ -155,7 +155,7 @@ def test_large_plan_statistics():
     assert plan["hbm_bytes"] == npass * 2 * (1 << 28) * 16 - (1 << 28) * 16 * 0
     # every gate of a pass lies on its tile qubits or is diagonal
     assert 30 < npass < 200
-    assert plan["k"] == 12 and plan["w"] == 8
+    assert plan["k"] == plan["R"] + plan["w"] and plan["w"] >= 8
 
 
 def test_relabel_only_pass_orders_loads_before_stores():
