@@ -163,14 +163,20 @@ void *sv_device_ptr(sv_state s);
  *   SV_OPT_SMALL_PATH     1 (default): states of n below the tiled minimum run
  *                         in one workgroup; 2: force that path when n allows.
  *   SV_OPT_PROFILE        1: time every pass kernel with HIP events (see
- *                         sv_profile_read); 0 (default): off. */
+ *                         sv_profile_read); 0 (default): off.
+ *   SV_OPT_REMAP          1 (default): between passes, move the qubits the
+ *                         next pass needs onto the contiguous low index bits
+ *                         (each pass stores its tile with its own bits
+ *                         permuted; the state is back in canonical order
+ *                         when sv_apply_circuit's work completes); 0: off. */
 enum sv_option {
     SV_OPT_FUSE = 1,
     SV_OPT_MIN_LOW_QUBITS = 2,
     SV_OPT_MAX_DENSE = 3,
     SV_OPT_ON_DEMAND_H = 4,
     SV_OPT_SMALL_PATH = 5,
-    SV_OPT_PROFILE = 6
+    SV_OPT_PROFILE = 6,
+    SV_OPT_REMAP = 7
 };
 sv_status sv_set_option(sv_state s, int option, int64_t value);
 

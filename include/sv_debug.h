@@ -18,14 +18,17 @@ extern "C" {
  * opts (may be NULL for defaults): [0] fuse (0/1), [1] lowest qubits kept in a
  * tile (3..7), [2] dense gates per pass, [3] on-demand Hadamards (0/1),
  * [4] state is a known basis state (0/1), [5] that basis index, [6] small-path
- * mode (1 or 2) — the meanings of the matching SV_OPT_* options.
+ * mode (1 or 2), [7] qubit remapping (0/1) — the meanings of the matching
+ * SV_OPT_* options.
  * Layout of `out`: 256-byte header of int64 fields
  *   [0] small path, [1] passes, [2] layouts, [3] ops, [4] small ops,
  *   [5] constant reals per batch entry, [6] exchanges, [7] generated
  *   Hadamards, [8] gates applied, [9] k, [10] w, [11] R, [12] swizzle width,
  *   [13..17] byte offsets of the pass, layout, op, small-op and constant
  *   arrays, [18] algorithmic HBM bytes, [19] relabelled permutation gates,
- * followed by those arrays (constants in FP64, batch entry 0).
+ *   [20] passes that only put qubits back on their own bits,
+ * followed by those arrays (constants in the state's precision: FP64 for
+ * SV_C128, FP32 for SV_C64; batch entry 0).
  * Returns the number of bytes the dump needs (nothing is written when `out`
  * is NULL or `cap` is smaller), or a negative sv_status on bad input. */
 int64_t sv_debug_plan(int n, int dtype, const sv_gate *gates, size_t n_gates,

@@ -65,6 +65,7 @@ PlanOptions plan_options(const sv_state_s *s) {
     o.basis_known = s->basis_known;
     o.basis_j = s->basis_j;
     o.small_mode = s->small_mode;
+    o.remap = s->remap;
     return o;
 }
 
@@ -494,6 +495,10 @@ sv_status sv_set_option(sv_state s, int option, int64_t value) {
             if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_PROFILE takes 0 or 1");
             s->profile = value != 0;
             return SV_OK;
+        case SV_OPT_REMAP:
+            if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_REMAP takes 0 or 1");
+            s->remap = value != 0;
+            return SV_OK;
         default:
             return fail(SV_EINVAL, "unknown option %d", option);
         }
@@ -691,6 +696,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
         tmp.basis_known = opts[4] != 0;
         tmp.basis_j = (uint64_t)opts[5];
         tmp.small_mode = (int)opts[6];
+        tmp.remap = opts[7] != 0;
     }
     const PlanOptions po = plan_options(&tmp);
     Plan p = build_plan(n, gates, n_gates, po);
@@ -724,6 +730,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     h[17] = (int64_t)(header + L.consts);
     h[18] = plan_hbm_bytes(p, n, dtype == SV_C128 ? 16 : 8);
     h[19] = p.n_relabel;
+    h[20] = p.n_restore;
     serialize_plan(p, L, gates, params, n_params, 1, dtype == SV_C64, o + header);
     return (int64_t)total;
 }

@@ -64,6 +64,7 @@ struct sv_state_s {
     int max_dense = 1 << 20;
     bool gen_h = true;
     int small_mode = 1;
+    bool remap = true;
     bool profile = false;
 
     // plan upload: pinned staging + device copy

@@ -145,47 +145,39 @@ struct Blocker {
     }
 };
 
-// Split the gates into passes (lists of indices into cg) and their tile sets.
-static std::vector<std::vector<int>> form_passes(const std::vector<CGate> &cg,
-                                                 const std::vector<int> &order, int n, int k,
-                                                 const PlanOptions &opt, int c,
-                                                 std::vector<uint64_t> &qsets) {
-    std::vector<std::vector<int>> passes;
-    std::vector<int> pending = order;
+// One pass: take gates in order (moving a gate past deferred ones only where
+// they commute) while the union of their tile needs fits k qubits, starting
+// from the qubits that must be in every tile (`low`). Returns the tile set;
+// `taken` and `deferred` are indices into cg.
+static uint64_t form_one_pass(const std::vector<CGate> &cg, const std::vector<int> &pending,
+                              int n, int k, const PlanOptions &opt, uint64_t low,
+                              std::vector<int> &taken, std::vector<int> &deferred) {
     const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
-    const uint64_t low = bit(c) - 1;
-    while (!pending.empty()) {
-        uint64_t Q = low & all;
-        Blocker blk;
-        std::vector<int> taken, deferred;
-        int dense = 0;
-        bool closed = false;
-        for (size_t i = 0; i < pending.size(); ++i) {
-            const int gi = pending[i];
-            const CGate &g = cg[gi];
-            if (closed) { deferred.push_back(gi); continue; }
-            bool take = false;
-            if (!blk.conflicts(g)) {
-                const bool dense_ok = g.cls != G_DENSE1 || dense < opt.max_dense;
-                if (dense_ok && (g.qneed & ~Q) == 0) take = true;
-                else if (dense_ok && popc(Q | g.qneed) <= k) { Q |= g.qneed; take = true; }
-            }
-            if (take) {
-                taken.push_back(gi);
-                if (g.cls == G_DENSE1) ++dense;
-                if (!opt.fuse) closed = true;
-            } else {
-                deferred.push_back(gi);
-                blk.defer(g);
-                if ((blk.nondiag & all) == all) closed = true;  // nothing can move past
-            }
+    uint64_t Q = low & all;
+    Blocker blk;
+    int dense = 0;
+    bool closed = false;
+    for (size_t i = 0; i < pending.size(); ++i) {
+        const int gi = pending[i];
+        const CGate &g = cg[gi];
+        if (closed) { deferred.push_back(gi); continue; }
+        bool take = false;
+        if (!blk.conflicts(g)) {
+            const bool dense_ok = g.cls != G_DENSE1 || dense < opt.max_dense;
+            if (dense_ok && (g.qneed & ~Q) == 0) take = true;
+            else if (dense_ok && popc(Q | g.qneed) <= k) { Q |= g.qneed; take = true; }
         }
-        for (int qq = 0; qq < n && popc(Q) < k; ++qq) Q |= bit(qq);  // fill with the lowest qubits
-        passes.push_back(taken);
-        qsets.push_back(Q);
-        pending.swap(deferred);
+        if (take) {
+            taken.push_back(gi);
+            if (g.cls == G_DENSE1) ++dense;
+            if (!opt.fuse) closed = true;
+        } else {
+            deferred.push_back(gi);
+            blk.defer(g);
+            if ((blk.nondiag & all) == all) closed = true;  // nothing can move past
+        }
     }
-    return passes;
+    return Q;
 }
 
 static double hadamard_magnitude(int h) {
@@ -225,7 +217,10 @@ struct PassCtx {
     Plan &P;
     const std::vector<CGate> &cg;
     int n, k, w;
-    uint8_t q[32];
+    uint8_t q[32];          // physical bit position of label l (ascending): the tile's bits
+    uint8_t gpos[32];       // physical bit each label is addressed at by the layout being built
+    const int *phys = nullptr;   // physical bit of every logical qubit (qubits off the tile)
+    const int *logi = nullptr;   // logical qubit at every physical bit
     int label_of[64];
     // layout state: position of every label and the XOR mask
     int reg_label[kLayoutRegBits], thr_label[kLayoutThreadBits];
@@ -443,6 +438,34 @@ struct PassCtx {
         emit_exch(ml, layout_index(), s2, l2);
     }
 
+    // Bring the final layout into lane order for the store: lane s holds
+    // label lane[s] and, with v, register 0 holds reg0 (labels the store
+    // addresses at the tile's lowest bits). Exchanges only when the current
+    // layout differs; other registers stay where they are if possible.
+    void settle_lanes(const int *lane, int reg0) {
+        bool same = true;
+        for (int s = 0; s < 6; ++s) same &= thr_label[s] == lane[s];
+        if (opt.v) same &= reg_label[0] == reg0;
+        if (same) return;
+        LState b{};
+        uint32_t placed = 0;
+        for (int s = 0; s < 6; ++s) { b.thr[s] = lane[s]; placed |= 1u << lane[s]; }
+        int p = 0, t = 6;
+        if (opt.v) { b.reg[p++] = reg0; placed |= 1u << reg0; }
+        for (int pr = opt.v; pr < opt.R; ++pr)
+            if (!((placed >> reg_label[pr]) & 1)) { b.reg[p++] = reg_label[pr]; placed |= 1u << reg_label[pr]; }
+        for (int l = 0; l < k; ++l) {
+            if ((placed >> l) & 1) continue;
+            if (p < opt.R) b.reg[p++] = l;
+            else b.thr[t++] = l;
+            placed |= 1u << l;
+        }
+        b.xmask = 0;
+        b.fixed_thr = 6;
+        b.storable = opt.v != 0;   // keeps register 0 pinned in the exchange search
+        exchange_to(b);
+    }
+
     bool is_storable() const {
         for (int s = 0; s < 6; ++s)
             if (thr_label[s] < opt.v || thr_label[s] >= opt.v + 6) return false;
@@ -465,24 +488,26 @@ struct PassCtx {
         DevLayout L;
         std::memset(&L, 0, sizeof L);
         for (int s = 0; s < w; ++s) {
-            L.thr_goff[s] = 1ull << q[thr_label[s]];
+            L.thr_goff[s] = 1ull << gpos[thr_label[s]];
             L.thr_slot[s] = slot_lin(thr_label[s], opt.m);
             L.thr_local[s] = (uint8_t)thr_label[s];
         }
         for (int p = 0; p < opt.R; ++p) {
-            L.reg_goff[p] = 1ull << q[reg_label[p]];
+            L.reg_goff[p] = 1ull << gpos[reg_label[p]];
             L.reg_slot[p] = slot_lin(reg_label[p], opt.m);
             L.reg_local[p] = (uint8_t)reg_label[p];
         }
         for (int l = 0; l < k; ++l) {
             if ((xmask >> l) & 1) {
-                if (pos_reg[l] >= 0) L.reg_goff_xor ^= 1ull << q[l];
-                else L.goff_xor ^= 1ull << q[l];
+                if (pos_reg[l] >= 0) L.reg_goff_xor ^= 1ull << gpos[l];
+                else L.goff_xor ^= 1ull << gpos[l];
                 L.slot_xor ^= slot_lin(l, opt.m);
             }
         }
         L.xor_local = xmask;
-        if (opt.v && reg_label[0] == 0 && !(xmask & 1)) L.flags |= LAYOUT_PAIR_IO;
+        // complex64 16-byte I/O: register bit 0 addresses physical bit 0
+        if (opt.v && gpos[reg_label[0]] == 0 && !((xmask >> reg_label[0]) & 1))
+            L.flags |= LAYOUT_PAIR_IO;
         P.layouts.push_back(L);
         cur_layout = (int)P.layouts.size() - 1 - layout_begin;
         return cur_layout;
@@ -492,7 +517,7 @@ struct PassCtx {
         Src s{};
         const int l = label_of[qubit];
         if (l < 0) {
-            s.code = (uint8_t)(SRC_TILE | qubit);
+            s.code = (uint8_t)(SRC_TILE | phys[qubit]);
             s.inv = 0;
             s.reg = false;
             return s;
@@ -764,9 +789,12 @@ struct PassCtx {
             for (int p = 0; p < opt.R; ++p) flush_nondiag(p);
             uint64_t qmask = 0;
             uint32_t lm = 0;
+            uint64_t pidx = 0;   // the marked index with its bits at their physical positions
+            for (int qq = 0; qq < n; ++qq)
+                if ((g.index >> qq) & 1) pidx |= bit(phys[qq]);
             for (int l = 0; l < k; ++l) {
                 qmask |= bit(q[l]);
-                if ((g.index >> q[l]) & 1) lm |= 1u << l;
+                if ((pidx >> q[l]) & 1) lm |= 1u << l;
             }
             const uint32_t phys = lm ^ xmask;
             int t = 0, j = 0;
@@ -776,7 +804,7 @@ struct PassCtx {
             o.hdr.a = (uint8_t)j;
             o.hdr.sa = (uint8_t)(t & 0xFF);   // thread index: up to 2^10 threads
             o.hdr.sb = (uint8_t)(t >> 8);
-            o.hdr.data = g.index & ~qmask;
+            o.hdr.data = pidx & ~qmask;
             break;
         }
         case G_X: {
@@ -923,24 +951,82 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     P.n_gen_h = popc(gen_mask);
     P.gates_applied += P.n_gen_h;
 
-    std::vector<int> order;
-    for (size_t i = start; i < cg.size(); ++i) order.push_back((int)i);
+    std::vector<int> pending;
+    for (size_t i = start; i < cg.size(); ++i) pending.push_back((int)i);
     const int c = std::max(opt.v + 1, std::min(opt.c, k - 2));
-    std::vector<uint64_t> qsets;
-    std::vector<std::vector<int>> groups = form_passes(cg, order, n, k, opt, c, qsets);
-    if (groups.empty() && generate) {
-        groups.emplace_back();
-        qsets.push_back(bit(k) - 1);
-    }
 
-    for (size_t pi = 0; pi < groups.size(); ++pi) {
+    // Qubit remapping: logical qubit q lives at physical index bit phys[q].
+    // Every tile contains the c lowest physical bits (contiguous HBM runs);
+    // a pass may store its tile under any permutation of the tile's own
+    // physical bits, so the store puts on the low bits the qubits the next
+    // pass needs. Passes at the end put every qubit back (phys = identity).
+    std::vector<int> phys(n), logi(n);
+    for (int q = 0; q < n; ++q) phys[q] = logi[q] = q;
+    const bool remap = opt.remap && opt.fuse && n > k;
+    auto low_set = [&]() {
+        uint64_t m = 0;
+        for (int p = 0; p < c; ++p) m |= bit(logi[p]);
+        return m;
+    };
+    auto identity = [&]() {
+        for (int q = 0; q < n; ++q) if (phys[q] != q) return false;
+        return true;
+    };
+
+    // Tile set of a restoring pass: the low bits and the qubits homed there
+    // (every displacement is a pair of a low bit and a high bit).
+    auto restore_set = [&]() {
+        uint64_t Q = low_set();
+        for (int a = 0; a < c; ++a) Q |= bit(a);
+        for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(logi[p]);
+        return Q;
+    };
+
+    bool first = true;
+    int restores = 0;
+    while (true) {
+        std::vector<int> taken, deferred;
+        uint64_t Q;
+        bool restoring = false;
+        uint64_t want = 0;
+        bool home_lanes = false;
+        if (!pending.empty() || (first && generate)) {
+            Q = form_one_pass(cg, pending, n, k, opt, low_set(), taken, deferred);
+            if (remap) {
+                // qubits the next pass wants on the low bits: spare tile
+                // slots take them so that the store can put them there
+                if (!deferred.empty()) {
+                    std::vector<int> t2, d2;
+                    want = form_one_pass(cg, deferred, n, k, opt, 0, t2, d2);
+                    for (int qq = 0; qq < n && popc(Q) < k; ++qq)
+                        if (((want >> qq) & 1) && phys[qq] == qq) Q |= bit(qq);
+                } else {
+                    home_lanes = true;   // last gate pass: head home
+                    for (int a = 0; a < c && popc(Q) < k; ++a) Q |= bit(a);
+                }
+            }
+            for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(logi[p]);
+        } else if (remap && !identity()) {
+            if (++restores > 2 * n) throw std::logic_error("qubit order not restored");
+            Q = restore_set();
+            restoring = true;
+            home_lanes = true;
+        } else {
+            break;
+        }
+
         PassCtx X(opt, P, cg, n, k, w);
         X.gkinds = kinds.data();
-        const uint64_t Q = qsets[pi];
+        X.phys = phys.data();
+        X.logi = logi.data();
         for (int qq = 0; qq < 64; ++qq) X.label_of[qq] = -1;
         std::memset(X.q, 0, sizeof X.q);
-        for (int qq = 0, l = 0; qq < n; ++qq)
-            if ((Q >> qq) & 1) { X.q[l] = (uint8_t)qq; X.label_of[qq] = l; ++l; }
+        {
+            int l = 0;
+            for (int p = 0; p < n; ++p)   // labels in ascending physical order
+                if ((Q >> logi[p]) & 1) { X.q[l] = (uint8_t)p; X.label_of[logi[p]] = l; ++l; }
+        }
+        for (int l = 0; l < k; ++l) X.gpos[l] = X.q[l];
 
         DevPass dp;
         std::memset(&dp, 0, sizeof dp);
@@ -952,7 +1038,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         dp.layout_begin = (int)P.layouts.size();
         X.layout_begin = dp.layout_begin;
 
-        std::vector<int> rem = groups[pi];
+        std::vector<int> rem = taken;
         const uint64_t U = X.U_labels();
         const int ru = opt.R - opt.v;
         auto labels_of = [&](uint64_t qmask) {
@@ -980,7 +1066,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         X.load(X.storable(S0));
         X.layout_index();
 
-        while (true) {
+        while (!rem.empty()) {
             Blocker blk;
             std::vector<int> left;
             for (int gi : rem) {
@@ -1023,14 +1109,96 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             }
         }
         X.flush_all();
-        if (!X.is_storable()) {
-            uint64_t su = X.reg_labels() & U;
-            while (popc(su) > ru) su &= su - 1;
-            for (int lb = 0; lb < k && popc(su) < ru; ++lb)
-                if ((U >> lb) & 1) su |= bit(lb);
-            X.exchange_to(X.storable(su));
+
+        int sigma[32];   // new physical bit of every label
+        for (int l = 0; l < k; ++l) sigma[l] = X.q[l];
+        if (!remap) {
+            if (!X.is_storable()) {
+                uint64_t su = X.reg_labels() & U;
+                while (popc(su) > ru) su &= su - 1;
+                for (int lb = 0; lb < k && popc(su) < ru; ++lb)
+                    if ((U >> lb) & 1) su |= bit(lb);
+                X.exchange_to(X.storable(su));
+            }
+        } else {
+            // Remapping keeps every displaced qubit in a pair: the low bit a
+            // holds the qubit homed at a high bit h, and qubit a sits at h.
+            // The store may undo pairs (both bits in the tile) and make new
+            // ones (a wanted qubit at its home h in the tile takes a low bit
+            // whose own qubit moves to h). Unchanged qubits stay put.
+            for (int a = 0; a < n; ++a) {
+                const int h = logi[a];
+                if (h == a) continue;
+                const bool ok = (a < c && h >= c && phys[a] == h) || (a >= c && h < c && logi[h] == a);
+                if (!ok) throw std::logic_error("qubit pair invariant broken");
+            }
+            uint64_t inP = 0;
+            for (int l = 0; l < k; ++l) inP |= bit(X.q[l]);
+            std::vector<int> dest(n, -1);   // new physical bit of moved logical qubits
+            const bool free_exch = !X.is_storable();
+            const uint64_t Wm = home_lanes ? 0 : want;
+            int undone = 0, made = 0;
+            for (int a = 0; a < c; ++a) {
+                const int h = logi[a];
+                if (h == a || !((inP >> h) & 1)) continue;   // no pair, or qubit a off the tile
+                if (!home_lanes && ((Wm >> h) & 1)) continue;  // the next pass wants h low
+                dest[h] = h;
+                dest[a] = a;
+                ++undone;
+            }
+            if (!home_lanes) {
+                uint64_t taken_low = 0;
+                for (int hq = 0; hq < n; ++hq) {
+                    if (!((Wm >> hq) & 1) || hq < c || phys[hq] != hq || !((inP >> hq) & 1)) continue;
+                    int slot = -1;
+                    for (int a = 0; a < c && slot < 0; ++a) {
+                        if ((taken_low >> a) & 1) continue;
+                        // low bit a holds (or gets back, after an undo) its own qubit
+                        const bool own = dest[a] == a || (logi[a] == a && dest[a] < 0);
+                        if (own && !((Wm >> a) & 1)) slot = a;
+                    }
+                    if (slot < 0) break;
+                    dest[hq] = slot;
+                    dest[slot] = hq;
+                    taken_low |= bit(slot);
+                    ++made;
+                }
+            }
+            // A lane change costs an exchange unless the pass ends with one.
+            if (!home_lanes && !free_exch && made < 2) {
+                std::fill(dest.begin(), dest.end(), -1);
+                undone = made = 0;
+            }
+            for (int l = 0; l < k; ++l) {
+                const int x = logi[X.q[l]];
+                sigma[l] = dest[x] >= 0 ? dest[x] : X.q[l];
+            }
+            uint64_t hit = 0;
+            for (int l = 0; l < k; ++l) hit |= bit(sigma[l]);
+            if (hit != inP) throw std::logic_error("store permutation is not a bijection of the tile");
+            int lane[6], reg0 = -1;
+            for (int l = 0; l < k; ++l) {
+                if (opt.v && sigma[l] == X.q[0]) reg0 = l;
+                for (int s2 = 0; s2 < 6; ++s2)
+                    if (sigma[l] == X.q[opt.v + s2]) lane[s2] = l;
+            }
+            X.settle_lanes(lane, reg0);
+        }
+        bool moved_any = false;
+        for (int l = 0; l < k; ++l) moved_any |= X.gpos[l] != (uint8_t)sigma[l];
+        if (moved_any) {   // the store addresses the labels at their new bits
+            for (int l = 0; l < k; ++l) X.gpos[l] = (uint8_t)sigma[l];
+            X.cur_layout = -1;
         }
         dp.store_layout = X.layout_index();
+        if (remap) {
+            std::vector<int> moved(k);
+            for (int l = 0; l < k; ++l) moved[l] = logi[X.q[l]];
+            for (int l = 0; l < k; ++l) {
+                phys[moved[l]] = sigma[l];
+                logi[sigma[l]] = moved[l];
+            }
+        }
         // In-place safety: without an exchange, nothing orders one wave's loads
         // before another wave's stores to the same tile.
         bool exch_in_pass = false;
@@ -1038,26 +1206,29 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             if (P.ops[oi].hdr.code == OP_EXCH) exch_in_pass = true;
         if (!exch_in_pass && dp.store_layout != 0) dp.flags |= PASS_SYNC_STORE;
 
-        if (pi == 0 && generate) {
+        if (first && generate) {
             dp.flags |= PASS_GENERATE;
             dp.gen_j = opt.basis_j;
             dp.gen_mask = gen_mask;
             dp.gen_scale = hadamard_magnitude(popc(gen_mask));
         }
         if (X.h_count > 0) {
-            const double s = hadamard_magnitude(X.h_count);
+            const double sc = hadamard_magnitude(X.h_count);
             if (X.first_payload >= 0) {
-                P.ops[X.first_payload].scale *= s;
+                P.ops[X.first_payload].scale *= sc;
             } else if (dp.flags & PASS_GENERATE) {
-                dp.gen_scale *= s;
+                dp.gen_scale *= sc;
             } else {
                 HostOp &so = X.emit(OP_SCALE);
                 so.pk = PK_SCALE;
-                so.scale = s;
+                so.scale = sc;
             }
         }
         dp.op_end = (int)P.ops.size();
         P.passes.push_back(dp);
+        if (restoring) ++P.n_restore;
+        first = false;
+        pending.swap(deferred);
     }
     return P;
 }

@@ -94,6 +94,7 @@ struct PlanOptions {
     int c = 6;            // lowest qubits always in the tile
     int w_max = 8;        // thread bits of a full workgroup
     bool fuse = true;     // false: one pass per gate
+    bool remap = true;    // permute the tile's address bits at each store (see build_plan)
     int max_dense = 1 << 20;  // dense register operations (DENSE1) per pass
     bool gen_h = true;    // generate leading Hadamards of a basis state
     bool basis_known = false;
@@ -116,6 +117,7 @@ struct Plan {
     int64_t n_gen_h = 0;
     int64_t gates_applied = 0;
     int64_t n_relabel = 0;             // permutation gates absorbed into layouts
+    int64_t n_restore = 0;             // passes that only put qubits back on their own bits
 };
 
 // Structural classification of a validated gate (independent of the angle).

@@ -25,7 +25,8 @@ GATE_KIND = {
     "CPHASE": 16, "MARK": 17,
 }
 
-OPT_FUSE, OPT_MIN_LOW_QUBITS, OPT_MAX_DENSE, OPT_ON_DEMAND_H, OPT_SMALL_PATH, OPT_PROFILE = 1, 2, 3, 4, 5, 6
+OPT_FUSE, OPT_MIN_LOW_QUBITS, OPT_MAX_DENSE, OPT_ON_DEMAND_H, OPT_SMALL_PATH, OPT_PROFILE, OPT_REMAP = \
+    1, 2, 3, 4, 5, 6, 7
 
 # struct sv_gate (32 bytes)
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("param", "<i4"),
@@ -254,12 +255,13 @@ assert OP_DTYPE.itemsize == 80 and SOP_DTYPE.itemsize == 16
 
 def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] = None,
                fuse: bool = True, min_low: int = 6, max_dense: int = 1 << 20,
-               gen_h: bool = True, basis: Optional[int] = 0, small_mode: int = 1) -> dict:
+               gen_h: bool = True, basis: Optional[int] = 0, small_mode: int = 1,
+               remap: bool = True) -> dict:
     """The plan sv_apply_circuit would run (no GPU needed): see include/sv_debug.h."""
     arr = np.ascontiguousarray(gate_array(gates))
     p = None if params is None else np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
     opts = np.array([int(fuse), min_low, max_dense, int(gen_h), int(basis is not None),
-                     0 if basis is None else basis, small_mode, 0], dtype=np.int64)
+                     0 if basis is None else basis, small_mode, int(remap)], dtype=np.int64)
     dt = SV_C128 if dtype == "c128" else SV_C64
     L = lib()
     need = L.sv_debug_plan(n, dt, _ptr(arr), len(arr), _ptr(p), 0 if p is None else len(p),
@@ -274,7 +276,7 @@ def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] 
     h = buf[:256].view(np.int64)
     out = {"small": bool(h[0]), "k": int(h[9]), "w": int(h[10]), "R": int(h[11]), "m": int(h[12]),
            "exchanges": int(h[6]), "generated_h": int(h[7]), "gates": int(h[8]),
-           "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19])}
+           "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19]), "restores": int(h[20])}
 
     def take(off, count, dt_):
         return buf[off: off + count * dt_.itemsize].view(dt_).copy()

@@ -196,3 +196,27 @@ def test_diagonal_heavy_mix(n, seed, dtype):
     codes = set(int(c) for c in plan["ops"]["code"])
     assert {3, 16, 17, 18} <= codes, codes          # UDN, D1H, D2Q, D1HU
     assert plan["relabels"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,depth,seed,kind", [(16, 14, 3, "random"), (17, 10, 4, "random"),
+                                              (16, 12, 6, "capacity")])
+def test_remapped_plans(n, depth, seed, kind, dtype):
+    """Multi-pass plans whose stores permute the tile's bits (qubit
+    remapping), including the passes that put qubits back, against the
+    oracle; remapping never costs passes here and does move qubits."""
+    gates = (synth.random_circuit(n, depth, seed) if kind == "random"
+             else synth.capacity_circuit(n, depth, seed))
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates, dtype)
+    assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
+    fixed = P.debug_plan(n, gates, dtype=dtype, remap=False)
+    assert len(plan["passes"]) <= len(fixed["passes"])
+    lay = plan["layouts"]
+    moved = 0
+    for p in plan["passes"]:
+        L0 = lay[int(p["layout_begin"])]
+        Ls = lay[int(p["layout_begin"]) + int(p["store_layout"])]
+        moved += int(sorted(L0["thr_goff"][:8].tolist()) != sorted(Ls["thr_goff"][:8].tolist())
+                     or sorted(L0["reg_goff"][:plan["R"]].tolist()) != sorted(Ls["reg_goff"][:plan["R"]].tolist()))
+    assert moved > 0
