@@ -234,20 +234,37 @@ __device__ __forceinline__ void r_scale(cpx<T> (&a)[NR], T s) {
         SV_CASE_B(4, __VA_ARGS__) SV_CASE_B(5, __VA_ARGS__) default : break;   \
     }
 
+// An operation record as the kernel reads it: the same 80 bytes as DevOp,
+// with the byte fields of the header taken from two aligned 32-bit words
+// (a byte field read on its own can become a vector load whose latency the
+// interpreter would wait out on every operation).
+struct OpRec {
+    uint32_t h0;            // code | a << 8 | b << 16 | sa << 24
+    uint32_t h1;            // sb | pad
+    uint64_t data;
+    uint64_t payload[8];
+    __device__ __forceinline__ uint32_t code() const { return h0 & 0xFFu; }
+    __device__ __forceinline__ uint32_t a() const { return (h0 >> 8) & 0xFFu; }
+    __device__ __forceinline__ uint32_t b() const { return (h0 >> 16) & 0xFFu; }
+    __device__ __forceinline__ uint32_t sa() const { return h0 >> 24; }
+    __device__ __forceinline__ uint32_t sb() const { return h1 & 0xFFu; }
+};
+static_assert(sizeof(OpRec) == sizeof(DevOp), "OpRec mirrors DevOp");
+
 // Payload element i of an operation, as T (i is a compile-time constant at
 // every call site, so the record stays in scalar registers).
 template <typename T>
-__device__ __forceinline__ T pl(const DevOp &op, int i);
+__device__ __forceinline__ T pl(const OpRec &op, int i);
 template <>
-__device__ __forceinline__ double pl<double>(const DevOp &op, int i) {
+__device__ __forceinline__ double pl<double>(const OpRec &op, int i) {
     return __builtin_bit_cast(double, op.payload[i]);
 }
 template <>
-__device__ __forceinline__ float pl<float>(const DevOp &op, int i) {
+__device__ __forceinline__ float pl<float>(const OpRec &op, int i) {
     return __builtin_bit_cast(float, (uint32_t)(op.payload[i >> 1] >> (32 * (i & 1))));
 }
 template <typename T>
-__device__ __forceinline__ cpx<T> plc(const DevOp &op, int e) {
+__device__ __forceinline__ cpx<T> plc(const OpRec &op, int e) {
     return mk<T>(pl<T>(op, 2 * e), pl<T>(op, 2 * e + 1));
 }
 
@@ -366,9 +383,13 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
 
     // Global index of the tile's amplitude with all tile-local bits zero:
     // the tile number with zeros inserted at the tile qubits (ascending).
+    // (q[] is read as aligned 32-bit words: scalar loads, not byte loads)
+    const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
     uint64_t base = blockIdx.x;
-    for (int l = 0; l < k; ++l) {
-        const int b = P.q[l];
+#pragma unroll
+    for (int l = 0; l < 28; ++l) {
+        if (l >= k) break;
+        const int b = (qw[l >> 2] >> (8 * (l & 3))) & 0xFF;
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
 
@@ -410,18 +431,19 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
     const int oe = P.op_end;
     int oi = P.op_begin;
     if (oi < oe) {
-        DevOp op = opb[oi];
+        const OpRec *recs = reinterpret_cast<const OpRec *>(opb);
+        OpRec op = recs[oi];
         for (;;) {
-            const DevOp nxt = opb[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
-            switch (op.code) {
+            const OpRec nxt = recs[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
+            switch (op.code()) {
             case OP_EXCH: {
-                const uint32_t lo = (1u << op.sb) - 1u;
+                const uint32_t lo = (1u << op.sb()) - 1u;
                 uint64_t gd;
                 uint32_t tw, tr, sw[NR], sr[NR];
-                thr_part<W>(LB[op.a], tid, gd, tw);
-                thr_part<W>(LB[op.b], tid, gd, tr);
-                reg_slot<R>(LB[op.a], sw);
-                reg_slot<R>(LB[op.b], sr);
+                thr_part<W>(LB[op.a()], tid, gd, tw);
+                thr_part<W>(LB[op.b()], tid, gd, tr);
+                reg_slot<R>(LB[op.a()], sw);
+                reg_slot<R>(LB[op.b()], sr);
                 tw = drop_bit(tw, lo) << SH;
                 tr = drop_bit(tr, lo) << SH;
 #pragma unroll
@@ -429,19 +451,19 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                     sw[j] = drop_bit(sw[j], lo) << SH;
                     sr[j] = drop_bit(sr[j], lo) << SH;
                 }
-                if ((op.sa & ~SRC_POS_MASK) == SRC_REG) {
-                    SV_SWITCH_A(op.sa & SRC_POS_MASK, exch_reg_halves<PA>(a, ldsb, tw, sw, tr, sr))
+                if ((op.sa() & ~SRC_POS_MASK) == SRC_REG) {
+                    SV_SWITCH_A(op.sa() & SRC_POS_MASK, exch_reg_halves<PA>(a, ldsb, tw, sw, tr, sr))
                 } else {
-                    exch_thr_halves(a, ldsb, tw, sw, tr, sr, (tid >> (op.sa & SRC_POS_MASK)) & 1);
+                    exch_thr_halves(a, ldsb, tw, sw, tr, sr, (tid >> (op.sa() & SRC_POS_MASK)) & 1);
                 }
                 break;
             }
             case OP_D1H: {
                 const cpx<T> d = plc<T>(op, 0);
-                if (op.b) {
-                    SV_SWITCH_A(op.a, r_d1_half<PA, 1>(a, d))
+                if (op.b()) {
+                    SV_SWITCH_A(op.a(), r_d1_half<PA, 1>(a, d))
                 } else {
-                    SV_SWITCH_A(op.a, r_d1_half<PA, 0>(a, d))
+                    SV_SWITCH_A(op.a(), r_d1_half<PA, 0>(a, d))
                 }
                 break;
             }
@@ -449,29 +471,29 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 // rare (both qubits of a CZ / CPHASE in registers): selects
                 // keep the code small instead of one body per bit pair
                 const cpx<T> d = plc<T>(op, 0), one = mk<T>((T)1, (T)0);
-                const int xa = op.sa & 1, xb = (op.sa >> 1) & 1;
+                const int xa = op.sa() & 1, xb = (op.sa() >> 1) & 1;
 #pragma unroll
                 for (int j = 0; j < NR; ++j) {
-                    const bool hit = ((j >> op.a) & 1) == xa && ((j >> op.b) & 1) == xb;
+                    const bool hit = ((j >> op.a()) & 1) == xa && ((j >> op.b()) & 1) == xb;
                     cmul_ip(a[j], hit ? d : one);
                 }
                 break;
             }
             case OP_D1HU: {
                 const cpx<T> d = plc<T>(op, 0);
-                const bool on = src_bit(op.sa, tid, base) == ((op.b >> 1) & 1);
+                const bool on = src_bit(op.sa(), tid, base) == ((op.b() >> 1) & 1);
                 const cpx<T> e = on ? d : mk<T>((T)1, (T)0);
-                if (op.b & 1) {
-                    SV_SWITCH_A(op.a, r_d1_half<PA, 1>(a, e))
+                if (op.b() & 1) {
+                    SV_SWITCH_A(op.a(), r_d1_half<PA, 1>(a, e))
                 } else {
-                    SV_SWITCH_A(op.a, r_d1_half<PA, 0>(a, e))
+                    SV_SWITCH_A(op.a(), r_d1_half<PA, 0>(a, e))
                 }
                 break;
             }
             case OP_D1R: {
                 const cpx<T> d0 = cmul(f, plc<T>(op, 0)), d1 = cmul(f, plc<T>(op, 1));
                 f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a, r_d1_reg<PA>(a, d0, d1))
+                SV_SWITCH_A(op.a(), r_d1_reg<PA>(a, d0, d1))
                 break;
             }
             case OP_UDN: {
@@ -481,9 +503,9 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 constexpr int UDT = sizeof(T) == 8 ? kMaxUdTermsC128 : kMaxUdTerms;
 #pragma unroll
                 for (int i = 0; i < UDT; ++i) {
-                    if (i >= (int)op.a) break;
-                    const uint8_t s1 = i < 4 ? (uint8_t)(op.data >> (16 * i)) : op.sa;
-                    const uint8_t s2 = i < 4 ? (uint8_t)(op.data >> (16 * i + 8)) : op.sb;
+                    if (i >= (int)op.a()) break;
+                    const uint8_t s1 = i < 4 ? (uint8_t)(op.data >> (16 * i)) : op.sa();
+                    const uint8_t s2 = i < 4 ? (uint8_t)(op.data >> (16 * i + 8)) : op.sb();
                     const int on = src_bit(s1, tid, base) & (s2 == kNoSource ? 1 : src_bit(s2, tid, base));
                     const cpx<T> r = plc<T>(op, i + 1);
                     g = on ? cmul(g, r) : g;
@@ -500,52 +522,52 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 const cpx<T> d[4] = {cmul(f, plc<T>(op, 0)), cmul(f, plc<T>(op, 1)),
                                      cmul(f, plc<T>(op, 2)), cmul(f, plc<T>(op, 3))};
                 f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA != PB) r_d2_regreg<PA, PB>(a, d)))
+                SV_SWITCH_A(op.a(), SV_SWITCH_B(op.b(), if constexpr (PA != PB) r_d2_regreg<PA, PB>(a, d)))
                 break;
             }
             case OP_D2RU: {
-                const int u = src_bit(op.sa, tid, base);
+                const int u = src_bit(op.sa(), tid, base);
                 const cpx<T> e0 = cmul(f, u ? plc<T>(op, 2) : plc<T>(op, 0));
                 const cpx<T> e1 = cmul(f, u ? plc<T>(op, 3) : plc<T>(op, 1));
                 f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a, r_d1_reg<PA>(a, e0, e1))
+                SV_SWITCH_A(op.a(), r_d1_reg<PA>(a, e0, e1))
                 break;
             }
             case OP_DENSE1: {
                 const cpx<T> g00 = cmul(f, plc<T>(op, 0)), g01 = cmul(f, plc<T>(op, 1));
                 const cpx<T> g10 = cmul(f, plc<T>(op, 2)), g11 = cmul(f, plc<T>(op, 3));
                 f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a, r_dense1<PA>(a, g00, g01, g10, g11))
+                SV_SWITCH_A(op.a(), r_dense1<PA>(a, g00, g01, g10, g11))
                 break;
             }
             case OP_H: {
-                SV_SWITCH_A(op.a, r_h<PA>(a))
+                SV_SWITCH_A(op.a(), r_h<PA>(a))
                 break;
             }
             case OP_X: {
-                SV_SWITCH_A(op.a, r_x<PA>(a))
+                SV_SWITCH_A(op.a(), r_x<PA>(a))
                 break;
             }
             case OP_CXR: {
-                SV_SWITCH_A(op.a, SV_SWITCH_B(op.b, if constexpr (PA != PB) r_cx_reg<PA, PB>(a)))
+                SV_SWITCH_A(op.a(), SV_SWITCH_B(op.b(), if constexpr (PA != PB) r_cx_reg<PA, PB>(a)))
                 break;
             }
             case OP_CXU: {
-                const bool c = src_bit(op.sa, tid, base) != 0;
-                SV_SWITCH_A(op.a, r_cx_uni<PA>(a, c))
+                const bool c = src_bit(op.sa(), tid, base) != 0;
+                SV_SWITCH_A(op.a(), r_cx_uni<PA>(a, c))
                 break;
             }
             case OP_CXT: {
-                if ((base >> (op.sa & SRC_POS_MASK)) & 1) {
-                    SV_SWITCH_A(op.a, r_x<PA>(a))
+                if ((base >> (op.sa() & SRC_POS_MASK)) & 1) {
+                    SV_SWITCH_A(op.a(), r_x<PA>(a))
                 }
                 break;
             }
             case OP_MARK: {
-                if (base == op.data && tid == (int)(op.sa | (op.sb << 8))) {
+                if (base == op.data && tid == (int)(op.sa() | (op.sb() << 8))) {
 #pragma unroll
                     for (int j = 0; j < NR; ++j)
-                        if (j == (int)op.a) a[j] = mk<T>(-a[j].x, -a[j].y);
+                        if (j == (int)op.a()) a[j] = mk<T>(-a[j].x, -a[j].y);
                 }
                 break;
             }

@@ -16,6 +16,7 @@
 // An EXCH operation re-distributes the tile through LDS into a new layout.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 
 namespace sv {
@@ -128,6 +129,7 @@ struct DevPass {      // 96 bytes
 static_assert(sizeof(DevOp) == 80, "DevOp layout");
 static_assert(sizeof(DevLayout) == 256, "DevLayout layout");
 static_assert(sizeof(DevPass) == 96, "DevPass layout");
+static_assert(offsetof(DevPass, q) % 4 == 0, "DevPass::q is read as 32-bit words");
 
 // Ops of the one-workgroup small-state kernel: the whole state sits in LDS.
 enum SmallCode : uint8_t {
