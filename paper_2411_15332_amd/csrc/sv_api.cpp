@@ -371,7 +371,18 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
         if (!validate_gates(s->n, gates, n_gates, n_params, params != nullptr, err))
             return fail(SV_EINVAL, "%s", err.c_str());
         if (n_gates == 0) return SV_OK;
-        Plan p = build_plan(s->n, gates, n_gates, plan_options(s));
+        const PlanOptions po = plan_options(s);
+        const bool hit = s->plan_valid && s->plan_gates.size() == n_gates &&
+                         same_options(s->plan_opts, po) &&
+                         std::memcmp(s->plan_gates.data(), gates, n_gates * sizeof(sv_gate)) == 0;
+        if (!hit) {
+            s->plan_valid = false;
+            s->plan = build_plan(s->n, gates, n_gates, po);
+            s->plan_gates.assign(gates, gates + n_gates);
+            s->plan_opts = po;
+            s->plan_valid = true;
+        }
+        const Plan &p = s->plan;
         st = run_plan(s, s->buf, s->batch, p, gates, params, n_params);
         if (st != SV_OK) return st;
         s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();

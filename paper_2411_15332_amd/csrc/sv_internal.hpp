@@ -89,6 +89,15 @@ struct sv_state_s {
     double *d_grad = nullptr;
     size_t d_grad_cap = 0;
 
+    // The last sv_apply_circuit plan, reused when the next call brings the
+    // same gate records under the same plan options (starting basis state
+    // included); only its constants are materialized again (parameters may
+    // differ). Planning is host work; every pass still runs on the device.
+    std::vector<sv_gate> plan_gates;
+    sv::PlanOptions plan_opts;
+    sv::Plan plan;
+    bool plan_valid = false;
+
     int64_t stats[8] = {0};
 
     struct Timed { hipEvent_t a, b; double bytes; };

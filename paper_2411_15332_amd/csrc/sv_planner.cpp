@@ -145,22 +145,32 @@ struct Blocker {
     }
 };
 
+// Gates not yet placed, in order: `head` holds gates a pass scanned and
+// deferred, followed by order[tail..] (never scanned). A pass stops scanning
+// once every qubit is blocked, so a long circuit is not rescanned per pass.
+struct GateQueue {
+    std::vector<int> head;
+    const std::vector<int> *order = nullptr;
+    size_t tail = 0;
+    bool empty() const { return head.empty() && tail >= order->size(); }
+};
+
 // One pass: take gates in order (moving a gate past deferred ones only where
 // they commute) while the union of their tile needs fits k qubits, starting
-// from the qubits that must be in every tile (`low`). Returns the tile set;
-// `taken` and `deferred` are indices into cg.
-static uint64_t form_one_pass(const std::vector<CGate> &cg, const std::vector<int> &pending,
-                              int n, int k, const PlanOptions &opt, uint64_t low,
-                              std::vector<int> &taken, std::vector<int> &deferred) {
+// from the qubits that must be in every tile (`low`). Returns the tile set.
+// With `commit`, the taken gates go to `taken` and `pend` keeps the rest;
+// without, `pend` is left unchanged (a look-ahead).
+static uint64_t form_one_pass(const std::vector<CGate> &cg, GateQueue &pend, int n, int k,
+                              const PlanOptions &opt, uint64_t low, bool commit,
+                              std::vector<int> &taken) {
     const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
     uint64_t Q = low & all;
     Blocker blk;
     int dense = 0;
     bool closed = false;
-    for (size_t i = 0; i < pending.size(); ++i) {
-        const int gi = pending[i];
+    std::vector<int> new_head;
+    auto visit = [&](int gi) {
         const CGate &g = cg[gi];
-        if (closed) { deferred.push_back(gi); continue; }
         bool take = false;
         if (!blk.conflicts(g)) {
             const bool dense_ok = g.cls != G_DENSE1 || dense < opt.max_dense;
@@ -168,14 +178,24 @@ static uint64_t form_one_pass(const std::vector<CGate> &cg, const std::vector<in
             else if (dense_ok && popc(Q | g.qneed) <= k) { Q |= g.qneed; take = true; }
         }
         if (take) {
-            taken.push_back(gi);
+            if (commit) taken.push_back(gi);
             if (g.cls == G_DENSE1) ++dense;
             if (!opt.fuse) closed = true;
         } else {
-            deferred.push_back(gi);
+            if (commit) new_head.push_back(gi);
             blk.defer(g);
             if ((blk.nondiag & all) == all) closed = true;  // nothing can move past
         }
+    };
+    size_t hi = 0;
+    for (; hi < pend.head.size() && !closed; ++hi) visit(pend.head[hi]);
+    size_t t = pend.tail;
+    for (; t < pend.order->size() && !closed; ++t) visit((*pend.order)[t]);
+    if (commit) {
+        // unscanned head entries stay, in order, after the newly deferred ones
+        for (; hi < pend.head.size(); ++hi) new_head.push_back(pend.head[hi]);
+        pend.head.swap(new_head);
+        pend.tail = t;
     }
     return Q;
 }
@@ -889,6 +909,14 @@ struct PassCtx {
 
 }  // namespace
 
+bool same_options(const PlanOptions &a, const PlanOptions &b) {
+    return a.R == b.R && a.v == b.v && a.m == b.m && a.c == b.c && a.w_max == b.w_max &&
+           a.fuse == b.fuse && a.remap == b.remap && a.max_dense == b.max_dense &&
+           a.gen_h == b.gen_h && a.basis_known == b.basis_known &&
+           (!a.basis_known || a.basis_j == b.basis_j) && a.ud_max == b.ud_max &&
+           a.small_max == b.small_max && a.small_mode == b.small_mode;
+}
+
 Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt) {
     Plan P;
     P.n = n;
@@ -951,8 +979,10 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     P.n_gen_h = popc(gen_mask);
     P.gates_applied += P.n_gen_h;
 
-    std::vector<int> pending;
-    for (size_t i = start; i < cg.size(); ++i) pending.push_back((int)i);
+    std::vector<int> order;
+    for (size_t i = start; i < cg.size(); ++i) order.push_back((int)i);
+    GateQueue pending;
+    pending.order = &order;
     const int c = std::max(opt.v + 1, std::min(opt.c, k - 2));
 
     // Qubit remapping: logical qubit q lives at physical index bit phys[q].
@@ -985,19 +1015,19 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     bool first = true;
     int restores = 0;
     while (true) {
-        std::vector<int> taken, deferred;
+        std::vector<int> taken;
         uint64_t Q;
         bool restoring = false;
         uint64_t want = 0;
         bool home_lanes = false;
         if (!pending.empty() || (first && generate)) {
-            Q = form_one_pass(cg, pending, n, k, opt, low_set(), taken, deferred);
+            Q = form_one_pass(cg, pending, n, k, opt, low_set(), true, taken);
             if (remap) {
                 // qubits the next pass wants on the low bits: spare tile
                 // slots take them so that the store can put them there
-                if (!deferred.empty()) {
-                    std::vector<int> t2, d2;
-                    want = form_one_pass(cg, deferred, n, k, opt, 0, t2, d2);
+                if (!pending.empty()) {
+                    std::vector<int> t2;
+                    want = form_one_pass(cg, pending, n, k, opt, 0, false, t2);
                     for (int qq = 0; qq < n && popc(Q) < k; ++qq)
                         if (((want >> qq) & 1) && phys[qq] == qq) Q |= bit(qq);
                 } else {
@@ -1228,7 +1258,6 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         P.passes.push_back(dp);
         if (restoring) ++P.n_restore;
         first = false;
-        pending.swap(deferred);
     }
     return P;
 }

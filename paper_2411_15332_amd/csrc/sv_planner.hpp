@@ -87,6 +87,9 @@ struct HostOp {
     double scale = 1.0;
 };
 
+struct PlanOptions;
+bool same_options(const PlanOptions &a, const PlanOptions &b);
+
 struct PlanOptions {
     int R = 4;            // register bits per thread
     int v = 0;            // vector bits (complex64: 1, label 0 in register 0 for 16-byte I/O)

@@ -301,3 +301,32 @@ def test_relabel_passes_race_free_n27(P):
         got, st = run(P, n, gates)
         assert st["relabels"] > 0
         assert maxdiff(got, ref) <= 1e-12
+
+
+def test_plan_reuse_across_calls(P):
+    """The handle reuses its last plan for identical gate records and
+    options: repeated calls with new parameters, and a call after the state
+    stopped being a known basis state (no generated Hadamards then), all match
+    the oracle."""
+    n = 16
+    L = 2
+    gates = [synth.Gate("H", q) for q in range(n)] + synth.qnn_ansatz(n, L)
+    p1 = synth.qnn_params(n, L, 1, 1)[0]
+    p2 = synth.qnn_params(n, L, 1, 2)[0]
+    with P.StateVector(n, "c128") as sv:
+        sv.apply(gates, p1[None, :])
+        a1 = sv.numpy()[0].copy()
+        st1 = sv.plan_stats()
+        sv.set_basis(0)
+        sv.apply(gates, p2[None, :])
+        a2 = sv.numpy()[0].copy()
+        st2 = sv.plan_stats()
+        sv.apply(gates, p1[None, :])        # from a2: no longer a basis state
+        a3 = sv.numpy()[0].copy()
+        st3 = sv.plan_stats()
+    assert st1["generated_h"] == n and st2["generated_h"] == n and st3["generated_h"] == 0
+    r1 = O.simulate(n, gates, p1)
+    r2 = O.simulate(n, gates, p2)
+    r3 = O.simulate(n, gates, p1, psi0=r2)
+    for got, ref in ((a1, r1), (a2, r2), (a3, r3)):
+        assert maxdiff(got, ref) <= TOL["c128"]
