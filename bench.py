@@ -296,7 +296,7 @@ def main():
         },
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {
-            "bound": "hbm", "kernel": "k_pass<double>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "bound": "hbm", "kernel": "k_pass<double, false>", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": tr, "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms, "launches": k_launches,

@@ -57,19 +57,23 @@ typedef enum sv_dtype { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
  *   RY(t) = [[c,-s],[s,c]], RZ(t) = diag(e^{-it/2}, e^{it/2}), P(t) = diag(1,e^{it}),
  *   CNOT, CZ = diag(1,1,1,-1), SWAP, CPHASE(t) = diag(1,1,1,e^{it}),
  *   MARK = I - 2|m><m| on all n qubits (m = sv_gate.index; the Grover oracle
- *   of Sec. IV-D, and with m = 0 the zero-state reflection). */
+ *   of Sec. IV-D, and with m = 0 the zero-state reflection),
+ *   U1 / U2 = a general 2x2 / 4x4 complex matrix (any 1- or 2-qubit gate of
+ *   Table 1), read from the parameter table: params[b][param ...] holds 8 / 32
+ *   reals, row-major (re, im) pairs; U2's index is (b_q0 << 1) | b_q1. */
 typedef enum sv_gate_kind {
     SV_GATE_I = 0, SV_GATE_X = 1, SV_GATE_Y = 2, SV_GATE_Z = 3, SV_GATE_H = 4,
     SV_GATE_S = 5, SV_GATE_SDG = 6, SV_GATE_T = 7, SV_GATE_TDG = 8,
     SV_GATE_RX = 9, SV_GATE_RY = 10, SV_GATE_RZ = 11, SV_GATE_P = 12,
     SV_GATE_CNOT = 13, SV_GATE_CZ = 14, SV_GATE_SWAP = 15, SV_GATE_CPHASE = 16,
-    SV_GATE_MARK = 17,
-    SV_GATE_KIND_COUNT = 18
+    SV_GATE_MARK = 17, SV_GATE_U1 = 18, SV_GATE_U2 = 19,
+    SV_GATE_KIND_COUNT = 20
 } sv_gate_kind;
 
 /* One gate, 32 bytes. q1 = -1 for 1-qubit gates and MARK; q0 = -1 for MARK.
  * param = -1: use `angle`; param >= 0: the angle is params[b][param] for batch
- * entry b (see sv_apply_circuit). index: basis index of MARK, else ignored. */
+ * entry b (see sv_apply_circuit); U1 / U2 require param >= 0 (the first of
+ * their 8 / 32 matrix reals). index: basis index of MARK, else ignored. */
 typedef struct sv_gate {
     int32_t kind;
     int32_t q0;

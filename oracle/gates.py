@@ -41,7 +41,8 @@ _FIXED_2Q = {
 
 
 def matrix(name: str, angle: float = 0.0) -> np.ndarray:
-    """The gate's 2x2 or 4x4 complex128 matrix (MARK has none: it is n-qubit)."""
+    """The gate's 2x2 or 4x4 complex128 matrix (MARK has none: it is n-qubit;
+    U1 / U2 take theirs from the parameters, see params_matrix)."""
     if name in _FIXED_1Q:
         return np.array(_FIXED_1Q[name], dtype=np.complex128)
     if name in _FIXED_2Q:
@@ -65,7 +66,17 @@ def arity(name: str) -> int:
     """1 or 2 for matrix gates, 0 for the n-qubit MARK."""
     if name == "MARK":
         return 0
-    return 2 if name in _FIXED_2Q or name == "CPHASE" else 1
+    return 2 if name in _FIXED_2Q or name in ("CPHASE", "U2") else 1
+
+
+def params_matrix(name: str, params, offset: int) -> np.ndarray:
+    """The matrix of a U1 (2x2) or U2 (4x4) gate: row-major (re, im) pairs
+    of reals read from the parameter vector starting at `offset`."""
+    size = 2 if name == "U1" else 4
+    v = np.asarray(params, dtype=np.float64)[offset: offset + 2 * size * size]
+    if v.size != 2 * size * size:
+        raise ValueError(f"{name} needs {2 * size * size} reals from parameter {offset}")
+    return (v[0::2] + 1j * v[1::2]).reshape(size, size)
 
 
 def generator(name: str) -> np.ndarray:

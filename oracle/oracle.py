@@ -107,7 +107,12 @@ def encode(gates: Sequence, params: Optional[np.ndarray] = None):
             kind[k] = 3
             idx[k] = g.index
             continue
-        m = G.matrix(g.name, _angle(g, params))
+        if g.name in ("U1", "U2"):
+            if params is None or g.param < 0:
+                raise ValueError(f"{g.name} reads its matrix from the parameters")
+            m = G.params_matrix(g.name, params, g.param)
+        else:
+            m = G.matrix(g.name, _angle(g, params))
         kind[k] = a
         q0[k] = g.q0
         q1[k] = g.q1
@@ -229,7 +234,8 @@ def monomial_amplitudes(n: int, gates: Sequence, indices: Sequence[int], initial
         if g.name == "MARK":
             amp = np.where(idx == np.int64(g.index), -amp, amp)
             continue
-        mat = G.matrix(g.name, _angle(g, params))
+        mat = (G.params_matrix(g.name, params, g.param) if g.name in ("U1", "U2")
+               else G.matrix(g.name, _angle(g, params)))
         cols, vals = _row_nonzero(mat)
         if G.arity(g.name) == 1:
             r = (idx >> g.q0) & 1

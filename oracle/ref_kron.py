@@ -82,8 +82,11 @@ def mtp_operator(n: int, gate, params: Optional[np.ndarray] = None) -> np.ndarra
         d = np.ones(1 << n, dtype=np.complex128)
         d[gate.index] = -1.0
         return np.diag(d)
-    ang = float(params[gate.param]) if gate.param >= 0 else gate.angle
-    g = G.matrix(gate.name, ang)
+    if gate.name in ("U1", "U2"):
+        g = G.params_matrix(gate.name, params, gate.param)
+    else:
+        ang = float(params[gate.param]) if gate.param >= 0 else gate.angle
+        g = G.matrix(gate.name, ang)
     if G.arity(gate.name) == 1:
         return embed_1q(n, gate.q0, g)
     return embed_2q_kron(n, gate.q0, gate.q1, g)

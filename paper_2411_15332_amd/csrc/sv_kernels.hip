@@ -180,6 +180,15 @@ __device__ __forceinline__ void r_d1_reg(cpx<T> (&a)[NR], cpx<T> d0, cpx<T> d1) 
     for (int j = 0; j < NR; ++j) cmul_ip(a[j], (j & (1 << P)) ? d1 : d0);
 }
 
+// Exchange register bits PA and PB: slots with bit PA set and PB clear swap
+// with the slot that has them the other way round.
+template <int PA, int PB, typename T, int NR>
+__device__ __forceinline__ void r_rperm(cpx<T> (&a)[NR]) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (((j >> PA) & 1) && !((j >> PB) & 1)) cswap(a[j], a[j ^ (1 << PA) ^ (1 << PB)]);
+}
+
 // amp *= d for the slots whose register bit P equals V
 template <int P, int V, typename T, int NR>
 __device__ __forceinline__ void r_d1_half(cpx<T> (&a)[NR], cpx<T> d) {
@@ -362,7 +371,9 @@ __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
     return (src & ~SRC_POS_MASK) == SRC_THR ? (tid >> pos) & 1 : (int)((base >> pos) & 1);
 }
 
-template <typename T>
+// D2: the variant that also executes OP_DENSE2 (its 4x4 needs many more
+// registers; passes without it run the lean variant).
+template <typename T, bool D2>
 __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
                                               const DevPass *__restrict__ passes, int pass_idx,
                                               const DevLayout *__restrict__ layouts,
@@ -434,7 +445,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         const OpRec *recs = reinterpret_cast<const OpRec *>(opb);
         OpRec op = recs[oi];
         for (;;) {
-            const OpRec nxt = recs[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
+            OpRec nxt = recs[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
             switch (op.code()) {
             case OP_EXCH: {
                 const uint32_t lo = (1u << op.sb()) - 1u;
@@ -488,6 +499,39 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 } else {
                     SV_SWITCH_A(op.a(), r_d1_half<PA, 0>(a, e))
                 }
+                break;
+            }
+            case OP_RPERM: {   // emitted only in passes with OP_DENSE2
+                if constexpr (D2) {
+                    SV_SWITCH_A(op.a(), SV_SWITCH_B(op.b(), if constexpr (PA != PB) r_rperm<PA, PB>(a)))
+                }
+                break;
+            }
+            case OP_DENSE2: {
+                if constexpr (!D2) break;
+                // 4x4 on register bits 1 and 0; its 16 entries continue in the
+                // payloads of the OP_CONT records that follow
+                constexpr int PER = sizeof(T) == 8 ? 4 : 8;
+                constexpr int NC = 16 / PER - 1;
+                cpx<T> m[16];
+#pragma unroll
+                for (int e = 0; e < PER; ++e) m[e] = plc<T>(op, e);
+#pragma unroll
+                for (int t = 0; t < NC; ++t) {
+                    const OpRec &c = recs[oi + 1 + t];
+#pragma unroll
+                    for (int e = 0; e < PER; ++e) m[PER * (t + 1) + e] = plc<T>(c, e);
+                }
+#pragma unroll
+                for (int j0 = 0; j0 < NR; j0 += 4) {
+                    const cpx<T> x0 = a[j0], x1 = a[j0 + 1], x2 = a[j0 + 2], x3 = a[j0 + 3];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        a[j0 + r] = cadd(cmul2(m[4 * r], x0, m[4 * r + 1], x1),
+                                         cmul2(m[4 * r + 2], x2, m[4 * r + 3], x3));
+                }
+                oi += NC;   // skip the continuation records
+                nxt = recs[oi + 1 < oe ? oi + 1 : oi];
                 break;
             }
             case OP_D1R: {
@@ -827,6 +871,23 @@ __device__ __forceinline__ void small_apply(cpx<T> *s, uint32_t N, const SmallOp
         }
         break;
     }
+    case SOP_DENSE2: {
+        const int lo = q0 < q1 ? q0 : q1, hi = q0 < q1 ? q1 : q0;
+        for (uint32_t p = tid; p < N / 4; p += nt) {
+            const uint32_t b = ins0(ins0(p, lo), hi);
+            const uint32_t ii[4] = {b, b | (1u << q1), b | (1u << q0), b | (1u << q0) | (1u << q1)};
+            cpx<T> x[4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) x[l] = s[ii[l]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const T *row = c + 8 * r;
+                s[ii[r]] = cadd(cmul2(ldc(row), x[0], ldc(row + 2), x[1]),
+                                cmul2(ldc(row + 4), x[2], ldc(row + 6), x[3]));
+            }
+        }
+        break;
+    }
     case SOP_X:
         for (uint32_t p = tid; p < N / 2; p += nt) {
             const uint32_t i0 = ins0(p, q0), i1 = i0 | (1u << q0);
@@ -995,12 +1056,22 @@ hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const De
         return hipErrorInvalidValue;
     const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
     const dim3 block(1u << h_pass.w);
-    if (dt == 2)
-        hipLaunchKernelGGL(k_pass<double>, grid, block, 0, st, (cpx<double> *)state, n_amps,
-                           d_passes, pass_idx, d_layouts, d_ops, ops_stride);
-    else
-        hipLaunchKernelGGL(k_pass<float>, grid, block, 0, st, (cpx<float> *)state, n_amps,
-                           d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+    const bool d2 = (h_pass.flags & PASS_DENSE2) != 0;
+    if (dt == 2) {
+        if (d2)
+            hipLaunchKernelGGL((k_pass<double, true>), grid, block, 0, st, (cpx<double> *)state,
+                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+        else
+            hipLaunchKernelGGL((k_pass<double, false>), grid, block, 0, st, (cpx<double> *)state,
+                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+    } else {
+        if (d2)
+            hipLaunchKernelGGL((k_pass<float, true>), grid, block, 0, st, (cpx<float> *)state,
+                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+        else
+            hipLaunchKernelGGL((k_pass<float, false>), grid, block, 0, st, (cpx<float> *)state,
+                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+    }
     return hipGetLastError();
 }
 

@@ -58,6 +58,11 @@ enum OpCode : uint8_t {
     OP_D2Q = 17,     // amp *= d for the slots whose register bits a, b equal bits 0, 1 of sa
     OP_D1HU = 18,    // amp *= d for the slots whose register bit a equals bit 0 of b, when
                      // the bit of source sa equals bit 1 of b (f untouched)
+    OP_RPERM = 19,   // exchange register bits a and b (slots j with bit a = 1, bit b = 0
+                     // swap with j ^ 2^a ^ 2^b)
+    OP_DENSE2 = 20,  // 4x4 on register bits 1 (high) and 0 (low): entries row-major, the
+                     // first ones in this payload, the rest in the OP_CONT records after it
+    OP_CONT = 21,    // continuation of the preceding operation's payload (not executed)
 };
 
 constexpr uint8_t kNoSource = 0xFF;
@@ -108,6 +113,7 @@ enum : uint32_t {
     PASS_GENERATE = 1u,     // no load: amplitudes of H^M |j> generated in place
     PASS_SYNC_STORE = 2u,   // barrier before the store: the store layout moves amplitudes
                             // between waves and no exchange has separated loads from stores
+    PASS_DENSE2 = 4u,       // the pass holds OP_DENSE2 (run by the kernel variant with it)
 };
 
 struct DevPass {      // 96 bytes

@@ -35,7 +35,11 @@ static bool is_angled(int kind) {
 }
 static bool is_2q(int kind) {
     return kind == SV_GATE_CNOT || kind == SV_GATE_CZ || kind == SV_GATE_SWAP ||
-           kind == SV_GATE_CPHASE;
+           kind == SV_GATE_CPHASE || kind == SV_GATE_U2;
+}
+// Reals a matrix gate reads from the parameter table (0: not a matrix gate).
+static size_t matrix_reals(int kind) {
+    return kind == SV_GATE_U1 ? 8 : kind == SV_GATE_U2 ? 32 : 0;
 }
 
 bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params,
@@ -68,7 +72,15 @@ bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params
             err = buf;
             return false;
         }
-        if (g.param >= 0) {
+        if (matrix_reals(g.kind)) {
+            if (g.param < 0 || !params_given || (size_t)g.param + matrix_reals(g.kind) > n_params) {
+                snprintf(buf, sizeof buf,
+                         "gate %zu: U%d needs %zu matrix reals from parameter %d (n_params = %zu)",
+                         i, g.kind == SV_GATE_U1 ? 1 : 2, matrix_reals(g.kind), g.param, n_params);
+                err = buf;
+                return false;
+            }
+        } else if (g.param >= 0) {
             if (!is_angled(g.kind)) {
                 snprintf(buf, sizeof buf, "gate %zu: kind %d takes no parameter", i, g.kind);
                 err = buf;
@@ -106,7 +118,8 @@ CGate classify(const sv_gate &g, int n, int src) {
     case SV_GATE_RZ: case SV_GATE_P:
         c.cls = G_D1; break;
     case SV_GATE_H: c.cls = G_H; break;
-    case SV_GATE_RX: case SV_GATE_RY: c.cls = G_DENSE1; break;
+    case SV_GATE_RX: case SV_GATE_RY: case SV_GATE_U1: c.cls = G_DENSE1; break;
+    case SV_GATE_U2: c.cls = G_DENSE2; break;
     case SV_GATE_CNOT: c.cls = G_CX; break;
     case SV_GATE_CZ: case SV_GATE_CPHASE: c.cls = G_D2; break;
     case SV_GATE_SWAP: c.cls = G_SWAP; break;
@@ -121,6 +134,7 @@ CGate classify(const sv_gate &g, int n, int src) {
     case G_H: case G_DENSE1: c.support = c.qneed = c.rneed = bit(c.q0); break;
     case G_CX: c.support = bit(c.q0) | bit(c.q1); c.qneed = c.rneed = bit(c.q1); break;
     case G_SWAP: c.support = c.qneed = bit(c.q0) | bit(c.q1); break;
+    case G_DENSE2: c.support = c.qneed = c.rneed = bit(c.q0) | bit(c.q1); break;
     default: break;
     }
     return c;
@@ -755,6 +769,19 @@ struct PassCtx {
         return (uint8_t)(((x ^ inv0) << 1) | (y ^ inv1));
     }
 
+    // Exchange register bits p and r (labels, pending products and the data).
+    void rperm(int p, int r) {
+        if (p == r) return;
+        HostOp &o = emit(OP_RPERM);
+        o.hdr.a = (uint8_t)p;
+        o.hdr.b = (uint8_t)r;
+        std::swap(reg_label[p], reg_label[r]);
+        pos_reg[reg_label[p]] = p;
+        pos_reg[reg_label[r]] = r;
+        std::swap(pend[p], pend[r]);
+        cur_layout = -1;
+    }
+
     void apply(const CGate &g) {
         ++P.gates_applied;
         switch (g.cls) {
@@ -887,6 +914,34 @@ struct PassCtx {
             if (c.inv) compose(t.p, Factor{FK_X, false, -1}, PC_A, true);
             break;
         }
+        case G_DENSE2: {
+            // a 4x4 on register bits 1 (q0) and 0 (q1)
+            const int l0 = label_of[g.q0], l1 = label_of[g.q1];
+            rperm(pos_reg[l0], 1);
+            rperm(pos_reg[l1], 0);
+            flush(0);
+            flush(1);
+            emit_ud();
+            if (f_used) {
+                emit(OP_APPLYF);
+                f_used = false;
+            }
+            const int invm = (int)(((xmask >> l0) & 1) << 1 | ((xmask >> l1) & 1));
+            const int per = opt.v ? 8 : 4;   // matrix entries per record payload
+            HostOp &o = emit(OP_DENSE2);
+            o.pk = PK_MAT4;
+            o.gate = g.src;
+            for (int e = 0; e < 4; ++e) o.perm[e] = (uint8_t)(e ^ invm);
+            const uint8_t prm[4] = {o.perm[0], o.perm[1], o.perm[2], o.perm[3]};
+            for (int e0 = per; e0 < 16; e0 += per) {
+                HostOp &c = emit(OP_CONT);
+                c.pk = PK_CONT;
+                c.gate = g.src;
+                c.hdr.a = (uint8_t)e0;
+                std::memcpy(c.perm, prm, 4);
+            }
+            break;
+        }
         case G_SWAP: {
             const int l0 = label_of[g.q0], l1 = label_of[g.q1];
             const int r0 = pos_reg[l0], r1 = pos_reg[l1], t0 = pos_thr[l0], t1 = pos_thr[l1];
@@ -958,6 +1013,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             case G_SWAP: so.code = SOP_SWAP; break;
             case G_H: so.code = SOP_DENSE1; so.data = cblock(CK_HMAT, 8); break;
             case G_DENSE1: so.code = SOP_DENSE1; so.data = cblock(CK_DENSE1, 8); break;
+            case G_DENSE2: so.code = SOP_DENSE2; so.data = cblock(CK_DENSE2, 32); break;
             default: continue;
             }
             P.sops.push_back(so);
@@ -1232,8 +1288,10 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         // In-place safety: without an exchange, nothing orders one wave's loads
         // before another wave's stores to the same tile.
         bool exch_in_pass = false;
-        for (size_t oi = (size_t)dp.op_begin; oi < P.ops.size(); ++oi)
+        for (size_t oi = (size_t)dp.op_begin; oi < P.ops.size(); ++oi) {
             if (P.ops[oi].hdr.code == OP_EXCH) exch_in_pass = true;
+            if (P.ops[oi].hdr.code == OP_DENSE2) dp.flags |= PASS_DENSE2;
+        }
         if (!exch_in_pass && dp.store_layout != 0) dp.flags |= PASS_SYNC_STORE;
 
         if (first && generate) {
@@ -1314,7 +1372,12 @@ static void factor_mat(const Factor &f, const sv_gate *gates, const double *para
     switch (f.kind) {
     case FK_GATE: {
         const sv_gate &g = gates[f.gate];
-        gate_mat2(g.kind, gate_angle(g, params, n_params, b), m);
+        if (g.kind == SV_GATE_U1) {
+            const double *v = params + (size_t)b * n_params + (size_t)g.param;
+            for (int e = 0; e < 4; ++e) m[e] = cd(v[2 * e], v[2 * e + 1]);
+        } else {
+            gate_mat2(g.kind, gate_angle(g, params, n_params, b), m);
+        }
         break;
     }
     case FK_X: m[0] = 0.0; m[1] = 1.0; m[2] = 1.0; m[3] = 0.0; break;
@@ -1344,7 +1407,7 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
             const HostOp &h = p.ops[i];
             DevOp rec = h.hdr;
             std::memset(rec.payload, 0, sizeof rec.payload);
-            double v[2 + 2 * kMaxUdTerms] = {0};
+            double v[16] = {0};   // up to 64 payload bytes of FP32 values
             int count = 0;
             switch (h.pk) {
             case PK_MAT2:
@@ -1379,6 +1442,23 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
                 break;
             }
             case PK_SCALE: v[0] = h.scale; count = 1; break;
+            case PK_MAT4:
+            case PK_CONT: {
+                // entries e0 .. e0 + per - 1 of the row-major 4x4, physical
+                // (row, col) -> gate-local (perm[row], perm[col])
+                const sv_gate &g = gates[h.gate];
+                const double *mv = params + (size_t)b * n_params + (size_t)g.param;
+                const int per = f32 ? 8 : 4;
+                const int e0 = h.pk == PK_CONT ? h.hdr.a : 0;
+                for (int t = 0; t < per; ++t) {
+                    const int e = e0 + t, r = e >> 2, c = e & 3;
+                    const int src = 4 * h.perm[r] + h.perm[c];
+                    v[2 * t] = mv[2 * src];
+                    v[2 * t + 1] = mv[2 * src + 1];
+                }
+                count = 2 * per;
+                break;
+            }
             case PK_SIDE: {
                 cd M[4] = {1.0, 0.0, 0.0, 1.0};
                 for (const Factor &f : h.factors) {
@@ -1451,6 +1531,9 @@ void materialize_consts(const Plan &p, const sv_gate *gates, const double *param
                 cd e[4];
                 gate_diag4(g.kind, t, e);
                 for (int i = 0; i < 4; ++i) { d[2 * i] = e[i].real(); d[2 * i + 1] = e[i].imag(); }
+            } else if (cb.kind == CK_DENSE2 || (cb.kind == CK_DENSE1 && g.kind == SV_GATE_U1)) {
+                const double *mv = params + (size_t)b * n_params + (size_t)g.param;
+                std::memcpy(d, mv, (cb.kind == CK_DENSE2 ? 32 : 8) * sizeof(double));
             } else {
                 cd m[4];
                 gate_mat2(cb.kind == CK_HMAT ? (int)SV_GATE_H : g.kind, t, m);

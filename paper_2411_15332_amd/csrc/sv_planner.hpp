@@ -18,8 +18,9 @@ namespace sv {
 //                (the DAX entry restricted to the gate's own 2^k x 2^k matrix)
 //   H       a Hadamard: one magnitude and on-demand signs (RH)
 //   DENSE1  general 2x2
+//   DENSE2  general 4x4 (matrix gate U2)
 enum GClass : uint8_t {
-    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1
+    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1, G_DENSE2
 };
 
 struct CGate {
@@ -34,7 +35,7 @@ struct CGate {
 };
 
 // Small-path constant block: `count` reals per batch entry at offset `off`.
-enum ConstKind : uint8_t { CK_D1 = 1, CK_D2, CK_DENSE1, CK_HMAT };
+enum ConstKind : uint8_t { CK_D1 = 1, CK_D2, CK_DENSE1, CK_HMAT, CK_DENSE2 };
 struct ConstBlock {
     ConstKind kind;
     int gate;
@@ -59,6 +60,9 @@ enum PayloadKind : uint8_t {
     PK_SIDE,    // one diagonal entry of the product of `factors` (hdr.b: 0 or 1)
     PK_G3,      // entry 3 of the 2-qubit diagonal gate (its one non-trivial entry)
     PK_UDN,     // C and the term ratios of the merged uniform diagonals `ucon`
+    PK_MAT4,    // a U2 gate's 4x4 matrix, rows and columns permuted by perm (16 entries,
+                // continued in the records that follow the operation)
+    PK_CONT,    // continuation record of the preceding PK_MAT4 (entries from `gate` e0)
 };
 
 // One diagonal gate on thread or tile-base bits inside a merged OP_UDN.

@@ -22,7 +22,7 @@ SV_C64, SV_C128 = 1, 2
 GATE_KIND = {
     "I": 0, "X": 1, "Y": 2, "Z": 3, "H": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "RX": 9, "RY": 10, "RZ": 11, "P": 12, "CNOT": 13, "CZ": 14, "SWAP": 15,
-    "CPHASE": 16, "MARK": 17,
+    "CPHASE": 16, "MARK": 17, "U1": 18, "U2": 19,
 }
 
 OPT_FUSE, OPT_MIN_LOW_QUBITS, OPT_MAX_DENSE, OPT_ON_DEMAND_H, OPT_SMALL_PATH, OPT_PROFILE, OPT_REMAP = \

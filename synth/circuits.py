@@ -34,8 +34,11 @@ class Gate(NamedTuple):
     index: int = 0
 
 
-ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P")
-TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE")
+ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P", "U1")
+TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE", "U2")
+# U1 / U2: a general 2x2 / 4x4 matrix taken from the parameter vector at
+# `param` (8 / 32 reals: row-major (re, im) pairs), see matrix_params().
+MATRIX_GATES = ("U1", "U2")
 N_QUBIT = ("MARK",)
 GATE_NAMES = ONE_QUBIT + TWO_QUBIT + N_QUBIT
 ANGLED = ("RX", "RY", "RZ", "P", "CPHASE")
@@ -102,6 +105,25 @@ def capacity_circuit(n: int, layers: int, seed: int, p_dense: float = 0.1) -> Li
         if n >= 2:
             gates.extend(_layer_pairs(rng, n, CAPACITY_2Q_POOL, 0.5))
     return gates
+
+
+def matrix_params(m: np.ndarray) -> np.ndarray:
+    """A 2x2 or 4x4 complex matrix as the reals a U1 / U2 gate reads from the
+    parameter vector: row-major (re, im) pairs."""
+    m = np.asarray(m, dtype=np.complex128)
+    out = np.empty(2 * m.size)
+    out[0::2] = m.real.ravel()
+    out[1::2] = m.imag.ravel()
+    return out
+
+
+def random_unitary(dim: int, rng: np.random.Generator) -> np.ndarray:
+    """A random dim x dim unitary (QR of a complex Gaussian matrix with the
+    phases of R's diagonal divided out)."""
+    z = rng.normal(size=(dim, dim)) + 1j * rng.normal(size=(dim, dim))
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))
 
 
 def grover_iterations(n: int) -> int:
@@ -195,25 +217,35 @@ def random_state(n: int, seed: int) -> np.ndarray:
     return v / np.linalg.norm(v)
 
 
-def random_1q_unitary_free_circuit(n: int, count: int, seed: int,
-                                   names: Sequence[str] = GATE_NAMES) -> List[Gate]:
-    """``count`` gates drawn uniformly from ``names`` on random qubits (distinct
-    pairs for 2-qubit kinds, random index for MARK). Used by exhaustive tests."""
+def all_kinds_circuit(n: int, seed: int):
+    """Every gate kind on every qubit (2-qubit kinds with a random partner,
+    MARK with a random index), shuffled. U1 / U2 take random unitaries from the
+    returned parameter vector. Returns (gates, params)."""
     rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(count):
-        name = names[int(rng.integers(len(names)))]
-        ang = float(rng.uniform(0.0, 2.0 * math.pi)) if name in ANGLED else 0.0
-        if name in TWO_QUBIT:
-            if n < 2:
-                continue
-            a, b = rng.choice(n, size=2, replace=False)
-            out.append(Gate(name, int(a), int(b), ang))
-        elif name == "MARK":
-            out.append(Gate(name, -1, -1, 0.0, -1, int(rng.integers(0, 1 << n))))
-        else:
-            out.append(Gate(name, int(rng.integers(n)), -1, ang))
-    return out
+    gates: List[Gate] = []
+    params: List[float] = []
+    for name in GATE_NAMES:
+        for q in range(n):
+            ang = float(rng.uniform(0.0, 2.0 * math.pi))
+            if name in MATRIX_GATES:
+                off = len(params)
+                params.extend(matrix_params(random_unitary(2 if name == "U1" else 4, rng)).tolist())
+                if name == "U2":
+                    if n < 2:
+                        continue
+                    gates.append(Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), 0.0, off))
+                else:
+                    gates.append(Gate(name, q, -1, 0.0, off))
+            elif name in TWO_QUBIT:
+                if n < 2:
+                    continue
+                gates.append(Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
+            elif name == "MARK":
+                gates.append(Gate(name, -1, -1, 0.0, -1, int(rng.integers(0, 1 << n))))
+            else:
+                gates.append(Gate(name, q, -1, ang))
+    order = rng.permutation(len(gates))
+    return [gates[i] for i in order], np.array(params, dtype=np.float64)
 
 
 def amplitude_gate_updates(n: int, gates: Sequence[Gate]) -> int:

@@ -11,7 +11,8 @@ from __future__ import annotations
 import numpy as np
 
 (OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
- OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU) = range(1, 19)
+ OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU, OP_RPERM, OP_DENSE2,
+ OP_CONT) = range(1, 22)
 NO_SOURCE = 0xFF
 SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE = range(1, 11)
 SRC_REG, SRC_THR, SRC_TILE = 0, 1, 2
@@ -57,6 +58,13 @@ def run_small(plan, psi, n):
             a = idx[(((idx >> q0) & 1) == 1) & (((idx >> q1) & 1) == 0)]
             b = (a & ~(1 << q0)) | (1 << q1)
             psi[a], psi[b] = psi[b].copy(), psi[a].copy()
+        elif code == SOP_DENSE2:
+            m = _c(c, data, 16).reshape(4, 4)
+            base = idx[(((idx >> q0) & 1) == 0) & (((idx >> q1) & 1) == 0)]
+            ii = [base, base | (1 << q1), base | (1 << q0), base | (1 << q0) | (1 << q1)]
+            x = [psi[i].copy() for i in ii]
+            for r in range(4):
+                psi[ii[r]] = sum(m[r, cc] * x[cc] for cc in range(4))
         else:
             raise NotImplementedError(code)
     return psi
@@ -120,7 +128,9 @@ def run_plan(plan, psi, n):
             lo = [j for j in range(NR) if not (j >> p) & 1]
             return lo, [j | (1 << p) for j in lo]
 
-        for op in plan["ops"][int(P["op_begin"]): int(P["op_end"])]:
+        ops = plan["ops"]
+        for oi in range(int(P["op_begin"]), int(P["op_end"])):
+            op = ops[oi]
             code, oa, ob, sa, sb, data = (int(op["code"]), int(op["a"]), int(op["b"]),
                                           int(op["sa"]), int(op["sb"]), int(op["data"]))
             pl = op["payload"].view(np.float32).astype(np.float64) if plan.get("f32") else op["payload"]
@@ -174,6 +184,24 @@ def run_plan(plan, psi, n):
                     on = src_bit(s1) & (1 if s2 == NO_SOURCE else src_bit(s2))
                     g = np.where(on == 1, g * d[i + 1], g)
                 f = f * g
+            elif code == OP_CONT:
+                continue   # payload of the preceding OP_DENSE2
+            elif code == OP_RPERM:
+                sel = [j for j in range(NR) if (j >> oa) & 1 and not (j >> ob) & 1]
+                oth = [j ^ (1 << oa) ^ (1 << ob) for j in sel]
+                a[:, :, sel], a[:, :, oth] = a[:, :, oth].copy(), a[:, :, sel].copy()
+            elif code == OP_DENSE2:
+                per = 8 if plan.get("f32") else 4
+                ent = []
+                for t in range(16 // per):
+                    rec = ops[oi + t]
+                    v = rec["payload"].view(np.float32).astype(np.float64) if plan.get("f32") else rec["payload"]
+                    ent += list(v[0::2][:per] + 1j * v[1::2][:per])
+                m = np.array(ent).reshape(4, 4)
+                for j0 in range(0, NR, 4):
+                    x = [a[:, :, j0 + e].copy() for e in range(4)]
+                    for r in range(4):
+                        a[:, :, j0 + r] = sum(m[r, cc] * x[cc] for cc in range(4))
             elif code == OP_D1H:
                 sel = ((j_idx >> oa) & 1) == ob
                 a = np.where(sel, a * d[0], a)

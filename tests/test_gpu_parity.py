@@ -44,29 +44,13 @@ def maxdiff(a, b):
     return float(np.max(np.abs(a - b)))
 
 
-def all_kinds_circuit(n, seed):
-    rng = np.random.default_rng(seed)
-    gates = []
-    for name in synth.GATE_NAMES:
-        for q in range(n):
-            ang = float(rng.uniform(0, 2 * math.pi))
-            if name in synth.TWO_QUBIT:
-                gates.append(synth.Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
-            elif name == "MARK":
-                gates.append(synth.Gate(name, -1, -1, 0.0, -1, int(rng.integers(1 << n))))
-            else:
-                gates.append(synth.Gate(name, q, -1, ang))
-    rng.shuffle(gates)
-    return gates
-
-
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [3, 10, 12, 14, 17])
 def test_every_kind_every_position(P, n, dtype):
-    gates = all_kinds_circuit(n, n)
+    gates, params = synth.all_kinds_circuit(n, n)
     psi0 = synth.random_state(n, 100 + n)
-    ref = O.simulate(n, gates, psi0=psi0)
-    got, _ = run(P, n, gates, dtype, psi0=psi0)
+    ref = O.simulate(n, gates, params, psi0=psi0)
+    got, _ = run(P, n, gates, dtype, psi0=psi0, params=params[None, :])
     assert maxdiff(got, ref) <= TOL[dtype]
 
 
@@ -330,3 +314,27 @@ def test_plan_reuse_across_calls(P):
     r3 = O.simulate(n, gates, p1, psi0=r2)
     for got, ref in ((a1, r1), (a2, r2), (a3, r3)):
         assert maxdiff(got, ref) <= TOL["c128"]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_matrix_gates_at_scale(P, dtype):
+    """Random circuits with general 1- and 2-qubit matrix gates (U1, U2) mixed
+    into the plain gate set at n = 20 (many tiles and passes)."""
+    n = 20
+    rng = np.random.default_rng(77)
+    gates = synth.random_circuit(n, 6, 77)
+    params = []
+    mixed = []
+    for g in gates:
+        mixed.append(g)
+        if rng.random() < 0.15:
+            q0, q1 = (int(x) for x in rng.choice(n, 2, replace=False))
+            mixed.append(synth.Gate("U2", q0, q1, 0.0, len(params)))
+            params += synth.matrix_params(synth.random_unitary(4, rng)).tolist()
+        if rng.random() < 0.1:
+            mixed.append(synth.Gate("U1", int(rng.integers(n)), -1, 0.0, len(params)))
+            params += synth.matrix_params(synth.random_unitary(2, rng)).tolist()
+    params = np.array(params)
+    ref = O.simulate(n, mixed, params)
+    got, st = run(P, n, mixed, dtype, params=params[None, :])
+    assert maxdiff(got, ref) <= TOL[dtype]

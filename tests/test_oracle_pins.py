@@ -35,7 +35,8 @@ def _golden_lines(name):
 ANGLES = [0.0, 0.3, 1.7, math.pi, 4.9, -2.2]
 
 
-@pytest.mark.parametrize("name", [n for n in synth.GATE_NAMES if n != "MARK"])
+@pytest.mark.parametrize("name", [n for n in synth.GATE_NAMES
+                                  if n != "MARK" and n not in synth.MATRIX_GATES])
 def test_gate_unitary(name):
     for a in ANGLES:
         m = G.matrix(name, a)
@@ -112,6 +113,8 @@ def test_1q_embedding_is_paper_kron_order():
 def _all_single_gates(n, rng):
     out = []
     for name in synth.GATE_NAMES:
+        if name in synth.MATRIX_GATES:
+            continue   # pinned separately (test_matrix_gates_*)
         ar = G.arity(name)
         ang = float(rng.uniform(0, 2 * math.pi))
         if ar == 1:
@@ -394,3 +397,59 @@ def test_monomial_amplitudes_closed_forms():
     assert np.allclose(z, 2 ** -1.5 * np.array([1, -1] * 4))
     with pytest.raises(ValueError):
         O.monomial_amplitudes(3, [synth.Gate("H", 0)], [0])
+
+
+# ------------------------------------------------ matrix gates (U1, U2)
+
+def test_matrix_gates_reproduce_named_gates():
+    """A U1 / U2 carrying a named gate's matrix acts as that gate."""
+    n = 5
+    rng = np.random.default_rng(7)
+    psi0 = synth.random_state(n, 3)
+    cases = [("RX", 1.3), ("H", 0.0), ("T", 0.0), ("RZ", 2.2)]
+    for name, ang in cases:
+        params = synth.matrix_params(G.matrix(name, ang))
+        for q in range(n):
+            a = O.simulate(n, [synth.Gate(name, q, -1, ang)], psi0=psi0)
+            b = O.simulate(n, [synth.Gate("U1", q, -1, 0.0, 0)], params, psi0=psi0)
+            assert np.max(np.abs(a - b)) < 1e-15
+    for name, ang in [("CNOT", 0.0), ("SWAP", 0.0), ("CPHASE", 0.7)]:
+        params = synth.matrix_params(G.matrix(name, ang))
+        for q0, q1 in [(0, 3), (4, 1), (2, 3)]:
+            a = O.simulate(n, [synth.Gate(name, q0, q1, ang)], psi0=psi0)
+            b = O.simulate(n, [synth.Gate("U2", q0, q1, 0.0, 0)], params, psi0=psi0)
+            assert np.max(np.abs(a - b)) < 1e-15
+    # U2 = A (x) B acts as A on its first operand and B on its second
+    A, B = synth.random_unitary(2, rng), synth.random_unitary(2, rng)
+    p = np.concatenate([synth.matrix_params(np.kron(A, B)), synth.matrix_params(A),
+                        synth.matrix_params(B)])
+    a = O.simulate(n, [synth.Gate("U2", 3, 1, 0.0, 0)], p, psi0=psi0)
+    b = O.simulate(n, [synth.Gate("U1", 3, -1, 0.0, 32), synth.Gate("U1", 1, -1, 0.0, 40)], p,
+                   psi0=psi0)
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_matrix_gates_vs_kronecker(n):
+    """Random U1 on every qubit and random U2 on every ordered pair against the
+    Kronecker-product operators (element-wise 2-qubit embedding)."""
+    rng = np.random.default_rng(n)
+    gates, params = [], []
+    for q in range(n):
+        gates.append(synth.Gate("U1", q, -1, 0.0, len(params)))
+        params += synth.matrix_params(synth.random_unitary(2, rng)).tolist()
+    for a in range(n):
+        for b in range(n):
+            if a != b:
+                gates.append(synth.Gate("U2", a, b, 0.0, len(params)))
+                params += synth.matrix_params(synth.random_unitary(4, rng)).tolist()
+    params = np.array(params)
+    psi0 = synth.random_state(n, 5)
+    U = np.eye(1 << n, dtype=complex)
+    for g in gates:
+        m = G.params_matrix(g.name, params, g.param)
+        E = K.embed_1q(n, g.q0, m) if g.name == "U1" else K.embed_2q_def(n, g.q0, g.q1, m)
+        U = E @ U
+    want = U @ psi0
+    got = O.simulate(n, gates, params, psi0=psi0)
+    assert np.max(np.abs(got - want)) < 1e-13

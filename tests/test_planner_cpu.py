@@ -95,22 +95,11 @@ def test_plan_options(opts):
 
 @pytest.mark.parametrize("n", [11, 14, 15])
 def test_every_gate_kind_every_position(n):
-    rng = np.random.default_rng(0)
-    gates = []
-    for name in synth.GATE_NAMES:
-        for q in range(n):
-            ang = float(rng.uniform(0, 2 * math.pi))
-            if name in synth.TWO_QUBIT:
-                gates.append(synth.Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
-            elif name == "MARK":
-                gates.append(synth.Gate(name, -1, -1, 0.0, -1, int(rng.integers(1 << n))))
-            else:
-                gates.append(synth.Gate(name, q, -1, ang))
-    rng.shuffle(gates)
+    gates, params = synth.all_kinds_circuit(n, n)
     psi0 = synth.random_state(n, 9)
-    ref = O.simulate(n, gates, psi0=psi0)
+    ref = O.simulate(n, gates, params, psi0=psi0)
     for dt in ("c128", "c64"):
-        got, _ = _emulate(n, gates, dt, psi0=psi0)
+        got, _ = _emulate(n, gates, dt, psi0=psi0, params=params)
         assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
 
 
@@ -220,3 +209,24 @@ def test_remapped_plans(n, depth, seed, kind, dtype):
         moved += int(sorted(L0["thr_goff"][:8].tolist()) != sorted(Ls["thr_goff"][:8].tolist())
                      or sorted(L0["reg_goff"][:plan["R"]].tolist()) != sorted(Ls["reg_goff"][:plan["R"]].tolist()))
     assert moved > 0
+
+
+@pytest.mark.parametrize("n", [3, 6, 9])
+def test_small_path_every_kind(n):
+    gates, params = synth.all_kinds_circuit(n, 40 + n)
+    ref = O.simulate(n, gates, params)
+    for dt in ("c128", "c64"):
+        got, plan = _emulate(n, gates, dt, params=params)
+        assert plan["small"]
+        assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
+
+
+def test_matrix_gate_validation():
+    g1 = [synth.Gate("U1", 0, -1, 0.0, 2)]
+    with pytest.raises(P.SVError):
+        P.debug_plan(12, g1, params=np.zeros(9))      # 2 + 8 > 9 reals
+    P.debug_plan(12, g1, params=np.zeros(10))
+    with pytest.raises(P.SVError):
+        P.debug_plan(12, [synth.Gate("U2", 0, 1, 0.0, -1)])   # matrix must come from params
+    with pytest.raises(P.SVError):
+        P.debug_plan(12, [synth.Gate("U2", 3, 3, 0.0, 0)], params=np.zeros(32))
