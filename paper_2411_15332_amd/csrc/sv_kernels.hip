@@ -197,6 +197,15 @@ __device__ __forceinline__ void r_d1_half(cpx<T> (&a)[NR], cpx<T> d) {
         if (((j >> P) & 1) == V) cmul_ip(a[j], d);
 }
 
+// amp *= d for the slots whose register bit P equals V and whose bit pb
+// (uniform, run time) equals xb
+template <int P, int V, typename T, int NR>
+__device__ __forceinline__ void r_d1_quarter(cpx<T> (&a)[NR], cpx<T> d, uint32_t pb, uint32_t xb) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (((j >> P) & 1) == V && (((uint32_t)j >> pb) & 1u) == xb) cmul_ip(a[j], d);
+}
+
 template <int PA, int PB, typename T, int NR>
 __device__ __forceinline__ void r_d2_regreg(cpx<T> (&a)[NR], const cpx<T> (&d)[4]) {
 #pragma unroll
@@ -479,25 +488,29 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 break;
             }
             case OP_D2Q: {
-                // rare (both qubits of a CZ / CPHASE in registers): selects
-                // keep the code small instead of one body per bit pair
-                const cpx<T> d = plc<T>(op, 0), one = mk<T>((T)1, (T)0);
-                const int xa = op.sa() & 1, xb = (op.sa() >> 1) & 1;
-#pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    const bool hit = ((j >> op.a()) & 1) == xa && ((j >> op.b()) & 1) == xb;
-                    cmul_ip(a[j], hit ? d : one);
+                // the quarter of the slots with bit a == xa and bit b == xb:
+                // bit a (and its value) at compile time, bit b per slot by a
+                // uniform branch
+                const cpx<T> d = plc<T>(op, 0);
+                const uint32_t pb = op.b(), xb = (op.sa() >> 1) & 1;
+                if (op.sa() & 1) {
+                    SV_SWITCH_A(op.a(), r_d1_quarter<PA, 1>(a, d, pb, xb))
+                } else {
+                    SV_SWITCH_A(op.a(), r_d1_quarter<PA, 0>(a, d, pb, xb))
                 }
                 break;
             }
             case OP_D1HU: {
+                // under an execution mask: threads (and, for tile-base or
+                // upper thread bits, whole waves) whose bit does not match skip
                 const cpx<T> d = plc<T>(op, 0);
                 const bool on = src_bit(op.sa(), tid, base) == ((op.b() >> 1) & 1);
-                const cpx<T> e = on ? d : mk<T>((T)1, (T)0);
-                if (op.b() & 1) {
-                    SV_SWITCH_A(op.a(), r_d1_half<PA, 1>(a, e))
-                } else {
-                    SV_SWITCH_A(op.a(), r_d1_half<PA, 0>(a, e))
+                if (on) {
+                    if (op.b() & 1) {
+                        SV_SWITCH_A(op.a(), r_d1_half<PA, 1>(a, d))
+                    } else {
+                        SV_SWITCH_A(op.a(), r_d1_half<PA, 0>(a, d))
+                    }
                 }
                 break;
             }
