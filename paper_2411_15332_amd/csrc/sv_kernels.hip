@@ -160,6 +160,24 @@ __device__ __forceinline__ void r_h(cpx<T> (&a)[NR]) {
     }
 }
 
+// The 2x2 diag(i^G0, i^G1) R diag(1, i^BT) on register bit P, R real: two
+// real products per complex output instead of four. The factors of i are
+// re/im renames and signs, folded into the multiply-adds.
+template <int P, int G0, int G1, int BT, typename T, int NR>
+__device__ __forceinline__ void r_dense1_ri(cpx<T> (&a)[NR], T r00, T r01, T r10, T r11) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & (1 << P)) continue;
+        const int j1 = j | (1 << P);
+        const cpx<T> x0 = a[j], x1 = a[j1];
+        const T y1r = BT ? -x1.y : x1.x, y1i = BT ? x1.x : x1.y;   // i^BT x1
+        const T z0r = r00 * x0.x + r01 * y1r, z0i = r00 * x0.y + r01 * y1i;
+        const T z1r = r10 * x0.x + r11 * y1r, z1i = r10 * x0.y + r11 * y1i;
+        a[j] = G0 ? mk<T>(-z0i, z0r) : mk<T>(z0r, z0i);
+        a[j1] = G1 ? mk<T>(-z1i, z1r) : mk<T>(z1r, z1i);
+    }
+}
+
 template <int P, typename T, int NR>
 __device__ __forceinline__ void r_dense1(cpx<T> (&a)[NR], cpx<T> g00, cpx<T> g01, cpx<T> g10,
                                          cpx<T> g11) {
@@ -634,10 +652,27 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 break;
             }
             case OP_DENSE1: {
-                const cpx<T> g00 = cmul(f, plc<T>(op, 0)), g01 = cmul(f, plc<T>(op, 1));
-                const cpx<T> g10 = cmul(f, plc<T>(op, 2)), g11 = cmul(f, plc<T>(op, 3));
-                f = mk<T>((T)1, (T)0);
+                cpx<T> g00 = plc<T>(op, 0), g01 = plc<T>(op, 1);
+                cpx<T> g10 = plc<T>(op, 2), g11 = plc<T>(op, 3);
+                if (op.b()) {
+                    g00 = cmul(f, g00);
+                    g01 = cmul(f, g01);
+                    g10 = cmul(f, g10);
+                    g11 = cmul(f, g11);
+                    f = mk<T>((T)1, (T)0);
+                }
                 SV_SWITCH_A(op.a(), r_dense1<PA>(a, g00, g01, g10, g11))
+                break;
+            }
+            case OP_DENSE1RI: {
+                const T r00 = pl<T>(op, 0), r01 = pl<T>(op, 1), r10 = pl<T>(op, 2), r11 = pl<T>(op, 3);
+#define SV_RI(F) \
+    case F: SV_SWITCH_A(op.a(), (r_dense1_ri<PA, ((F) & 1), (((F) >> 1) & 1), ((F) >> 2)>(a, r00, r01, r10, r11))) break;
+                switch (op.b()) {
+                    SV_RI(0) SV_RI(1) SV_RI(2) SV_RI(3) SV_RI(4) SV_RI(5) SV_RI(6) SV_RI(7)
+                    default: break;
+                }
+#undef SV_RI
                 break;
             }
             case OP_H: {

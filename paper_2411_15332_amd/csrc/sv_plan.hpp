@@ -45,7 +45,8 @@ enum OpCode : uint8_t {
     OP_APPLYF = 5,   // amp *= f for every slot; f = 1
     OP_D2RR = 6,     // amp *= f d[(bit a of j << 1) | bit b of j], f = 1; payload d[4]
     OP_D2RU = 7,     // amp *= f e[u][bit a of j], u = bit of source sa, f = 1; payload e[2][2]
-    OP_DENSE1 = 8,   // f times a 2x2 on register bit a, f = 1; payload g00 g01 g10 g11
+    OP_DENSE1 = 8,   // a 2x2 on register bit a; payload g00 g01 g10 g11; with b = 1 the
+                     // matrix is first multiplied by f, and f = 1 (b = 0: f untouched)
     OP_H = 9,        // unscaled Hadamard butterfly (x0 + x1, x0 - x1) on register bit a
     OP_X = 10,       // swap the pairs of register bit a
     OP_CXR = 11,     // swap the pairs of register bit a where register bit b is 1
@@ -63,6 +64,9 @@ enum OpCode : uint8_t {
     OP_DENSE2 = 20,  // 4x4 on register bits 1 (high) and 0 (low): entries row-major, the
                      // first ones in this payload, the rest in the OP_CONT records after it
     OP_CONT = 21,    // continuation of the preceding operation's payload (not executed)
+    OP_DENSE1RI = 22,  // a 2x2 whose entries are each real or imaginary, on register bit a:
+                       // diag(i^g0, i^g1) R diag(1, i^bt) with R real (payload r00 r01 r10
+                       // r11), g0 = bit 0 of b, g1 = bit 1, bt = bit 2 (f untouched)
 };
 
 constexpr uint8_t kNoSource = 0xFF;

@@ -642,14 +642,89 @@ struct PassCtx {
             ++h_count;
         } else {
             emit_ud();
-            HostOp &o = emit(OP_DENSE1);
-            o.hdr.a = (uint8_t)p;
-            o.pk = PK_MAT2;
-            o.factors = pd.f;
+            uint8_t ri = 0;
+            if (!f_used && ri_form(pd.f, ri)) {
+                // half the arithmetic of a general 2x2; needs f = 1
+                HostOp &o = emit(OP_DENSE1RI);
+                o.hdr.a = (uint8_t)p;
+                o.hdr.b = ri;
+                o.pk = PK_MAT2RI;
+                o.factors = pd.f;
+            } else {
+                HostOp &o = emit(OP_DENSE1);
+                o.hdr.a = (uint8_t)p;
+                o.hdr.b = f_used ? 1 : 0;   // fold the pending per-thread factor
+                o.pk = PK_MAT2;
+                o.factors = pd.f;
+            }
             note_payload();
             f_used = false;
         }
         pd = Pending();
+    }
+
+    // Entry classes of a 2x2 as sets of phases: bit 0 real, bit 1 imaginary
+    // (0: the entry is zero for every parameter value, 3: complex).
+    static uint8_t ph_mul(uint8_t a, uint8_t b) {
+        if (!a || !b) return 0;
+        uint8_t r = 0;
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q)
+                if (((a >> p) & 1) && ((b >> q) & 1)) r |= (uint8_t)(1 << ((p + q) & 1));
+        return r;
+    }
+    void factor_classes(const Factor &f, uint8_t c[4]) const {
+        const uint8_t Z = 0, R = 1, I = 2, C = 3;
+        auto set = [&](uint8_t a, uint8_t b, uint8_t d, uint8_t e) { c[0] = a; c[1] = b; c[2] = d; c[3] = e; };
+        switch (f.kind) {
+        case FK_X: set(Z, R, R, Z); break;
+        case FK_YDIAG: set(I, Z, Z, I); break;
+        case FK_H: set(R, R, R, R); break;
+        default:
+            switch (cg_kind(f.gate)) {
+            case SV_GATE_I: case SV_GATE_Z: set(R, Z, Z, R); break;
+            case SV_GATE_X: set(Z, R, R, Z); break;
+            case SV_GATE_Y: set(Z, I, I, Z); break;
+            case SV_GATE_H: case SV_GATE_RY: set(R, R, R, R); break;
+            case SV_GATE_S: case SV_GATE_SDG: set(R, Z, Z, I); break;
+            case SV_GATE_T: case SV_GATE_TDG: case SV_GATE_P: set(R, Z, Z, C); break;
+            case SV_GATE_RX: set(R, I, I, R); break;
+            case SV_GATE_RZ: set(C, Z, Z, C); break;
+            default: set(C, C, C, C); break;
+            }
+        }
+        if (f.conj_x) {
+            std::swap(c[0], c[3]);
+            std::swap(c[1], c[2]);
+        }
+    }
+    // Whether the product of `fs` has, for every parameter value, the form
+    // diag(i^g0, i^g1) R diag(1, i^bt) with R real; `flags` = g0 | g1 << 1 | bt << 2.
+    bool ri_form(const std::vector<Factor> &fs, uint8_t &flags) const {
+        if (!gkinds) return false;
+        uint8_t m[4] = {1, 0, 0, 1};
+        for (const Factor &f : fs) {
+            uint8_t c[4];
+            factor_classes(f, c);
+            const uint8_t n[4] = {(uint8_t)(ph_mul(c[0], m[0]) | ph_mul(c[1], m[2])),
+                                  (uint8_t)(ph_mul(c[0], m[1]) | ph_mul(c[1], m[3])),
+                                  (uint8_t)(ph_mul(c[2], m[0]) | ph_mul(c[3], m[2])),
+                                  (uint8_t)(ph_mul(c[2], m[1]) | ph_mul(c[3], m[3]))};
+            std::copy(n, n + 4, m);
+        }
+        for (int fl = 0; fl < 8; ++fl) {
+            bool ok = true;
+            for (int e = 0; e < 4 && ok; ++e) {
+                const int r = e >> 1, col = e & 1;
+                const int ph = (((fl >> r) & 1) + (col ? (fl >> 2) & 1 : 0)) & 1;
+                ok = m[e] == 0 || m[e] == (uint8_t)(1 << ph);
+            }
+            if (ok) {
+                flags = (uint8_t)fl;
+                return true;
+            }
+        }
+        return false;
     }
     void flush_nondiag(int p) {
         if (pend[p].cls != PC_I && pend[p].cls != PC_D) flush(p);
@@ -1411,6 +1486,7 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
             int count = 0;
             switch (h.pk) {
             case PK_MAT2:
+            case PK_MAT2RI:
             case PK_DIAG2: {
                 cd M[4] = {1.0, 0.0, 0.0, 1.0};
                 for (const Factor &f : h.factors) {
@@ -1423,6 +1499,15 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
                 if (h.pk == PK_MAT2) {
                     for (int e = 0; e < 4; ++e) { v[2 * e] = M[e].real() * h.scale; v[2 * e + 1] = M[e].imag() * h.scale; }
                     count = 8;
+                } else if (h.pk == PK_MAT2RI) {
+                    // R_rc = M_rc / i^(g_r + bt c): exact, the other part is zero
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = e >> 1, col = e & 1;
+                        const int ph = ((h.hdr.b >> r) & 1) + (col ? (h.hdr.b >> 2) & 1 : 0);
+                        const double x = ph & 1 ? M[e].imag() : M[e].real();
+                        v[e] = (ph & 2 ? -x : x) * h.scale;
+                    }
+                    count = 4;
                 } else {
                     v[0] = M[0].real() * h.scale; v[1] = M[0].imag() * h.scale;
                     v[2] = M[3].real() * h.scale; v[3] = M[3].imag() * h.scale;

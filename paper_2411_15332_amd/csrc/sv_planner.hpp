@@ -54,6 +54,8 @@ struct Factor {
 enum PayloadKind : uint8_t {
     PK_NONE = 0,
     PK_MAT2,    // the 2x2 product of `factors`
+    PK_MAT2RI,  // the real R of that product written as diag(i^g0, i^g1) R diag(1, i^bt)
+                // (g0, g1, bt: bits 0..2 of hdr.b)
     PK_DIAG2,   // its two diagonal entries
     PK_D4,      // the 2-qubit diagonal gate's entries, permuted by perm
     PK_SCALE,   // one real

@@ -12,7 +12,7 @@ import numpy as np
 
 (OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
  OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU, OP_RPERM, OP_DENSE2,
- OP_CONT) = range(1, 22)
+ OP_CONT, OP_DENSE1RI) = range(1, 23)
 NO_SOURCE = 0xFF
 SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE = range(1, 11)
 SRC_REG, SRC_THR, SRC_TILE = 0, 1, 2
@@ -223,8 +223,21 @@ def run_plan(plan, psi, n):
             elif code == OP_DENSE1:
                 lo, hi = pairs(oa)
                 x0, x1 = a[:, :, lo], a[:, :, hi]
-                a[:, :, lo], a[:, :, hi] = f * (d[0] * x0 + d[1] * x1), f * (d[2] * x0 + d[3] * x1)
-                f = np.ones_like(f)
+                if ob:
+                    a[:, :, lo], a[:, :, hi] = f * (d[0] * x0 + d[1] * x1), f * (d[2] * x0 + d[3] * x1)
+                    f = np.ones_like(f)
+                else:
+                    # the planner leaves f out only while it is 1
+                    assert np.all(f == 1), "DENSE1 without the factor while f != 1"
+                    a[:, :, lo], a[:, :, hi] = d[0] * x0 + d[1] * x1, d[2] * x0 + d[3] * x1
+            elif code == OP_DENSE1RI:
+                assert np.all(f == 1), "DENSE1RI while f != 1"
+                g0, g1, bt = ob & 1, (ob >> 1) & 1, (ob >> 2) & 1
+                m = np.array([[pl[0], pl[1]], [pl[2], pl[3]]], dtype=np.complex128)
+                m = np.diag([1j ** g0, 1j ** g1]) @ m @ np.diag([1, 1j ** bt])
+                lo, hi = pairs(oa)
+                x0, x1 = a[:, :, lo], a[:, :, hi]
+                a[:, :, lo], a[:, :, hi] = m[0, 0] * x0 + m[0, 1] * x1, m[1, 0] * x0 + m[1, 1] * x1
             elif code == OP_H:
                 lo, hi = pairs(oa)
                 x0, x1 = a[:, :, lo], a[:, :, hi]
