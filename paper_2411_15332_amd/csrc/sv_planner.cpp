@@ -643,8 +643,10 @@ struct PassCtx {
         } else {
             emit_ud();
             uint8_t ri = 0;
-            if (!f_used && ri_form(pd.f, ri)) {
-                // half the arithmetic of a general 2x2; needs f = 1
+            if (ri_form(pd.f, ri)) {
+                // half the arithmetic of a general 2x2; a pending per-thread
+                // factor stays pending (it is the same for every register
+                // slot, so it commutes with register-bit operations)
                 HostOp &o = emit(OP_DENSE1RI);
                 o.hdr.a = (uint8_t)p;
                 o.hdr.b = ri;
@@ -656,9 +658,9 @@ struct PassCtx {
                 o.hdr.b = f_used ? 1 : 0;   // fold the pending per-thread factor
                 o.pk = PK_MAT2;
                 o.factors = pd.f;
+                f_used = false;
             }
             note_payload();
-            f_used = false;
         }
         pd = Pending();
     }

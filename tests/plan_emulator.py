@@ -136,6 +136,8 @@ def run_plan(plan, psi, n):
             pl = op["payload"].view(np.float32).astype(np.float64) if plan.get("f32") else op["payload"]
             d = pl[0::2] + 1j * pl[1::2]
             if code == OP_EXCH:
+                # the per-thread factor does not travel with the amplitudes
+                assert np.all(f == 1), "pending per-thread factor at an exchange"
                 # Two halves through a half-tile buffer: the half is the value
                 # of label sb, taken from the same register bit or thread bit
                 # (source sa) on both sides; slots drop bit sb.
@@ -227,11 +229,8 @@ def run_plan(plan, psi, n):
                     a[:, :, lo], a[:, :, hi] = f * (d[0] * x0 + d[1] * x1), f * (d[2] * x0 + d[3] * x1)
                     f = np.ones_like(f)
                 else:
-                    # the planner leaves f out only while it is 1
-                    assert np.all(f == 1), "DENSE1 without the factor while f != 1"
                     a[:, :, lo], a[:, :, hi] = d[0] * x0 + d[1] * x1, d[2] * x0 + d[3] * x1
             elif code == OP_DENSE1RI:
-                assert np.all(f == 1), "DENSE1RI while f != 1"
                 g0, g1, bt = ob & 1, (ob >> 1) & 1, (ob >> 2) & 1
                 m = np.array([[pl[0], pl[1]], [pl[2], pl[3]]], dtype=np.complex128)
                 m = np.diag([1j ** g0, 1j ** g1]) @ m @ np.diag([1, 1j ** bt])
@@ -266,6 +265,7 @@ def run_plan(plan, psi, n):
                 a = a * pl[0]
             else:
                 raise NotImplementedError(code)
+        assert np.all(f == 1), "pending per-thread factor at the store"
         goff, _ = tables(int(P["store_layout"]))
         assert np.all((goff & base) == 0)
         psi[base | goff] = a
