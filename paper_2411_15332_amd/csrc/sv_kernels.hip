@@ -375,62 +375,78 @@ __device__ __forceinline__ void thr_part(const DevLayout &L, int tid, uint64_t &
     s = sl;
 }
 
-// Register part: one value per slot j, XOR of the per-bit entries of j.
-template <int R>
-__device__ __forceinline__ void reg_goff(const DevLayout &L, uint64_t (&g)[1 << R]) {
-    g[0] = L.reg_goff_xor;
-#pragma unroll
-    for (int j = 1; j < (1 << R); ++j) g[j] = g[j & (j - 1)] ^ L.reg_goff[__builtin_ctz(j)];
-}
-template <int R>
-__device__ __forceinline__ void reg_slot(const DevLayout &L, uint32_t (&s)[1 << R]) {
-    s[0] = 0;
-#pragma unroll
-    for (int j = 1; j < (1 << R); ++j) s[j] = s[j & (j - 1)] ^ L.reg_slot[__builtin_ctz(j)];
-}
-
 // Slot index with bit `lo`-position removed (lo = 2^b - 1): the half-tile
 // address of a slot whose bit b is fixed by the half being exchanged.
 __device__ __forceinline__ uint32_t drop_bit(uint32_t x, uint32_t lo) {
     return (x & lo) | ((x >> 1) & ~lo);
 }
 
+// Register bit b of the i-th slot of a Gray-code walk over the register bits
+// other than P (the walk flips one bit per step: bit ctz(i) of the reduced
+// index).
+template <int P>
+__host__ __device__ constexpr int gray_bit(int i) {
+    return __builtin_ctz(i) < P ? __builtin_ctz(i) : __builtin_ctz(i) + 1;
+}
+// Slot j visited at step i of that walk in half h.
+template <int P>
+__host__ __device__ constexpr int gray_slot(int i, int h) {
+    const int g = i ^ (i >> 1);
+    return ((g >> P) << (P + 1)) | (h << P) | (g & ((1 << P) - 1));
+}
+
 // Half-tile exchange, halves chosen by register bit P: every thread takes
-// part in both halves with half of its registers.
-template <int P, typename T, int NR>
+// part in both halves with half of its registers. LDS byte addresses are the
+// thread part XOR the per-register-bit generators (gw, gr), accumulated along
+// a Gray-code walk, so only R generators stay live.
+template <int P, typename T, int NR, int R>
 __device__ __forceinline__ void exch_reg_halves(cpx<T> (&a)[NR], char *ldsb, uint32_t tw,
-                                                const uint32_t (&sw)[NR], uint32_t tr,
-                                                const uint32_t (&sr)[NR]) {
+                                                const uint32_t (&gw)[R], uint32_t tr,
+                                                const uint32_t (&gr)[R]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         __syncthreads();
+        uint32_t aw = h ? tw ^ gw[P] : tw;
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-            if (((j >> P) & 1) == h) *reinterpret_cast<cpx<T> *>(ldsb + (tw ^ sw[j])) = a[j];
+        for (int i = 0; i < NR / 2; ++i) {
+            if (i) aw ^= gw[gray_bit<P>(i)];
+            *reinterpret_cast<cpx<T> *>(ldsb + aw) = a[gray_slot<P>(i, h)];
+        }
         __syncthreads();
+        uint32_t ar = h ? tr ^ gr[P] : tr;
 #pragma unroll
-        for (int j = 0; j < NR; ++j)
-            if (((j >> P) & 1) == h) a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (tr ^ sr[j]));
+        for (int i = 0; i < NR / 2; ++i) {
+            if (i) ar ^= gr[gray_bit<P>(i)];
+            a[gray_slot<P>(i, h)] = *reinterpret_cast<const cpx<T> *>(ldsb + ar);
+        }
     }
 }
 
 // Half-tile exchange, halves chosen by a thread bit: the threads whose bit is
 // h move all of their registers in half h.
-template <typename T, int NR>
+template <typename T, int NR, int R>
 __device__ __forceinline__ void exch_thr_halves(cpx<T> (&a)[NR], char *ldsb, uint32_t tw,
-                                                const uint32_t (&sw)[NR], uint32_t tr,
-                                                const uint32_t (&sr)[NR], int mine) {
+                                                const uint32_t (&gw)[R], uint32_t tr,
+                                                const uint32_t (&gr)[R], int mine) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         __syncthreads();
         if (mine == h) {
+            uint32_t aw = tw;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) *reinterpret_cast<cpx<T> *>(ldsb + (tw ^ sw[j])) = a[j];
+            for (int i = 0; i < NR; ++i) {
+                if (i) aw ^= gw[__builtin_ctz(i)];
+                *reinterpret_cast<cpx<T> *>(ldsb + aw) = a[i ^ (i >> 1)];
+            }
         }
         __syncthreads();
         if (mine == h) {
+            uint32_t ar = tr;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) a[j] = *reinterpret_cast<const cpx<T> *>(ldsb + (tr ^ sr[j]));
+            for (int i = 0; i < NR; ++i) {
+                if (i) ar ^= gr[__builtin_ctz(i)];
+                a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T> *>(ldsb + ar);
+            }
         }
     }
 }
@@ -475,36 +491,44 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
 
     cpx<T> a[NR];
     {
+        // Global index of slot j: (base | thread part) XOR the register part,
+        // accumulated along a Gray-code walk over the register bits (the
+        // parts occupy disjoint bits), so only R per-bit offsets stay live.
         const DevLayout &L = LB[0];
         uint64_t gthr;
         uint32_t sdummy;
         thr_part<W>(L, tid, gthr, sdummy);
-        uint64_t greg[NR];
-        reg_goff<R>(L, greg);
-        const cpx<T> *tp = st + (base | gthr);
+        uint64_t idx = (base | gthr) ^ L.reg_goff_xor;
         if (P.flags & PASS_GENERATE) {
             // On-demand Hadamard-layer amplitudes of H^M |j>:
             // 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M.
             const uint64_t gm = P.gen_mask, gj = P.gen_j;
             const T mag = (T)P.gen_scale;
 #pragma unroll
-            for (int j = 0; j < NR; ++j) {
-                const uint64_t i = base | gthr | greg[j];
-                const bool on = ((i ^ gj) & ~gm) == 0;
-                const T v = (__popcll(i & gj & gm) & 1) ? -mag : mag;
-                a[j] = mk<T>(on ? v : (T)0, (T)0);
+            for (int i = 0; i < NR; ++i) {
+                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+                const bool on = ((idx ^ gj) & ~gm) == 0;
+                const T v = (__popcll(idx & gj & gm) & 1) ? -mag : mag;
+                a[i ^ (i >> 1)] = mk<T>(on ? v : (T)0, (T)0);
             }
         } else if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
+            // slots 2m and 2m + 1 are adjacent in memory (register bit 0 is
+            // label 0): one 16-byte access; walk the other register bits
 #pragma unroll
-            for (int j = 0; j < NR; j += 2) {
+            for (int i = 0; i < NR / 2; ++i) {
+                if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
+                const int j = (i ^ (i >> 1)) << 1;
                 cpx<float> a0, a1;
-                ld_stream2(reinterpret_cast<const cpx<float> *>(tp + greg[j]), a0, a1);
+                ld_stream2(reinterpret_cast<const cpx<float> *>(st + idx), a0, a1);
                 a[j] = mk<T>((T)a0.x, (T)a0.y);
                 a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < NR; ++j) a[j] = ld_stream(tp + greg[j]);
+            for (int i = 0; i < NR; ++i) {
+                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+                a[i ^ (i >> 1)] = ld_stream(st + idx);
+            }
         }
     }
 
@@ -519,23 +543,22 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
             switch (op.code()) {
             case OP_EXCH: {
                 const uint32_t lo = (1u << op.sb()) - 1u;
+                const DevLayout &Lw = LB[op.a()], &Lr = LB[op.b()];
                 uint64_t gd;
-                uint32_t tw, tr, sw[NR], sr[NR];
-                thr_part<W>(LB[op.a()], tid, gd, tw);
-                thr_part<W>(LB[op.b()], tid, gd, tr);
-                reg_slot<R>(LB[op.a()], sw);
-                reg_slot<R>(LB[op.b()], sr);
+                uint32_t tw, tr, gw[R], gr[R];
+                thr_part<W>(Lw, tid, gd, tw);
+                thr_part<W>(Lr, tid, gd, tr);
                 tw = drop_bit(tw, lo) << SH;
                 tr = drop_bit(tr, lo) << SH;
 #pragma unroll
-                for (int j = 0; j < NR; ++j) {
-                    sw[j] = drop_bit(sw[j], lo) << SH;
-                    sr[j] = drop_bit(sr[j], lo) << SH;
+                for (int b = 0; b < R; ++b) {
+                    gw[b] = drop_bit(Lw.reg_slot[b], lo) << SH;
+                    gr[b] = drop_bit(Lr.reg_slot[b], lo) << SH;
                 }
                 if ((op.sa() & ~SRC_POS_MASK) == SRC_REG) {
-                    SV_SWITCH_A(op.sa() & SRC_POS_MASK, exch_reg_halves<PA>(a, ldsb, tw, sw, tr, sr))
+                    SV_SWITCH_A(op.sa() & SRC_POS_MASK, exch_reg_halves<PA>(a, ldsb, tw, gw, tr, gr))
                 } else {
-                    exch_thr_halves(a, ldsb, tw, sw, tr, sr, (tid >> (op.sa() & SRC_POS_MASK)) & 1);
+                    exch_thr_halves(a, ldsb, tw, gw, tr, gr, (tid >> (op.sa() & SRC_POS_MASK)) & 1);
                 }
                 break;
             }
@@ -724,18 +747,21 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         uint64_t gthr;
         uint32_t sdummy;
         thr_part<W>(L, tid, gthr, sdummy);
-        uint64_t greg[NR];
-        reg_goff<R>(L, greg);
-        cpx<T> *tp = st + (base | gthr);
+        uint64_t idx = (base | gthr) ^ L.reg_goff_xor;
         if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
 #pragma unroll
-            for (int j = 0; j < NR; j += 2)
-                st_stream2(reinterpret_cast<cpx<float> *>(tp + greg[j]),
-                           mk<float>((float)a[j].x, (float)a[j].y),
+            for (int i = 0; i < NR / 2; ++i) {
+                if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
+                const int j = (i ^ (i >> 1)) << 1;
+                st_stream2(reinterpret_cast<cpx<float> *>(st + idx), mk<float>((float)a[j].x, (float)a[j].y),
                            mk<float>((float)a[j + 1].x, (float)a[j + 1].y));
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < NR; ++j) st_stream(tp + greg[j], a[j]);
+            for (int i = 0; i < NR; ++i) {
+                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+                st_stream(st + idx, a[i ^ (i >> 1)]);
+            }
         }
     }
 }
