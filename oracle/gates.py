@@ -11,6 +11,10 @@ is the high bit, e.g. CNOT(q0 = control, q1 = target).
 Parity pins (tests/test_oracle_pins.py): unitarity, the paper's X, Y and Y (x) X,
 rotations against scipy's matrix exponential of the Pauli matrices, and the
 algebraic identities S^2 = Z, T^2 = S, CPHASE(pi) = CZ, CNOT = (I (x) H) CZ (I (x) H).
+The Table 1 additions (CY, ISWAP, DCX, CRZ, RZZ, CU1, CCX, CSWAP) are pinned by
+the bit logic of the permutations, matrix exponentials of their generators,
+and textbook identities (CY = (I (x) S) CNOT (I (x) S^dagger), ISWAP^2 = Z (x) Z,
+DCX^3 = I, CCX = (I (x) I (x) H) CCZ (I (x) I (x) H), CSWAP from three CCX).
 """
 from __future__ import annotations
 
@@ -37,6 +41,26 @@ _FIXED_2Q = {
     "CNOT": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]],
     "CZ": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, -1]],
     "SWAP": [[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
+    # controlled Y (q0 = control)
+    "CY": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, -1j], [0, 0, 1j, 0]],
+    # SWAP with a factor i on the two exchanged states
+    "ISWAP": [[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]],
+    # double CNOT: |x y> -> |y, x xor y> (CNOT q0 -> q1, then CNOT q1 -> q0)
+    "DCX": [[1, 0, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1], [0, 1, 0, 0]],
+}
+
+# 3-qubit monomial gates (Table 1): local index (b_q0 << 2) | (b_q1 << 1) | b_q2.
+# CCX (Toffoli): q0, q1 controls, q2 target. CSWAP (Fredkin): q0 control,
+# q1 and q2 exchanged.
+def _perm8(a: int, b: int) -> np.ndarray:
+    m = np.eye(8, dtype=np.complex128)
+    m[[a, b]] = m[[b, a]]
+    return m
+
+
+_FIXED_3Q = {
+    "CCX": _perm8(6, 7),
+    "CSWAP": _perm8(5, 6),
 }
 
 
@@ -47,6 +71,8 @@ def matrix(name: str, angle: float = 0.0) -> np.ndarray:
         return np.array(_FIXED_1Q[name], dtype=np.complex128)
     if name in _FIXED_2Q:
         return np.array(_FIXED_2Q[name], dtype=np.complex128)
+    if name in _FIXED_3Q:
+        return _FIXED_3Q[name].copy()
     c, s = math.cos(angle / 2.0), math.sin(angle / 2.0)
     if name == "RX":
         return np.array([[c, -1j * s], [-1j * s, c]], dtype=np.complex128)
@@ -57,16 +83,26 @@ def matrix(name: str, angle: float = 0.0) -> np.ndarray:
                         dtype=np.complex128)
     if name == "P":
         return np.array([[1, 0], [0, cmath.exp(1j * angle)]], dtype=np.complex128)
-    if name == "CPHASE":
+    if name in ("CPHASE", "CU1"):
         return np.diag([1, 1, 1, cmath.exp(1j * angle)]).astype(np.complex128)
+    if name == "CRZ":   # controlled RZ (q0 = control)
+        return np.diag([1, 1, cmath.exp(-0.5j * angle), cmath.exp(0.5j * angle)]).astype(np.complex128)
+    if name == "RZZ":   # exp(-i angle Z (x) Z / 2)
+        m, p = cmath.exp(-0.5j * angle), cmath.exp(0.5j * angle)
+        return np.diag([m, p, p, m]).astype(np.complex128)
     raise ValueError(f"no matrix for gate {name!r}")
 
 
+TWO_QUBIT_ANGLED = ("CPHASE", "CU1", "CRZ", "RZZ")
+
+
 def arity(name: str) -> int:
-    """1 or 2 for matrix gates, 0 for the n-qubit MARK."""
+    """1, 2 or 3 for matrix gates, 0 for the n-qubit MARK."""
     if name == "MARK":
         return 0
-    return 2 if name in _FIXED_2Q or name in ("CPHASE", "U2") else 1
+    if name in _FIXED_3Q:
+        return 3
+    return 2 if name in _FIXED_2Q or name in TWO_QUBIT_ANGLED or name == "U2" else 1
 
 
 def params_matrix(name: str, params, offset: int) -> np.ndarray:

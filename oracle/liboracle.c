@@ -6,14 +6,15 @@
  *
  * What it computes is the plain definition of full-state simulation (paper
  * Sec. II-A, the equations U = I^(k-1) (x) G (x) I^(n-k) and U|phi>): every gate
- * is applied as a dense 2x2 or 4x4 complex matrix on the amplitudes it couples,
+ * is applied as a dense 2x2, 4x4 or 8x8 complex matrix on the amplitudes it couples,
  * in double precision, with no use of sparsity, diagonality or Hadamard
  * structure. The one n-qubit gate, MARK(m) (sign flip of basis state |m>, the
  * Grover phase oracle of Sec. IV-D), is applied by its definition.
  *
  * Conventions: amplitude index i = sum_q b_q 2^q (qubit q is bit q). A 2-qubit
  * gate matrix is indexed by the local index (b_q0 << 1) | b_q1, so the first
- * operand q0 is the high local bit. Complex numbers are C99 double complex,
+ * operand q0 is the high local bit; a 3-qubit gate's local index is
+ * (b_q0 << 2) | (b_q1 << 1) | b_q2. Complex numbers are C99 double complex,
  * interleaved (re, im) in memory.
  */
 #include <complex.h>
@@ -89,6 +90,31 @@ void or_apply_2q(cplx *psi, int n, int q0, int q1, const cplx *m) {
     }
 }
 
+/* 8x8 matrix on qubits (q0, q1, q2); row/column index (b_q0 << 2) | (b_q1 << 1) | b_q2. */
+void or_apply_3q(cplx *psi, int n, int q0, int q1, int q2, const cplx *m) {
+    const int64_t eighth = 1LL << (n - 3);
+    int srt[3] = {q0, q1, q2};
+    for (int i = 0; i < 3; ++i)
+        for (int j = i + 1; j < 3; ++j)
+            if (srt[j] < srt[i]) { int t = srt[i]; srt[i] = srt[j]; srt[j] = t; }
+    const int64_t s0 = 1LL << q0, s1 = 1LL << q1, s2 = 1LL << q2;
+#pragma omp parallel for schedule(static) if (eighth >= OR_PAR_MIN)
+    for (int64_t p = 0; p < eighth; ++p) {
+        int64_t base = ins0(ins0(ins0(p, srt[0]), srt[1]), srt[2]);
+        int64_t idx[8];
+        cplx a[8];
+        for (int l = 0; l < 8; ++l) {
+            idx[l] = base | ((l >> 2) & 1 ? s0 : 0) | ((l >> 1) & 1 ? s1 : 0) | ((l & 1) ? s2 : 0);
+            a[l] = psi[idx[l]];
+        }
+        for (int r = 0; r < 8; ++r) {
+            cplx acc = 0.0;
+            for (int c = 0; c < 8; ++c) acc += m[8 * r + c] * a[c];
+            psi[idx[r]] = acc;
+        }
+    }
+}
+
 /* MARK(m): the diagonal operator I - 2|m><m|. */
 void or_apply_mark(cplx *psi, int n, uint64_t mk) {
     (void)n;
@@ -96,27 +122,34 @@ void or_apply_mark(cplx *psi, int n, uint64_t mk) {
 }
 
 /*
- * Apply a whole gate list. kind[g] = 1 (1-qubit, matrix mats[16g .. 16g+3]),
- * 2 (2-qubit, mats[16g .. 16g+15]) or 3 (MARK, basis index idx[g]).
+ * Apply a whole gate list. kind[g] = 1 (1-qubit, matrix mats[64g .. 64g+3]),
+ * 2 (2-qubit, mats[64g .. 64g+15]), 3 (MARK, basis index idx[g]) or
+ * 4 (3-qubit on q0, q1, q2, mats[64g .. 64g+63]).
  * Returns the number of gates applied, or -(g+1) for a bad record g.
  */
 int64_t or_run(cplx *psi, int n, int64_t ng, const int32_t *kind,
-               const int32_t *q0, const int32_t *q1, const cplx *mats,
+               const int32_t *q0, const int32_t *q1, const int32_t *q2, const cplx *mats,
                const uint64_t *idx) {
     for (int64_t g = 0; g < ng; ++g) {
         switch (kind[g]) {
         case 1:
             if (q0[g] < 0 || q0[g] >= n) return -(g + 1);
-            or_apply_1q(psi, n, q0[g], mats + 16 * g);
+            or_apply_1q(psi, n, q0[g], mats + 64 * g);
             break;
         case 2:
             if (q0[g] < 0 || q0[g] >= n || q1[g] < 0 || q1[g] >= n || q0[g] == q1[g])
                 return -(g + 1);
-            or_apply_2q(psi, n, q0[g], q1[g], mats + 16 * g);
+            or_apply_2q(psi, n, q0[g], q1[g], mats + 64 * g);
             break;
         case 3:
             if (idx[g] >= (1ULL << n)) return -(g + 1);
             or_apply_mark(psi, n, idx[g]);
+            break;
+        case 4:
+            if (n < 3 || q0[g] < 0 || q0[g] >= n || q1[g] < 0 || q1[g] >= n || q2[g] < 0 || q2[g] >= n ||
+                q0[g] == q1[g] || q0[g] == q2[g] || q1[g] == q2[g])
+                return -(g + 1);
+            or_apply_3q(psi, n, q0[g], q1[g], q2[g], mats + 64 * g);
             break;
         default:
             return -(g + 1);

@@ -54,7 +54,7 @@ def lib():
         L.or_apply_1q.argtypes = [P, ctypes.c_int, ctypes.c_int, P]
         L.or_apply_2q.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
         L.or_apply_mark.argtypes = [P, ctypes.c_int, ctypes.c_uint64]
-        L.or_run.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, P, P]
+        L.or_run.argtypes = [P, ctypes.c_int, ctypes.c_int64, P, P, P, P, P, P]
         L.or_run.restype = ctypes.c_int64
         L.or_norm2.argtypes = [P, ctypes.c_int]
         L.or_norm2.restype = ctypes.c_double
@@ -94,12 +94,13 @@ def _angle(g, params) -> float:
 
 
 def encode(gates: Sequence, params: Optional[np.ndarray] = None):
-    """Gate list -> flat arrays (kind, q0, q1, mats[16], idx) for or_run."""
+    """Gate list -> flat arrays (kind, q0, q1, q2, mats[64], idx) for or_run."""
     ng = len(gates)
     kind = np.zeros(ng, dtype=np.int32)
     q0 = np.zeros(ng, dtype=np.int32)
     q1 = np.zeros(ng, dtype=np.int32)
-    mats = np.zeros((ng, 16), dtype=np.complex128)
+    q2 = np.full(ng, -1, dtype=np.int32)
+    mats = np.zeros((ng, 64), dtype=np.complex128)
     idx = np.zeros(ng, dtype=np.uint64)
     for k, g in enumerate(gates):
         a = G.arity(g.name)
@@ -113,11 +114,13 @@ def encode(gates: Sequence, params: Optional[np.ndarray] = None):
             m = G.params_matrix(g.name, params, g.param)
         else:
             m = G.matrix(g.name, _angle(g, params))
-        kind[k] = a
+        kind[k] = 4 if a == 3 else a
         q0[k] = g.q0
         q1[k] = g.q1
+        if a == 3:
+            q2[k] = g.q2
         mats[k, : m.size] = m.reshape(-1)
-    return kind, q0, q1, mats, idx
+    return kind, q0, q1, q2, mats, idx
 
 
 def apply(psi: np.ndarray, n: int, gates: Sequence, params: Optional[np.ndarray] = None) -> np.ndarray:
@@ -125,8 +128,9 @@ def apply(psi: np.ndarray, n: int, gates: Sequence, params: Optional[np.ndarray]
     assert psi.dtype == np.complex128 and psi.flags.c_contiguous and psi.size == (1 << n)
     if not gates:
         return psi
-    kind, q0, q1, mats, idx = encode(gates, params)
-    r = lib().or_run(_ptr(psi), n, len(gates), _ptr(kind), _ptr(q0), _ptr(q1), _ptr(mats), _ptr(idx))
+    kind, q0, q1, q2, mats, idx = encode(gates, params)
+    r = lib().or_run(_ptr(psi), n, len(gates), _ptr(kind), _ptr(q0), _ptr(q1), _ptr(q2), _ptr(mats),
+                     _ptr(idx))
     if r < 0:
         raise ValueError(f"oracle rejected gate #{-r - 1}: {gates[-r - 1]}")
     return psi
@@ -225,7 +229,8 @@ def monomial_amplitudes(n: int, gates: Sequence, indices: Sequence[int], initial
     row i's non-zero, so the amplitude is the product of the visited entries
     times psi_in at the index reached after walking the gates from last to
     first. The embedded U = I..(x) G (x)..I has U[i, c] = G[r(i), r(c)] where i
-    and c agree off the gate's qubits (r = the local row, (b_q0 << 1) | b_q1).
+    and c agree off the gate's qubits (r = the local row, (b_q0 << 1) | b_q1,
+    or (b_q0 << 2) | (b_q1 << 1) | b_q2 for a 3-qubit gate).
     initial: "uniform" (psi_in = 2^(-n/2) everywhere, i.e. H^n|0>) or a basis
     index j (psi_in = |j>). Returns complex128 [len(indices)]."""
     idx = np.array(indices, dtype=np.int64).copy()
@@ -241,6 +246,13 @@ def monomial_amplitudes(n: int, gates: Sequence, indices: Sequence[int], initial
             r = (idx >> g.q0) & 1
             c = cols[r]
             idx = (idx & ~np.int64(1 << g.q0)) | (c << g.q0)
+        elif G.arity(g.name) == 3:
+            qs = (g.q0, g.q1, g.q2)
+            r = (((idx >> qs[0]) & 1) << 2) | (((idx >> qs[1]) & 1) << 1) | ((idx >> qs[2]) & 1)
+            c = cols[r]
+            idx = idx & ~np.int64(sum(1 << q for q in qs))
+            for sh, q in zip((2, 1, 0), qs):
+                idx = idx | (((c >> sh) & 1) << q)
         else:
             r = (((idx >> g.q0) & 1) << 1) | ((idx >> g.q1) & 1)
             c = cols[r]

@@ -63,6 +63,19 @@ def embed_2q_kron(n: int, q0: int, q1: int, g: np.ndarray) -> np.ndarray:
     return Pm @ K @ Pm.T
 
 
+def embed_3q_kron(n: int, q0: int, q1: int, q2: int, g: np.ndarray) -> np.ndarray:
+    """G (x) I^(n-3) acts on bits (n-1, n-2, n-3) as (high, mid, low); relabel
+    those bits to (q0, q1, q2) and the remaining bits, in order, to the rest."""
+    K = kron_all([g] + [I2] * (n - 3)) if n > 3 else g.copy()
+    rest = [b for b in range(n) if b not in (q0, q1, q2)]
+    dest = [0] * n
+    for src, d in zip(range(n - 3), rest):
+        dest[src] = d
+    dest[n - 1], dest[n - 2], dest[n - 3] = q0, q1, q2
+    Pm = bit_permutation_matrix(n, dest)
+    return Pm @ K @ Pm.T
+
+
 def embed_2q_def(n: int, q0: int, q1: int, g: np.ndarray) -> np.ndarray:
     """Element-wise definition of the embedded 2-qubit operator."""
     N = 1 << n
@@ -89,6 +102,8 @@ def mtp_operator(n: int, gate, params: Optional[np.ndarray] = None) -> np.ndarra
         g = G.matrix(gate.name, ang)
     if G.arity(gate.name) == 1:
         return embed_1q(n, gate.q0, g)
+    if G.arity(gate.name) == 3:
+        return embed_3q_kron(n, gate.q0, gate.q1, gate.q2, g)
     return embed_2q_kron(n, gate.q0, gate.q1, g)
 
 

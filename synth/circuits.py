@@ -14,6 +14,8 @@ A gate is a ``Gate`` record:
   param  -1, or an index into a per-circuit parameter vector that replaces
          ``angle`` (used by the QNN ansatz)
   index  basis index for MARK (sign flip of one basis state), else 0
+  q2     third qubit of a 3-qubit gate (CCX: q0, q1 controls, q2 target;
+         CSWAP: q0 control, q1 and q2 exchanged), -1 otherwise
 
 Qubit q is bit q of the amplitude index (qubit 0 is the least significant bit).
 """
@@ -32,15 +34,20 @@ class Gate(NamedTuple):
     angle: float = 0.0
     param: int = -1
     index: int = 0
+    q2: int = -1      # third qubit of CCX / CSWAP
 
 
 ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P", "U1")
-TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE", "U2")
+# Table 1 two-qubit gates beyond the config mix: controlled Y, iSWAP, double
+# CNOT, controlled RZ, ZZ rotation and controlled phase (CU1 = CPHASE).
+TABLE1_2Q = ("CY", "ISWAP", "DCX", "CRZ", "RZZ", "CU1")
+TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE", "U2") + TABLE1_2Q
+THREE_QUBIT = ("CCX", "CSWAP")
 # U1 / U2: a general 2x2 / 4x4 matrix taken from the parameter vector at
 # `param` (8 / 32 reals: row-major (re, im) pairs), see matrix_params().
 MATRIX_GATES = ("U1", "U2")
 N_QUBIT = ("MARK",)
-GATE_NAMES = ONE_QUBIT + TWO_QUBIT + N_QUBIT
+GATE_NAMES = ONE_QUBIT + TWO_QUBIT + THREE_QUBIT + N_QUBIT
 ANGLED = ("RX", "RY", "RZ", "P", "CPHASE")
 
 # Gate pools of the seeded random workloads.
@@ -218,8 +225,8 @@ def random_state(n: int, seed: int) -> np.ndarray:
 
 
 def all_kinds_circuit(n: int, seed: int):
-    """Every gate kind on every qubit (2-qubit kinds with a random partner,
-    MARK with a random index), shuffled. U1 / U2 take random unitaries from the
+    """Every gate kind on every qubit (2- and 3-qubit kinds with random
+    partners, MARK with a random index), shuffled. U1 / U2 take random unitaries from the
     returned parameter vector. Returns (gates, params)."""
     rng = np.random.default_rng(seed)
     gates: List[Gate] = []
@@ -240,12 +247,41 @@ def all_kinds_circuit(n: int, seed: int):
                 if n < 2:
                     continue
                 gates.append(Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), ang))
+            elif name in THREE_QUBIT:
+                if n < 3:
+                    continue
+                others = [int(x) for x in rng.permutation([x for x in range(n) if x != q])[:2]]
+                gates.append(Gate(name, q, others[0], 0.0, -1, 0, others[1]))
             elif name == "MARK":
                 gates.append(Gate(name, -1, -1, 0.0, -1, int(rng.integers(0, 1 << n))))
             else:
                 gates.append(Gate(name, q, -1, ang))
     order = rng.permutation(len(gates))
     return [gates[i] for i in order], np.array(params, dtype=np.float64)
+
+
+def table1_circuit(n: int, seed: int, layers: int = 4):
+    """The Table 1 additions (CY, ISWAP, DCX, CRZ, RZZ, CU1, CCX, CSWAP), three
+    of each per layer at random distinct operands, between layers of RY on
+    every qubit. CRZ, RZZ and CU1 read their angles from the returned
+    parameter vector. Returns (gates, params)."""
+    rng = np.random.default_rng(seed)
+    gates: List[Gate] = []
+    params: List[float] = []
+    for _ in range(layers):
+        for q in range(n):
+            gates.append(Gate("RY", q, -1, float(rng.uniform(0, 2 * math.pi))))
+        for name in TABLE1_2Q + THREE_QUBIT:
+            for _ in range(3):
+                qs = [int(x) for x in rng.permutation(n)[:3]]
+                if name in ("CRZ", "RZZ", "CU1"):
+                    params.append(float(rng.uniform(-math.pi, math.pi)))
+                    gates.append(Gate(name, qs[0], qs[1], 0.0, len(params) - 1))
+                elif name in THREE_QUBIT:
+                    gates.append(Gate(name, qs[0], qs[1], 0.0, -1, 0, qs[2]))
+                else:
+                    gates.append(Gate(name, qs[0], qs[1]))
+    return gates, np.array(params, dtype=np.float64)
 
 
 def amplitude_gate_updates(n: int, gates: Sequence[Gate]) -> int:

@@ -121,6 +121,9 @@ def _all_single_gates(n, rng):
             out += [synth.Gate(name, q, -1, ang) for q in range(n)]
         elif ar == 2 and n >= 2:
             out += [synth.Gate(name, a, b, ang) for a in range(n) for b in range(n) if a != b]
+        elif ar == 3 and n >= 3:
+            out += [synth.Gate(name, a, b, 0.0, -1, 0, c) for a in range(n) for b in range(n)
+                    for c in range(n) if len({a, b, c}) == 3]
         elif ar == 0:
             out += [synth.Gate(name, -1, -1, 0.0, -1, int(j)) for j in
                     sorted(set([0, (1 << n) - 1, int(rng.integers(1 << n))]))]
@@ -453,3 +456,120 @@ def test_matrix_gates_vs_kronecker(n):
     want = U @ psi0
     got = O.simulate(n, gates, params, psi0=psi0)
     assert np.max(np.abs(got - want)) < 1e-13
+
+
+# ------------------------------------------ Table 1 additions (CY ... CSWAP)
+
+def _bits(i, q):
+    return (i >> q) & 1
+
+
+def _expected_basis_image(g, i):
+    """(index, phase) of gate g applied to |i>, from the gates' bit logic."""
+    a, b, c = g.q0, g.q1, g.q2
+    if g.name == "CCX":
+        return (i ^ (1 << c)) if _bits(i, a) and _bits(i, b) else i, 1
+    if g.name == "CSWAP":
+        if _bits(i, a) and _bits(i, b) != _bits(i, c):
+            return i ^ (1 << b) ^ (1 << c), 1
+        return i, 1
+    if g.name == "DCX":   # |x y> -> |y, x xor y> on (q0, q1)
+        x, y = _bits(i, a), _bits(i, b)
+        j = i & ~((1 << a) | (1 << b))
+        return j | (y << a) | ((x ^ y) << b), 1
+    if g.name == "CY":    # Y on q1 when q0 = 1: |0> -> i|1>, |1> -> -i|0>
+        if not _bits(i, a):
+            return i, 1
+        return i ^ (1 << b), (1j if not _bits(i, b) else -1j)
+    if g.name == "ISWAP":  # |01>, |10> exchanged with a factor i
+        if _bits(i, a) != _bits(i, b):
+            return i ^ (1 << a) ^ (1 << b), 1j
+        return i, 1
+    raise ValueError(g.name)
+
+
+@pytest.mark.parametrize("name", ["CY", "ISWAP", "DCX", "CCX", "CSWAP"])
+def test_table1_monomials_by_bit_logic(name):
+    """Each basis state goes to one basis state times a phase, as the gate's
+    definition in words says; checked on every basis state of n = 4 for every
+    operand placement."""
+    n = 4
+    ar = G.arity(name)
+    placements = ([(a, b, -1) for a in range(n) for b in range(n) if a != b] if ar == 2 else
+                  [(a, b, c) for a in range(n) for b in range(n) for c in range(n) if len({a, b, c}) == 3])
+    for a, b, c in placements:
+        g = synth.Gate(name, a, b, 0.0, -1, 0, c)
+        for i in range(1 << n):
+            psi = np.zeros(1 << n, dtype=complex)
+            psi[i] = 1.0
+            out = O.simulate(n, [g], psi0=psi)
+            j, ph = _expected_basis_image(g, i)
+            ref = np.zeros(1 << n, dtype=complex)
+            ref[j] = ph
+            assert np.array_equal(out, ref), (g, i)
+
+
+def test_table1_monomials_one_nonzero_per_row():
+    """Table 1 lists CY, iSWAP, DCX, CCX and CSWAP with one non-zero per row."""
+    for name in ("CY", "ISWAP", "DCX", "CCX", "CSWAP"):
+        m = G.matrix(name)
+        assert all(np.count_nonzero(r) == 1 for r in m), name
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, -1.7, 2.9, math.pi])
+def test_table1_diagonals_are_exponentials(theta):
+    """CRZ = exp(-i t/2 |1><1| (x) Z), RZZ = exp(-i t/2 Z (x) Z) and
+    CU1 = exp(i t |11><11|), with scipy's matrix exponential."""
+    P1 = np.diag([0, 1]).astype(complex)
+    crz = scipy.linalg.expm(-0.5j * theta * np.kron(P1, PZ))
+    rzz = scipy.linalg.expm(-0.5j * theta * np.kron(PZ, PZ))
+    cu1 = scipy.linalg.expm(1j * theta * np.kron(P1, P1))
+    assert np.allclose(G.matrix("CRZ", theta), crz, atol=1e-14)
+    assert np.allclose(G.matrix("RZZ", theta), rzz, atol=1e-14)
+    assert np.allclose(G.matrix("CU1", theta), cu1, atol=1e-14)
+
+
+def test_table1_identities():
+    I2 = np.eye(2, dtype=complex)
+    H = np.array([[1, 1], [1, -1]], dtype=complex) / math.sqrt(2)
+    S = np.diag([1, 1j])
+    cnot = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=complex)
+    # CY = (I (x) S) CNOT (I (x) S^dagger)
+    assert np.allclose(G.matrix("CY"), np.kron(I2, S) @ cnot @ np.kron(I2, S.conj().T), atol=1e-15)
+    # iSWAP^2 = Z (x) Z
+    sw = G.matrix("ISWAP")
+    assert np.allclose(sw @ sw, np.kron(PZ, PZ), atol=1e-15)
+    # DCX = CNOT(q1 -> q0) CNOT(q0 -> q1), and DCX^3 = I (a 3-cycle)
+    cnot10 = np.array([[1, 0, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0], [0, 1, 0, 0]], dtype=complex)
+    d = G.matrix("DCX")
+    assert np.allclose(d, cnot10 @ cnot, atol=0)
+    assert np.allclose(d @ d @ d, np.eye(4), atol=0)
+    # CCX = (I (x) I (x) H) CCZ (I (x) I (x) H)
+    ccz = np.diag([1, 1, 1, 1, 1, 1, 1, -1]).astype(complex)
+    hh = np.kron(np.kron(I2, I2), H)
+    assert np.allclose(G.matrix("CCX"), hh @ ccz @ hh, atol=1e-15)
+    # CSWAP(c; a, b) = CCX(c, b -> a) CCX(c, a -> b) CCX(c, b -> a), built
+    # from the element-wise embedding of CCX on 3 qubits
+    def ccx_on(c, x, t):
+        return K.mtp_operator(3, synth.Gate("CCX", c, x, 0.0, -1, 0, t))
+    fred = ccx_on(2, 0, 1) @ ccx_on(2, 1, 0) @ ccx_on(2, 0, 1)
+    assert np.allclose(K.mtp_operator(3, synth.Gate("CSWAP", 2, 1, 0.0, -1, 0, 0)), fred, atol=0)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_3q_embedding_vs_definition(n):
+    """The Kronecker embedding of a 3-qubit gate against the element-wise
+    definition U[r, c] = G[l(r), l(c)] when r and c agree off the 3 qubits."""
+    rng = np.random.default_rng(n)
+    g = synth.random_unitary(8, rng)
+    N = 1 << n
+    for a, b, c in [(0, 1, 2), (n - 1, 0, 1), (1, n - 1, 0)]:
+        U = K.embed_3q_kron(n, a, b, c, g)
+        r = np.arange(N)[:, None]
+        col = np.arange(N)[None, :]
+        mask = (1 << a) | (1 << b) | (1 << c)
+        same = (r & ~mask) == (col & ~mask)
+        lr = (((r >> a) & 1) << 2) | (((r >> b) & 1) << 1) | ((r >> c) & 1)
+        lc = (((col >> a) & 1) << 2) | (((col >> b) & 1) << 1) | ((col >> c) & 1)
+        ref = np.where(same, g[lr, lc], 0.0)
+        assert np.allclose(U, ref, atol=1e-15)
