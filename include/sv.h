@@ -60,20 +60,31 @@ typedef enum sv_dtype { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
  *   of Sec. IV-D, and with m = 0 the zero-state reflection),
  *   U1 / U2 = a general 2x2 / 4x4 complex matrix (any 1- or 2-qubit gate of
  *   Table 1), read from the parameter table: params[b][param ...] holds 8 / 32
- *   reals, row-major (re, im) pairs; U2's index is (b_q0 << 1) | b_q1. */
+ *   reals, row-major (re, im) pairs; U2's index is (b_q0 << 1) | b_q1.
+ * Further Table 1 gates (2-qubit index (b_q0 << 1) | b_q1):
+ *   CY = controlled Y (q0 control), ISWAP = [[1,0,0,0],[0,0,i,0],[0,i,0,0],[0,0,0,1]],
+ *   DCX: |x y> -> |y, x xor y> (CNOT q0 -> q1, then CNOT q1 -> q0),
+ *   CRZ(t) = diag(1, 1, e^{-it/2}, e^{it/2}), RZZ(t) = exp(-i t Z(x)Z / 2),
+ *   CU1(t) = CPHASE(t);
+ *   3-qubit monomials, third qubit q2 = sv_gate.index, local index
+ *   (b_q0 << 2) | (b_q1 << 1) | b_q2: CCX (Toffoli: q0, q1 controls, q2
+ *   target) and CSWAP (Fredkin: q0 control, q1 and q2 exchanged). */
 typedef enum sv_gate_kind {
     SV_GATE_I = 0, SV_GATE_X = 1, SV_GATE_Y = 2, SV_GATE_Z = 3, SV_GATE_H = 4,
     SV_GATE_S = 5, SV_GATE_SDG = 6, SV_GATE_T = 7, SV_GATE_TDG = 8,
     SV_GATE_RX = 9, SV_GATE_RY = 10, SV_GATE_RZ = 11, SV_GATE_P = 12,
     SV_GATE_CNOT = 13, SV_GATE_CZ = 14, SV_GATE_SWAP = 15, SV_GATE_CPHASE = 16,
     SV_GATE_MARK = 17, SV_GATE_U1 = 18, SV_GATE_U2 = 19,
-    SV_GATE_KIND_COUNT = 20
+    SV_GATE_CY = 20, SV_GATE_ISWAP = 21, SV_GATE_DCX = 22, SV_GATE_CRZ = 23,
+    SV_GATE_RZZ = 24, SV_GATE_CU1 = 25, SV_GATE_CCX = 26, SV_GATE_CSWAP = 27,
+    SV_GATE_KIND_COUNT = 28
 } sv_gate_kind;
 
 /* One gate, 32 bytes. q1 = -1 for 1-qubit gates and MARK; q0 = -1 for MARK.
  * param = -1: use `angle`; param >= 0: the angle is params[b][param] for batch
  * entry b (see sv_apply_circuit); U1 / U2 require param >= 0 (the first of
- * their 8 / 32 matrix reals). index: basis index of MARK, else ignored. */
+ * their 8 / 32 matrix reals). index: basis index of MARK, third qubit of CCX
+ * and CSWAP, else ignored. */
 typedef struct sv_gate {
     int32_t kind;
     int32_t q0;

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["sv_kernels.hip", "sv_planner.cpp", "sv_api.cpp", "sv_engine.cpp"]
+SOURCES = ["sv_kernels.hip", "sv_planner.cpp", "sv_lower.cpp", "sv_api.cpp", "sv_engine.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -372,18 +372,24 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
             return fail(SV_EINVAL, "%s", err.c_str());
         if (n_gates == 0) return SV_OK;
         const PlanOptions po = plan_options(s);
-        const bool hit = s->plan_valid && s->plan_gates.size() == n_gates &&
+        const bool hit = s->plan_valid && s->plan_gates.size() == n_gates && s->plan_nparams == n_params &&
                          same_options(s->plan_opts, po) &&
                          std::memcmp(s->plan_gates.data(), gates, n_gates * sizeof(sv_gate)) == 0;
         if (!hit) {
             s->plan_valid = false;
-            s->plan = build_plan(s->n, gates, n_gates, po);
+            lower_gates(gates, n_gates, n_params, s->plan_low);
+            s->plan = build_plan(s->n, s->plan_low.gates.data(), s->plan_low.gates.size(), po);
             s->plan_gates.assign(gates, gates + n_gates);
+            s->plan_nparams = n_params;
             s->plan_opts = po;
             s->plan_valid = true;
         }
         const Plan &p = s->plan;
-        st = run_plan(s, s->buf, s->batch, p, gates, params, n_params);
+        std::vector<double> ext;
+        lower_params(s->plan_low, params, n_params, s->batch, ext);
+        st = ext.empty() ? run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), params, n_params)
+                         : run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), ext.data(),
+                                    n_params + s->plan_low.src.size());
         if (st != SV_OK) return st;
         s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
         s->stats[1] = p.n_exch;
@@ -563,6 +569,12 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
             if (gates[i].param >= 0 && k != SV_GATE_RX && k != SV_GATE_RY && k != SV_GATE_RZ)
                 return fail(SV_EUNSUPPORTED, "gate %zu: only RX, RY and RZ may reference parameters", i);
         }
+        // composite kinds (fixed angles only, checked above) become planner
+        // kinds; every parametric gate keeps its parameter index
+        Lowering low;
+        lower_gates(gates, n_gates, n_params, low);
+        gates = low.gates.data();
+        n_gates = low.gates.size();
         const int B = s->batch;
         const uint64_t N = 1ull << s->n;
         const size_t state_bytes = (size_t)N * s->amp_bytes;
@@ -625,7 +637,7 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
             case SV_GATE_RX: case SV_GATE_RY: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CPHASE:
                 if (g.param < 0) g.angle = -g.angle;   // referenced angles come from the negated table
                 break;
-            default: break;   // X, Y, Z, H, CNOT, CZ, SWAP, MARK, I are self-inverse
+            default: break;   // X, Y, Z, H, CNOT, CZ, SWAP, CCX, MARK, I are self-inverse
             }
             return g;
         };
@@ -710,6 +722,16 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
         tmp.remap = opts[7] != 0;
     }
     const PlanOptions po = plan_options(&tmp);
+    Lowering low;
+    lower_gates(gates, n_gates, n_params, low);
+    std::vector<double> ext;
+    lower_params(low, params, n_params, 1, ext);
+    if (!ext.empty()) {
+        params = ext.data();
+        n_params += low.src.size();
+    }
+    gates = low.gates.data();
+    n_gates = low.gates.size();
     Plan p = build_plan(n, gates, n_gates, po);
     const size_t real_bytes = dtype == SV_C64 ? 4 : 8;  // constants in the state's precision
     const Layout L = plan_sections(p, 1, real_bytes);

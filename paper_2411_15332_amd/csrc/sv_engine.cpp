@@ -29,8 +29,9 @@ namespace {
 
 struct Template {
     int n = 0, qubit = 0;
+    Lowering low;            // composite kinds lowered
     std::vector<sv_gate> gates;
-    size_t n_params = 0;
+    size_t n_params = 0;     // caller's parameters plus derived columns
     bool small = false;
     Plan plan;
 };
@@ -366,16 +367,18 @@ sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate
             auto t = std::make_shared<Template>();
             t->n = n_qubits;
             t->qubit = qubit;
-            t->gates.assign(gates, gates + n_gates);
-            t->n_params = n_params;
+            lower_gates(gates, n_gates, n_params, t->low);
+            t->gates = t->low.gates;
+            t->n_params = n_params + t->low.src.size();
             t->small = n_qubits <= e->small_max;
-            t->plan = build_plan(n_qubits, t->gates.data(), n_gates, engine_plan_options(e, t->small));
+            t->plan = build_plan(n_qubits, t->gates.data(), t->gates.size(), engine_plan_options(e, t->small));
             it = e->templates.emplace(key, std::move(t)).first;
         }
         Request r;
         r.id = id;
         r.t = it->second;
-        r.params.assign(params, params + n_params);
+        if (it->second->low.src.empty()) r.params.assign(params, params + n_params);
+        else lower_params(it->second->low, params, n_params, 1, r.params);
         e->queue.push_back(std::move(r));
         return SV_OK;
     });

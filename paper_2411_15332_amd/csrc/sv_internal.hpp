@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/sv.h"
+#include "sv_lower.hpp"
 #include "sv_planner.hpp"
 
 namespace sv {
@@ -94,7 +95,9 @@ struct sv_state_s {
     // included); only its constants are materialized again (parameters may
     // differ). Planning is host work; every pass still runs on the device.
     std::vector<sv_gate> plan_gates;
+    size_t plan_nparams = 0;
     sv::PlanOptions plan_opts;
+    sv::Lowering plan_low;   // the gates the plan was built from (composite kinds lowered)
     sv::Plan plan;
     bool plan_valid = false;
 

@@ -146,6 +146,17 @@ __device__ __forceinline__ void cswap(cpx<T> &p, cpx<T> &q) {
     vswap(p.y, q.y);
 }
 
+// Toffoli on register bit P: swap the pairs whose slot bits under the
+// register-control mask cm equal cv (uniform values: a scalar branch per slot).
+template <int P, typename T, int NR>
+__device__ __forceinline__ void r_ccx(cpx<T> (&a)[NR], uint32_t cm, uint32_t cv) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j & (1 << P)) continue;
+        if (((uint32_t)j & cm) == cv) cswap(a[j], a[j | (1 << P)]);
+    }
+}
+
 // Hadamard butterfly (x0 + x1, x0 - x1) as x0 <- x0 + x1, x1 <- x0' - 2 x1
 template <int P, typename T, int NR>
 __device__ __forceinline__ void r_h(cpx<T> (&a)[NR]) {
@@ -721,6 +732,19 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 }
                 break;
             }
+            case OP_CCX: {
+                // thread / tile-base controls: the threads whose bits do not
+                // match skip (execution mask); register controls pick slots
+                const uint32_t uv = (uint32_t)(op.data >> 8) & 3u;
+                bool on = true;
+                if (op.sa() != kNoSource) on = on && src_bit(op.sa(), tid, base) == (int)(uv & 1u);
+                if (op.sb() != kNoSource) on = on && src_bit(op.sb(), tid, base) == (int)(uv >> 1);
+                if (on) {
+                    const uint32_t cm = op.b(), cv = (uint32_t)op.data & 0xFFu;
+                    SV_SWITCH_A(op.a(), r_ccx<PA>(a, cm, cv))
+                }
+                break;
+            }
             case OP_MARK: {
                 if (base == op.data && tid == (int)(op.sa() | (op.sb() << 8))) {
 #pragma unroll
@@ -853,6 +877,20 @@ __global__ __launch_bounds__(256) void k_small(cpx<T> *__restrict__ state, int n
             for (uint32_t p = tid; p < N / 4; p += nt) {
                 const uint32_t b = ins0(ins0(p, lo), hi) | (1u << q0);
                 const uint32_t i1 = b | (1u << q1);
+                const cpx<T> t = s[b];
+                s[b] = s[i1];
+                s[i1] = t;
+            }
+            break;
+        }
+        case SOP_CCX: {  // q0, q1 = controls, q2 = target
+            const int q2 = op.q2;
+            int lo = q0 < q1 ? q0 : q1, mid = q0 < q1 ? q1 : q0, hi = q2;
+            if (hi < mid) { const int t = hi; hi = mid; mid = t; }
+            if (mid < lo) { const int t = mid; mid = lo; lo = t; }
+            for (uint32_t p = tid; p < N / 8; p += nt) {
+                const uint32_t b = ins0(ins0(ins0(p, lo), mid), hi) | (1u << q0) | (1u << q1);
+                const uint32_t i1 = b | (1u << q2);
                 const cpx<T> t = s[b];
                 s[b] = s[i1];
                 s[i1] = t;
@@ -1022,6 +1060,20 @@ __device__ __forceinline__ void small_apply(cpx<T> *s, uint32_t N, const SmallOp
         for (uint32_t p = tid; p < N / 4; p += nt) {
             const uint32_t b = ins0(ins0(p, lo), hi) | (1u << q0);
             const uint32_t i1 = b | (1u << q1);
+            const cpx<T> t = s[b];
+            s[b] = s[i1];
+            s[i1] = t;
+        }
+        break;
+    }
+    case SOP_CCX: {  // q0, q1 = controls, q2 = target
+        const int q2 = op.q2;
+        int lo = q0 < q1 ? q0 : q1, mid = q0 < q1 ? q1 : q0, hi = q2;
+        if (hi < mid) { const int t = hi; hi = mid; mid = t; }
+        if (mid < lo) { const int t = mid; mid = lo; lo = t; }
+        for (uint32_t p = tid; p < N / 8; p += nt) {
+            const uint32_t b = ins0(ins0(ins0(p, lo), mid), hi) | (1u << q0) | (1u << q1);
+            const uint32_t i1 = b | (1u << q2);
             const cpx<T> t = s[b];
             s[b] = s[i1];
             s[i1] = t;

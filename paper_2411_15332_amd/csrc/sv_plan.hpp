@@ -67,6 +67,9 @@ enum OpCode : uint8_t {
     OP_DENSE1RI = 22,  // a 2x2 whose entries are each real or imaginary, on register bit a:
                        // diag(i^g0, i^g1) R diag(1, i^bt) with R real (payload r00 r01 r10
                        // r11), g0 = bit 0 of b, g1 = bit 1, bt = bit 2 (f untouched)
+    OP_CCX = 23,       // swap the pairs of register bit a in the slots j with
+                       // (j & b) == data byte 0 (register controls), in the threads where
+                       // the bits of sources sa, sb (0xFF: none) equal bits 0, 1 of data byte 1
 };
 
 constexpr uint8_t kNoSource = 0xFF;
@@ -153,13 +156,15 @@ enum SmallCode : uint8_t {
     SOP_CX = 8,       // q0 = control, q1 = target
     SOP_SWAP = 9,     // q0, q1
     SOP_SCALE = 10,   // data (1 real)
+    SOP_CCX = 11,     // q0, q1 = controls, q2 = target
 };
 
 struct SmallOp {      // 16 bytes
     uint8_t code;
     uint8_t q0;
     uint8_t q1;
-    uint8_t pad[5];
+    uint8_t q2;       // SOP_CCX: target
+    uint8_t pad[4];
     uint64_t data;
 };
 static_assert(sizeof(SmallOp) == 16, "SmallOp layout");

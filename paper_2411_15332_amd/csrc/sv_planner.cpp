@@ -31,12 +31,16 @@ static inline uint64_t bit(int q) { return 1ull << q; }
 
 static bool is_angled(int kind) {
     return kind == SV_GATE_RX || kind == SV_GATE_RY || kind == SV_GATE_RZ ||
-           kind == SV_GATE_P || kind == SV_GATE_CPHASE;
+           kind == SV_GATE_P || kind == SV_GATE_CPHASE || kind == SV_GATE_CRZ ||
+           kind == SV_GATE_RZZ || kind == SV_GATE_CU1;
 }
 static bool is_2q(int kind) {
     return kind == SV_GATE_CNOT || kind == SV_GATE_CZ || kind == SV_GATE_SWAP ||
-           kind == SV_GATE_CPHASE || kind == SV_GATE_U2;
+           kind == SV_GATE_CPHASE || kind == SV_GATE_U2 || kind == SV_GATE_CY ||
+           kind == SV_GATE_ISWAP || kind == SV_GATE_DCX || kind == SV_GATE_CRZ ||
+           kind == SV_GATE_RZZ || kind == SV_GATE_CU1;
 }
+static bool is_3q(int kind) { return kind == SV_GATE_CCX || kind == SV_GATE_CSWAP; }
 // Reals a matrix gate reads from the parameter table (0: not a matrix gate).
 static size_t matrix_reals(int kind) {
     return kind == SV_GATE_U1 ? 8 : kind == SV_GATE_U2 ? 32 : 0;
@@ -57,6 +61,15 @@ bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params
             if (g.index >= N) {
                 snprintf(buf, sizeof buf, "gate %zu: MARK index %llu >= 2^%d", i,
                          (unsigned long long)g.index, n);
+                err = buf;
+                return false;
+            }
+        } else if (is_3q(g.kind)) {
+            const int64_t q2 = (int64_t)g.index;
+            if (g.q0 < 0 || g.q0 >= n || g.q1 < 0 || g.q1 >= n || g.index >= (uint64_t)n ||
+                g.q0 == g.q1 || g.q0 == q2 || g.q1 == q2) {
+                snprintf(buf, sizeof buf, "gate %zu: qubits (%d, %d, %lld) invalid for n = %d", i,
+                         g.q0, g.q1, (long long)q2, n);
                 err = buf;
                 return false;
             }
@@ -124,7 +137,12 @@ CGate classify(const sv_gate &g, int n, int src) {
     case SV_GATE_CZ: case SV_GATE_CPHASE: c.cls = G_D2; break;
     case SV_GATE_SWAP: c.cls = G_SWAP; break;
     case SV_GATE_MARK: c.cls = G_MARK; c.index = g.index; break;
-    default: c.cls = G_NOP; break;
+    case SV_GATE_CCX: c.cls = G_CCX; c.q2 = (int)g.index; break;
+    default:
+        // the composite kinds (CY ... CSWAP) are lowered before planning
+        if (g.kind >= SV_GATE_CY) throw std::logic_error("gate kind reached the planner unlowered");
+        c.cls = G_NOP;
+        break;
     }
     switch (c.cls) {
     case G_D1: c.diag = true; c.support = bit(c.q0); break;
@@ -135,6 +153,7 @@ CGate classify(const sv_gate &g, int n, int src) {
     case G_CX: c.support = bit(c.q0) | bit(c.q1); c.qneed = c.rneed = bit(c.q1); break;
     case G_SWAP: c.support = c.qneed = bit(c.q0) | bit(c.q1); break;
     case G_DENSE2: c.support = c.qneed = c.rneed = bit(c.q0) | bit(c.q1); break;
+    case G_CCX: c.support = bit(c.q0) | bit(c.q1) | bit(c.q2); c.qneed = c.rneed = bit(c.q2); break;
     default: break;
     }
     return c;
@@ -991,6 +1010,39 @@ struct PassCtx {
             if (c.inv) compose(t.p, Factor{FK_X, false, -1}, PC_A, true);
             break;
         }
+        case G_CCX: {
+            // Toffoli as a monomial: swap the target's register pairs where
+            // both controls hold 1. Register controls select slots; thread
+            // and tile-base controls give a per-thread condition.
+            flush(src_of(g.q2).p);
+            for (int cq : {g.q0, g.q1}) {
+                const Src c = src_of(cq);
+                if (c.reg) flush_nondiag(c.p);
+            }
+            const Src t = src_of(g.q2);   // flushes may relabel: read again
+            uint32_t cm = 0, cv = 0, uv = 0;
+            uint8_t us[2] = {kNoSource, kNoSource};
+            int nu = 0;
+            for (int cq : {g.q0, g.q1}) {
+                const Src c = src_of(cq);
+                const uint32_t val = 1u ^ (uint32_t)c.inv;   // physical bit of logical 1
+                if (c.reg) {
+                    cm |= 1u << c.p;
+                    cv |= val << c.p;
+                } else {
+                    us[nu] = c.code;
+                    uv |= val << nu;
+                    ++nu;
+                }
+            }
+            HostOp &o = emit(OP_CCX);
+            o.hdr.a = (uint8_t)t.p;
+            o.hdr.b = (uint8_t)cm;
+            o.hdr.sa = us[0];
+            o.hdr.sb = us[1];
+            o.hdr.data = cv | (uv << 8);
+            break;
+        }
         case G_DENSE2: {
             // a 4x4 on register bits 1 (q0) and 0 (q1)
             const int l0 = label_of[g.q0], l1 = label_of[g.q1];
@@ -1087,6 +1139,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             case G_X: so.code = SOP_X; break;
             case G_Y: so.code = SOP_Y; break;
             case G_CX: so.code = SOP_CX; break;
+            case G_CCX: so.code = SOP_CCX; so.q2 = (uint8_t)g.q2; break;
             case G_SWAP: so.code = SOP_SWAP; break;
             case G_H: so.code = SOP_DENSE1; so.data = cblock(CK_HMAT, 8); break;
             case G_DENSE1: so.code = SOP_DENSE1; so.data = cblock(CK_DENSE1, 8); break;

@@ -20,12 +20,13 @@ namespace sv {
 //   DENSE1  general 2x2
 //   DENSE2  general 4x4 (matrix gate U2)
 enum GClass : uint8_t {
-    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1, G_DENSE2
+    G_NOP = 0, G_D1, G_D2, G_MARK, G_X, G_Y, G_CX, G_SWAP, G_H, G_DENSE1, G_DENSE2, G_CCX
 };
 
 struct CGate {
     GClass cls = G_NOP;
     int q0 = -1, q1 = -1;   // 2-qubit: q0 is the high local bit (CX: control)
+    int q2 = -1;            // CCX: target (q0, q1 controls)
     int src = -1;           // index in the caller's gate list
     uint64_t index = 0;     // MARK basis index
     uint64_t support = 0;   // qubit mask the gate acts on

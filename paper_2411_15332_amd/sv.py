@@ -22,8 +22,10 @@ SV_C64, SV_C128 = 1, 2
 GATE_KIND = {
     "I": 0, "X": 1, "Y": 2, "Z": 3, "H": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "RX": 9, "RY": 10, "RZ": 11, "P": 12, "CNOT": 13, "CZ": 14, "SWAP": 15,
-    "CPHASE": 16, "MARK": 17, "U1": 18, "U2": 19,
+    "CPHASE": 16, "MARK": 17, "U1": 18, "U2": 19, "CY": 20, "ISWAP": 21, "DCX": 22,
+    "CRZ": 23, "RZZ": 24, "CU1": 25, "CCX": 26, "CSWAP": 27,
 }
+THREE_QUBIT_KINDS = ("CCX", "CSWAP")
 
 OPT_FUSE, OPT_MIN_LOW_QUBITS, OPT_MAX_DENSE, OPT_ON_DEMAND_H, OPT_SMALL_PATH, OPT_PROFILE, OPT_REMAP = \
     1, 2, 3, 4, 5, 6, 7
@@ -94,10 +96,12 @@ def last_error() -> str:
 
 
 def gate_array(gates: Sequence) -> np.ndarray:
-    """Gate records (objects with name, q0, q1, angle, param, index) -> sv_gate[]."""
+    """Gate records (objects with name, q0, q1, angle, param, index and, for
+    CCX / CSWAP, q2) -> sv_gate[] (a 3-qubit gate's q2 goes in `index`)."""
     arr = np.zeros(len(gates), dtype=GATE_DTYPE)
     for i, g in enumerate(gates):
-        arr[i] = (GATE_KIND[g.name], g.q0, g.q1, g.param, g.angle, g.index)
+        idx = g.q2 if g.name in THREE_QUBIT_KINDS else g.index
+        arr[i] = (GATE_KIND[g.name], g.q0, g.q1, g.param, g.angle, idx)
     return arr
 
 
@@ -247,7 +251,7 @@ LAYOUT_DTYPE = np.dtype([("thr_goff", "<u8", (10,)), ("reg_goff", "<u8", (6,)),
 assert LAYOUT_DTYPE.itemsize == 256
 OP_DTYPE = np.dtype([("code", "u1"), ("a", "u1"), ("b", "u1"), ("sa", "u1"), ("sb", "u1"),
                      ("pad", "u1", (3,)), ("data", "<u8"), ("payload", "<f8", (8,))])
-SOP_DTYPE = np.dtype([("code", "u1"), ("q0", "u1"), ("q1", "u1"), ("pad", "u1", (5,)),
+SOP_DTYPE = np.dtype([("code", "u1"), ("q0", "u1"), ("q1", "u1"), ("q2", "u1"), ("pad", "u1", (4,)),
                       ("data", "<u8")])
 assert PASS_DTYPE.itemsize == 96 and LAYOUT_DTYPE.itemsize == 256
 assert OP_DTYPE.itemsize == 80 and SOP_DTYPE.itemsize == 16

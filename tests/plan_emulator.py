@@ -12,9 +12,10 @@ import numpy as np
 
 (OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
  OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU, OP_RPERM, OP_DENSE2,
- OP_CONT, OP_DENSE1RI) = range(1, 23)
+ OP_CONT, OP_DENSE1RI, OP_CCX) = range(1, 24)
 NO_SOURCE = 0xFF
-SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE = range(1, 11)
+(SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE,
+ SOP_CCX) = range(1, 12)
 SRC_REG, SRC_THR, SRC_TILE = 0, 1, 2
 PASS_GENERATE = 1
 
@@ -53,6 +54,11 @@ def run_small(plan, psi, n):
         elif code == SOP_CX:
             i0 = idx[(((idx >> q0) & 1) == 1) & (((idx >> q1) & 1) == 0)]
             i1 = i0 | (1 << q1)
+            psi[i0], psi[i1] = psi[i1].copy(), psi[i0].copy()
+        elif code == SOP_CCX:
+            q2 = int(op["q2"])
+            i0 = idx[(((idx >> q0) & 1) == 1) & (((idx >> q1) & 1) == 1) & (((idx >> q2) & 1) == 0)]
+            i1 = i0 | (1 << q2)
             psi[i0], psi[i1] = psi[i1].copy(), psi[i0].copy()
         elif code == SOP_SWAP:
             a = idx[(((idx >> q0) & 1) == 1) & (((idx >> q1) & 1) == 0)]
@@ -258,6 +264,18 @@ def run_plan(plan, psi, n):
                 cb = src_bit(sa).astype(bool)
                 x0, x1 = a[:, :, lo], a[:, :, hi]
                 a[:, :, lo], a[:, :, hi] = np.where(cb, x1, x0), np.where(cb, x0, x1)
+            elif code == OP_CCX:
+                cm, cv, uv = ob, data & 0xFF, (data >> 8) & 3
+                assert cv & ~cm == 0
+                on = np.ones((tiles, NT, 1), dtype=bool)
+                if sa != NO_SOURCE:
+                    on &= src_bit(sa) == (uv & 1)
+                if sb != NO_SOURCE:
+                    on &= src_bit(sb) == (uv >> 1)
+                lo = [j for j in range(NR) if not (j >> oa) & 1 and (j & cm) == cv]
+                hi = [j | (1 << oa) for j in lo]
+                x0, x1 = a[:, :, lo].copy(), a[:, :, hi].copy()
+                a[:, :, lo], a[:, :, hi] = np.where(on, x1, x0), np.where(on, x0, x1)
             elif code == OP_MARK:
                 hit = (base == data) & (t_idx == (sa | (sb << 8))) & (j_idx == oa)
                 a = np.where(hit, -a, a)

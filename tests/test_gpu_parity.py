@@ -338,3 +338,37 @@ def test_matrix_gates_at_scale(P, dtype):
     ref = O.simulate(n, mixed, params)
     got, st = run(P, n, mixed, dtype, params=params[None, :])
     assert maxdiff(got, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [9, 20])
+def test_table1_gates(P, n, dtype):
+    """Table 1 additions: composite gates lowered on the host (CRZ, RZZ, CU1
+    with parameters, so derived angle columns, different per batch entry) and
+    CCX as a monomial pass op, on a small (n = 9) and a tiled (n = 20) state."""
+    gates, params = synth.table1_circuit(n, 90 + n)
+    rng = np.random.default_rng(n)
+    batch = 3
+    table = np.stack([params] + [rng.uniform(-math.pi, math.pi, params.size) for _ in range(batch - 1)])
+    got, _ = run(P, n, gates, dtype, params=table, batch=batch)
+    for b in range(batch):
+        ref = O.simulate(n, gates, table[b])
+        assert maxdiff(got[b], ref) <= TOL[dtype], b
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_ccx_control_placements(P, dtype):
+    """CCX with controls on register, thread and tile-base bits (n = 20)."""
+    n = 20
+    rng = np.random.default_rng(6)
+    gates = [synth.Gate("H", q) for q in range(n)]
+    for t in (6, 7, 8, 9, 12):
+        for c0, c1 in ((0, 1), (2, 18), (19, 16), (10, 3), (11, 13)):
+            if t in (c0, c1):
+                continue
+            gates.append(synth.Gate("RX", t, -1, float(rng.uniform(0, 6))))
+            gates.append(synth.Gate("CCX", c0, c1, 0.0, -1, 0, t))
+            gates.append(synth.Gate("RZ", c0, -1, float(rng.uniform(0, 6))))
+    ref = O.simulate(n, gates)
+    got, _ = run(P, n, gates, dtype)
+    assert maxdiff(got, ref) <= TOL[dtype]

@@ -49,6 +49,12 @@ def test_gate_record_layout():
     [synth.Gate("MARK", -1, -1, 0.0, -1, 1 << 12)],
     [synth.Gate("RY", 0, -1, 0.0, 5)],
     [synth.Gate("H", 0, -1, 0.0, 0)],
+    [synth.Gate("CCX", 0, 1, 0.0, -1, 0, 1)],       # target equals a control
+    [synth.Gate("CCX", 0, 1, 0.0, -1, 0, 12)],      # target out of range
+    [synth.Gate("CSWAP", 2, 2, 0.0, -1, 0, 3)],
+    [synth.Gate("CY", 4, 4)],
+    [synth.Gate("CRZ", 0, 1, 0.0, 3)],              # parameter not supplied
+    [synth.Gate("DCX", 0, 1, 0.0, 0)],              # takes no parameter
 ])
 def test_validation_rejects(bad):
     with pytest.raises(P.SVError) as e:
@@ -230,3 +236,40 @@ def test_matrix_gate_validation():
         P.debug_plan(12, [synth.Gate("U2", 0, 1, 0.0, -1)])   # matrix must come from params
     with pytest.raises(P.SVError):
         P.debug_plan(12, [synth.Gate("U2", 3, 3, 0.0, 0)], params=np.zeros(32))
+
+
+@pytest.mark.parametrize("n", [5, 12, 14, 16])
+def test_table1_gates_lowered_and_ccx(n):
+    gates, params = synth.table1_circuit(n, 70 + n)
+    psi0 = synth.random_state(n, 3)
+    ref = O.simulate(n, gates, params, psi0=psi0)
+    for dt in ("c128", "c64"):
+        got, plan = _emulate(n, gates, dt, psi0=psi0, params=params)
+        assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
+        if not plan["small"]:
+            codes = {int(o["code"]) for o in plan["ops"]}
+            assert 23 in codes   # CCX applied as a monomial op, not decomposed
+
+
+def test_ccx_control_placements():
+    """CCX with controls on every combination of register, thread and
+    tile-base bits: targets among the tile qubits, controls drawn from the
+    low (thread) bits, the others and the high (tile-base) bits."""
+    n = 15
+    rng = np.random.default_rng(5)
+    gates = [synth.Gate("H", q) for q in range(n)]
+    for t in (6, 7, 8, 9):
+        for c0, c1 in ((0, 1), (2, 13), (14, 12), (7 if t != 7 else 8, 3), (10, 11)):
+            if t in (c0, c1):
+                continue
+            gates.append(synth.Gate("RX", t, -1, float(rng.uniform(0, 6))))
+            gates.append(synth.Gate("CCX", c0, c1, 0.0, -1, 0, t))
+            gates.append(synth.Gate("RZ", c0, -1, float(rng.uniform(0, 6))))
+    psi0 = synth.random_state(n, 4)
+    ref = O.simulate(n, gates, psi0=psi0)
+    for dt in ("c128", "c64"):
+        got, plan = _emulate(n, gates, dt, psi0=psi0)
+        assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
+        ccx = [o for o in plan["ops"] if int(o["code"]) == 23]
+        kinds = {(int(o["b"]) != 0, int(o["sa"]) != 0xFF, int(o["sb"]) != 0xFF) for o in ccx}
+        assert len(kinds) >= 2, kinds
