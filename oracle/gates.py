@@ -31,6 +31,9 @@ _FIXED_1Q = {
     "Y": [[0, -1j], [1j, 0]],
     "Z": [[1, 0], [0, -1]],
     "H": [[SQRT1_2, SQRT1_2], [SQRT1_2, -SQRT1_2]],
+    # square root of X and its inverse
+    "SX": [[0.5 + 0.5j, 0.5 - 0.5j], [0.5 - 0.5j, 0.5 + 0.5j]],
+    "SXDG": [[0.5 - 0.5j, 0.5 + 0.5j], [0.5 + 0.5j, 0.5 - 0.5j]],
     "S": [[1, 0], [0, 1j]],
     "SDG": [[1, 0], [0, -1j]],
     "T": [[1, 0], [0, cmath.exp(1j * math.pi / 4)]],
@@ -47,6 +50,12 @@ _FIXED_2Q = {
     "ISWAP": [[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]],
     # double CNOT: |x y> -> |y, x xor y> (CNOT q0 -> q1, then CNOT q1 -> q0)
     "DCX": [[1, 0, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1], [0, 1, 0, 0]],
+    # echoed cross-resonance: (X (x) I - Y (x) X) / sqrt 2
+    "ECR": [[0, 0, SQRT1_2, 1j * SQRT1_2], [0, 0, 1j * SQRT1_2, SQRT1_2],
+            [SQRT1_2, -1j * SQRT1_2, 0, 0], [-1j * SQRT1_2, SQRT1_2, 0, 0]],
+    # controlled H and controlled SX (q0 = control)
+    "CH": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, SQRT1_2, SQRT1_2], [0, 0, SQRT1_2, -SQRT1_2]],
+    "CSX": [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0.5 + 0.5j, 0.5 - 0.5j], [0, 0, 0.5 - 0.5j, 0.5 + 0.5j]],
 }
 
 # 3-qubit monomial gates (Table 1): local index (b_q0 << 2) | (b_q1 << 1) | b_q2.
@@ -90,10 +99,57 @@ def matrix(name: str, angle: float = 0.0) -> np.ndarray:
     if name == "RZZ":   # exp(-i angle Z (x) Z / 2)
         m, p = cmath.exp(-0.5j * angle), cmath.exp(0.5j * angle)
         return np.diag([m, p, p, m]).astype(np.complex128)
+    if name == "RXX":   # exp(-i angle X (x) X / 2)
+        return np.array([[c, 0, 0, -1j * s], [0, c, -1j * s, 0], [0, -1j * s, c, 0],
+                         [-1j * s, 0, 0, c]], dtype=np.complex128)
+    if name == "RYY":   # exp(-i angle Y (x) Y / 2)
+        return np.array([[c, 0, 0, 1j * s], [0, c, -1j * s, 0], [0, -1j * s, c, 0],
+                         [1j * s, 0, 0, c]], dtype=np.complex128)
+    if name == "RZX":   # exp(-i angle Z (x) X / 2): Z on q0, X on q1
+        return np.array([[c, -1j * s, 0, 0], [-1j * s, c, 0, 0], [0, 0, c, 1j * s],
+                         [0, 0, 1j * s, c]], dtype=np.complex128)
     raise ValueError(f"no matrix for gate {name!r}")
 
 
-TWO_QUBIT_ANGLED = ("CPHASE", "CU1", "CRZ", "RZZ")
+# Gates with several angles, read from the parameter vector at `param`:
+# R(theta, phi), U(theta, phi, lambda), CU3(theta, phi, lambda),
+# CU(theta, phi, lambda, gamma).
+MULTI_ANGLE = {"R": 2, "U": 3, "CU3": 3, "CU": 4}
+
+
+def _u3(theta: float, phi: float, lam: float) -> np.ndarray:
+    c, s = math.cos(theta / 2.0), math.sin(theta / 2.0)
+    return np.array([[c, -cmath.exp(1j * lam) * s],
+                     [cmath.exp(1j * phi) * s, cmath.exp(1j * (phi + lam)) * c]], dtype=np.complex128)
+
+
+def _controlled(u: np.ndarray) -> np.ndarray:
+    m = np.eye(4, dtype=np.complex128)
+    m[2:, 2:] = u
+    return m
+
+
+def angles_matrix(name: str, angles) -> np.ndarray:
+    """Matrix of a several-angle gate (MULTI_ANGLE) from its angles.
+    R(t, p) = exp(-i t (cos p X + sin p Y) / 2); U(t, p, l) =
+    [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]];
+    CU3 = controlled U; CU(t, p, l, g) = controlled e^{ig} U(t, p, l)."""
+    a = [float(x) for x in angles]
+    if name == "R":
+        t, ph = a
+        c, s = math.cos(t / 2.0), math.sin(t / 2.0)
+        return np.array([[c, -1j * cmath.exp(-1j * ph) * s], [-1j * cmath.exp(1j * ph) * s, c]],
+                        dtype=np.complex128)
+    if name == "U":
+        return _u3(*a)
+    if name == "CU3":
+        return _controlled(_u3(*a))
+    if name == "CU":
+        return _controlled(cmath.exp(1j * a[3]) * _u3(*a[:3]))
+    raise ValueError(f"{name!r} is not a several-angle gate")
+
+
+TWO_QUBIT_ANGLED = ("CPHASE", "CU1", "CRZ", "RZZ", "RXX", "RYY", "RZX", "CU3", "CU")
 
 
 def arity(name: str) -> int:

@@ -93,6 +93,21 @@ def _angle(g, params) -> float:
     return float(g.angle)
 
 
+def gate_matrix(g, params: Optional[np.ndarray] = None) -> np.ndarray:
+    """The 2x2, 4x4 or 8x8 matrix of one gate record (angles and matrices that
+    the gate reads from the parameter vector taken from ``params``)."""
+    if g.name in ("U1", "U2"):
+        if params is None or g.param < 0:
+            raise ValueError(f"{g.name} reads its matrix from the parameters")
+        return G.params_matrix(g.name, params, g.param)
+    if g.name in G.MULTI_ANGLE:
+        k = G.MULTI_ANGLE[g.name]
+        if params is None or g.param < 0 or g.param + k > len(params):
+            raise ValueError(f"{g.name} reads {k} angles from the parameters")
+        return G.angles_matrix(g.name, np.asarray(params, dtype=np.float64)[g.param: g.param + k])
+    return G.matrix(g.name, _angle(g, params))
+
+
 def encode(gates: Sequence, params: Optional[np.ndarray] = None):
     """Gate list -> flat arrays (kind, q0, q1, q2, mats[64], idx) for or_run."""
     ng = len(gates)
@@ -108,12 +123,7 @@ def encode(gates: Sequence, params: Optional[np.ndarray] = None):
             kind[k] = 3
             idx[k] = g.index
             continue
-        if g.name in ("U1", "U2"):
-            if params is None or g.param < 0:
-                raise ValueError(f"{g.name} reads its matrix from the parameters")
-            m = G.params_matrix(g.name, params, g.param)
-        else:
-            m = G.matrix(g.name, _angle(g, params))
+        m = gate_matrix(g, params)
         kind[k] = 4 if a == 3 else a
         q0[k] = g.q0
         q1[k] = g.q1
@@ -239,8 +249,7 @@ def monomial_amplitudes(n: int, gates: Sequence, indices: Sequence[int], initial
         if g.name == "MARK":
             amp = np.where(idx == np.int64(g.index), -amp, amp)
             continue
-        mat = (G.params_matrix(g.name, params, g.param) if g.name in ("U1", "U2")
-               else G.matrix(g.name, _angle(g, params)))
+        mat = gate_matrix(g, params)
         cols, vals = _row_nonzero(mat)
         if G.arity(g.name) == 1:
             r = (idx >> g.q0) & 1

@@ -97,6 +97,9 @@ def mtp_operator(n: int, gate, params: Optional[np.ndarray] = None) -> np.ndarra
         return np.diag(d)
     if gate.name in ("U1", "U2"):
         g = G.params_matrix(gate.name, params, gate.param)
+    elif gate.name in G.MULTI_ANGLE:
+        k = G.MULTI_ANGLE[gate.name]
+        g = G.angles_matrix(gate.name, params[gate.param: gate.param + k])
     else:
         ang = float(params[gate.param]) if gate.param >= 0 else gate.angle
         g = G.matrix(gate.name, ang)

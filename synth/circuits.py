@@ -37,10 +37,14 @@ class Gate(NamedTuple):
     q2: int = -1      # third qubit of CCX / CSWAP
 
 
-ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P", "U1")
+ONE_QUBIT = ("I", "X", "Y", "Z", "H", "S", "SDG", "T", "TDG", "RX", "RY", "RZ", "P", "U1",
+             "SX", "SXDG", "R", "U")
 # Table 1 two-qubit gates beyond the config mix: controlled Y, iSWAP, double
 # CNOT, controlled RZ, ZZ rotation and controlled phase (CU1 = CPHASE).
-TABLE1_2Q = ("CY", "ISWAP", "DCX", "CRZ", "RZZ", "CU1")
+TABLE1_2Q = ("CY", "ISWAP", "DCX", "CRZ", "RZZ", "CU1", "RXX", "RYY", "RZX", "ECR", "CH", "CSX",
+             "CU3", "CU")
+# Gates whose several angles come from the parameter vector at `param`.
+MULTI_ANGLE = {"R": 2, "U": 3, "CU3": 3, "CU": 4}
 TWO_QUBIT = ("CNOT", "CZ", "SWAP", "CPHASE", "U2") + TABLE1_2Q
 THREE_QUBIT = ("CCX", "CSWAP")
 # U1 / U2: a general 2x2 / 4x4 matrix taken from the parameter vector at
@@ -243,6 +247,13 @@ def all_kinds_circuit(n: int, seed: int):
                     gates.append(Gate(name, q, int((q + 1 + rng.integers(n - 1)) % n), 0.0, off))
                 else:
                     gates.append(Gate(name, q, -1, 0.0, off))
+            elif name in MULTI_ANGLE:
+                if name in TWO_QUBIT and n < 2:
+                    continue
+                off = len(params)
+                params.extend(rng.uniform(-math.pi, math.pi, MULTI_ANGLE[name]).tolist())
+                q1 = int((q + 1 + rng.integers(n - 1)) % n) if name in TWO_QUBIT else -1
+                gates.append(Gate(name, q, q1, 0.0, off))
             elif name in TWO_QUBIT:
                 if n < 2:
                     continue
@@ -261,22 +272,29 @@ def all_kinds_circuit(n: int, seed: int):
 
 
 def table1_circuit(n: int, seed: int, layers: int = 4):
-    """The Table 1 additions (CY, ISWAP, DCX, CRZ, RZZ, CU1, CCX, CSWAP), three
-    of each per layer at random distinct operands, between layers of RY on
-    every qubit. CRZ, RZZ and CU1 read their angles from the returned
-    parameter vector. Returns (gates, params)."""
+    """The Table 1 gates beyond the config mix (SX, SXDG, R, U and the
+    2- and 3-qubit ones of TABLE1_2Q and THREE_QUBIT), three of each per layer
+    at random distinct operands, between layers of RY on every qubit. The
+    angled ones read their angles from the returned parameter vector.
+    Returns (gates, params)."""
     rng = np.random.default_rng(seed)
     gates: List[Gate] = []
     params: List[float] = []
     for _ in range(layers):
         for q in range(n):
             gates.append(Gate("RY", q, -1, float(rng.uniform(0, 2 * math.pi))))
-        for name in TABLE1_2Q + THREE_QUBIT:
+        for name in ("SX", "SXDG", "R", "U") + TABLE1_2Q + THREE_QUBIT:
             for _ in range(3):
                 qs = [int(x) for x in rng.permutation(n)[:3]]
-                if name in ("CRZ", "RZZ", "CU1"):
+                q1 = qs[1] if name in TWO_QUBIT else -1
+                if name in MULTI_ANGLE:
+                    params.extend(rng.uniform(-math.pi, math.pi, MULTI_ANGLE[name]).tolist())
+                    gates.append(Gate(name, qs[0], q1, 0.0, len(params) - MULTI_ANGLE[name]))
+                elif name in ("CRZ", "RZZ", "CU1", "RXX", "RYY", "RZX"):
                     params.append(float(rng.uniform(-math.pi, math.pi)))
-                    gates.append(Gate(name, qs[0], qs[1], 0.0, len(params) - 1))
+                    gates.append(Gate(name, qs[0], q1, 0.0, len(params) - 1))
+                elif name in ("SX", "SXDG"):
+                    gates.append(Gate(name, qs[0]))
                 elif name in THREE_QUBIT:
                     gates.append(Gate(name, qs[0], qs[1], 0.0, -1, 0, qs[2]))
                 else:

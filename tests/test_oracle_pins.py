@@ -39,7 +39,8 @@ ANGLES = [0.0, 0.3, 1.7, math.pi, 4.9, -2.2]
                                   if n != "MARK" and n not in synth.MATRIX_GATES])
 def test_gate_unitary(name):
     for a in ANGLES:
-        m = G.matrix(name, a)
+        m = (G.angles_matrix(name, [a, 0.3 * a + 0.1, -0.7 * a, 0.2][:G.MULTI_ANGLE[name]])
+             if name in G.MULTI_ANGLE else G.matrix(name, a))
         assert np.allclose(m.conj().T @ m, np.eye(m.shape[0]), atol=1e-15)
 
 
@@ -113,8 +114,8 @@ def test_1q_embedding_is_paper_kron_order():
 def _all_single_gates(n, rng):
     out = []
     for name in synth.GATE_NAMES:
-        if name in synth.MATRIX_GATES:
-            continue   # pinned separately (test_matrix_gates_*)
+        if name in synth.MATRIX_GATES or name in synth.MULTI_ANGLE:
+            continue   # pinned separately (test_matrix_gates_*, test_multi_angle_gates_vs_kron)
         ar = G.arity(name)
         ang = float(rng.uniform(0, 2 * math.pi))
         if ar == 1:
@@ -573,3 +574,90 @@ def test_3q_embedding_vs_definition(n):
         lc = (((col >> a) & 1) << 2) | (((col >> b) & 1) << 1) | ((col >> c) & 1)
         ref = np.where(same, g[lr, lc], 0.0)
         assert np.allclose(U, ref, atol=1e-15)
+
+
+# ------------------------------------------------ remaining Table 1 gates (f2)
+
+def _ry(t):
+    return scipy.linalg.expm(-0.5j * t * PY)
+
+
+def test_table1_sparsity_of_two_qubit_gates():
+    """Table 1: RXX, RYY, RZX and ECR are 50% zeros (two non-zeros per row);
+    CH, CSX, CU and CU3 are 62.5% zeros."""
+    rng = np.random.default_rng(1)
+    for name in ("RXX", "RYY", "RZX", "ECR", "CH", "CSX", "CU", "CU3"):
+        if name in G.MULTI_ANGLE:
+            m = G.angles_matrix(name, rng.uniform(0.2, 1.2, G.MULTI_ANGLE[name]))
+        else:
+            m = G.matrix(name, 0.7)
+        zeros = np.count_nonzero(np.abs(m) < 1e-15) / m.size
+        assert zeros == (0.5 if name in ("RXX", "RYY", "RZX", "ECR") else 0.625), name
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.4, -2.2, math.pi])
+def test_two_qubit_rotations_are_exponentials(theta):
+    for name, a, b in (("RXX", PX, PX), ("RYY", PY, PY), ("RZX", PZ, PX)):
+        ref = scipy.linalg.expm(-0.5j * theta * np.kron(a, b))
+        assert np.allclose(G.matrix(name, theta), ref, atol=1e-14), name
+
+
+def test_sx_r_u_definitions():
+    H = np.array([[1, 1], [1, -1]], dtype=complex) / math.sqrt(2)
+    S = np.diag([1, 1j])
+    sx = G.matrix("SX")
+    assert np.allclose(sx @ sx, PX, atol=1e-15)
+    assert np.allclose(sx, H @ S @ H, atol=1e-15)
+    assert np.allclose(G.matrix("SXDG"), sx.conj().T, atol=0)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        t, p, l = rng.uniform(-3, 3, 3)
+        ref_r = scipy.linalg.expm(-0.5j * t * (math.cos(p) * PX + math.sin(p) * PY))
+        assert np.allclose(G.angles_matrix("R", [t, p]), ref_r, atol=1e-14)
+        # U(t, p, l) = e^{i(p+l)/2} RZ(p) RY(t) RZ(l)
+        rz = lambda a: scipy.linalg.expm(-0.5j * a * PZ)
+        ref_u = np.exp(0.5j * (p + l)) * rz(p) @ _ry(t) @ rz(l)
+        assert np.allclose(G.angles_matrix("U", [t, p, l]), ref_u, atol=1e-14)
+        # textbook special cases
+        assert np.allclose(G.angles_matrix("U", [t, -math.pi / 2, math.pi / 2]),
+                           scipy.linalg.expm(-0.5j * t * PX), atol=1e-14)
+        assert np.allclose(G.angles_matrix("R", [t, math.pi / 2]), _ry(t), atol=1e-14)
+
+
+def test_controlled_and_echoed_gates():
+    I2 = np.eye(2, dtype=complex)
+    P0, P1 = np.diag([1, 0]).astype(complex), np.diag([0, 1]).astype(complex)
+    H = (PX + PZ) / math.sqrt(2)
+    # ECR = (X (x) I - Y (x) X) / sqrt 2 = RZX(-pi/4) (X (x) I) RZX(pi/4)
+    ecr = (np.kron(PX, I2) - np.kron(PY, PX)) / math.sqrt(2)
+    rzx = lambda t: scipy.linalg.expm(-0.5j * t * np.kron(PZ, PX))
+    assert np.allclose(G.matrix("ECR"), ecr, atol=1e-15)
+    assert np.allclose(G.matrix("ECR"), rzx(-math.pi / 4) @ np.kron(PX, I2) @ rzx(math.pi / 4), atol=1e-14)
+    # controlled gates: |0><0| (x) I + |1><1| (x) V
+    ctrl = lambda v: np.kron(P0, I2) + np.kron(P1, v)
+    assert np.allclose(G.matrix("CH"), ctrl(H), atol=1e-15)
+    csx = G.matrix("CSX")
+    assert np.allclose(csx @ csx, ctrl(PX), atol=1e-15)
+    rng = np.random.default_rng(3)
+    t, p, l, g = rng.uniform(-3, 3, 4)
+    u = G.angles_matrix("U", [t, p, l])
+    assert np.allclose(G.angles_matrix("CU3", [t, p, l]), ctrl(u), atol=0)
+    assert np.allclose(G.angles_matrix("CU", [t, p, l, g]), ctrl(np.exp(1j * g) * u), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_multi_angle_gates_vs_kron(n):
+    """R, U, CU3, CU (angles from the parameter vector) through the C oracle
+    against the Kronecker operator, at every operand placement."""
+    rng = np.random.default_rng(40 + n)
+    for name, k in synth.MULTI_ANGLE.items():
+        params = rng.uniform(-math.pi, math.pi, k + 2)
+        if G.arity(name) == 1:
+            gs = [synth.Gate(name, q, -1, 0.0, 1) for q in range(n)]
+        else:
+            gs = [synth.Gate(name, a, b, 0.0, 2) for a in range(n) for b in range(n) if a != b]
+        for g in gs:
+            psi0 = synth.random_state(n, int(rng.integers(1 << 30)))
+            ref = K.mtp_operator(n, g, params) @ psi0
+            got = O.simulate(n, [g], params, psi0=psi0)
+            assert np.max(np.abs(got - ref)) < 1e-14, g
