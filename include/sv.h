@@ -65,7 +65,14 @@ typedef enum sv_dtype { SV_C64 = 1, SV_C128 = 2 } sv_dtype;
  *   CY = controlled Y (q0 control), ISWAP = [[1,0,0,0],[0,0,i,0],[0,i,0,0],[0,0,0,1]],
  *   DCX: |x y> -> |y, x xor y> (CNOT q0 -> q1, then CNOT q1 -> q0),
  *   CRZ(t) = diag(1, 1, e^{-it/2}, e^{it/2}), RZZ(t) = exp(-i t Z(x)Z / 2),
- *   CU1(t) = CPHASE(t);
+ *   CU1(t) = CPHASE(t), RXX(t) / RYY(t) = exp(-i t X(x)X / 2) / exp(-i t Y(x)Y / 2),
+ *   RZX(t) = exp(-i t Z(x)X / 2) (Z on q0), ECR = (X(x)I - Y(x)X)/sqrt2,
+ *   CH, CSX = controlled H, controlled SX (q0 control);
+ *   SX = [[1+i,1-i],[1-i,1+i]]/2, SXDG = SX^dagger;
+ *   several angles read from params[b][param ...] (param >= 0 required):
+ *   R(t, p) = exp(-i t (cos p X + sin p Y) / 2),
+ *   U(t, p, l) = [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]],
+ *   CU3(t, p, l) = controlled U, CU(t, p, l, g) = controlled e^{ig} U(t, p, l);
  *   3-qubit monomials, third qubit q2 = sv_gate.index, local index
  *   (b_q0 << 2) | (b_q1 << 1) | b_q2: CCX (Toffoli: q0, q1 controls, q2
  *   target) and CSWAP (Fredkin: q0 control, q1 and q2 exchanged). */
@@ -77,14 +84,18 @@ typedef enum sv_gate_kind {
     SV_GATE_MARK = 17, SV_GATE_U1 = 18, SV_GATE_U2 = 19,
     SV_GATE_CY = 20, SV_GATE_ISWAP = 21, SV_GATE_DCX = 22, SV_GATE_CRZ = 23,
     SV_GATE_RZZ = 24, SV_GATE_CU1 = 25, SV_GATE_CCX = 26, SV_GATE_CSWAP = 27,
-    SV_GATE_KIND_COUNT = 28
+    SV_GATE_SX = 28, SV_GATE_SXDG = 29, SV_GATE_R = 30, SV_GATE_U = 31,
+    SV_GATE_RXX = 32, SV_GATE_RYY = 33, SV_GATE_RZX = 34, SV_GATE_ECR = 35,
+    SV_GATE_CH = 36, SV_GATE_CSX = 37, SV_GATE_CU3 = 38, SV_GATE_CU = 39,
+    SV_GATE_KIND_COUNT = 40
 } sv_gate_kind;
 
 /* One gate, 32 bytes. q1 = -1 for 1-qubit gates and MARK; q0 = -1 for MARK.
  * param = -1: use `angle`; param >= 0: the angle is params[b][param] for batch
  * entry b (see sv_apply_circuit); U1 / U2 require param >= 0 (the first of
- * their 8 / 32 matrix reals). index: basis index of MARK, third qubit of CCX
- * and CSWAP, else ignored. */
+ * their 8 / 32 matrix reals), and so do R, U, CU3, CU (the first of their
+ * 2 / 3 / 3 / 4 angles). index: basis index of MARK, third qubit of CCX and
+ * CSWAP, else ignored. */
 typedef struct sv_gate {
     int32_t kind;
     int32_t q0;

@@ -9,6 +9,17 @@
 //   RZZ(a, b; x)    = CPHASE(a, b; -2x) P_b(x) RZ_a(x)
 //   CU1(a, b; x)    = CPHASE(a, b; x)
 //   CSWAP(c; a, b)  = CNOT(b, a) CCX(c, a -> b) CNOT(b, a)
+//   SX = H S H, SXDG = H SDG H
+//   R(t, p)         = RZ(p) RX(t) RZ(-p)
+//   U(t, p, l)      = P(p) RY(t) P(l)
+//   RXX(x)          = (H (x) H) RZZ(x) (H (x) H)
+//   RYY(x)          = (S (x) S) RXX(x) (SDG (x) SDG)
+//   RZX(x)          = (I (x) H) RZZ(x) (I (x) H)
+//   ECR             = RZX(-pi/4) X_a RZX(pi/4)
+//   CH(c, t)        = RY_t(pi/4) CZ RY_t(-pi/4)
+//   CSX(c, t)       = H_t CPHASE(pi/2) H_t
+//   CU3(t, p, l)    = CPHASE(p) CRY(t) CPHASE(l), CRY(t) = CNOT RY(-t/2) CNOT RY(t/2)
+//   CU(t, p, l, g)  = P_c(g) CU3(t, p, l)
 // (operators written right to left: the rightmost is applied first). CCX is
 // not lowered: it is a monomial the pass kernel applies directly.
 #pragma once

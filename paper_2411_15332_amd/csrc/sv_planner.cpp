@@ -32,13 +32,28 @@ static inline uint64_t bit(int q) { return 1ull << q; }
 static bool is_angled(int kind) {
     return kind == SV_GATE_RX || kind == SV_GATE_RY || kind == SV_GATE_RZ ||
            kind == SV_GATE_P || kind == SV_GATE_CPHASE || kind == SV_GATE_CRZ ||
-           kind == SV_GATE_RZZ || kind == SV_GATE_CU1;
+           kind == SV_GATE_RZZ || kind == SV_GATE_CU1 || kind == SV_GATE_RXX ||
+           kind == SV_GATE_RYY || kind == SV_GATE_RZX;
 }
 static bool is_2q(int kind) {
-    return kind == SV_GATE_CNOT || kind == SV_GATE_CZ || kind == SV_GATE_SWAP ||
-           kind == SV_GATE_CPHASE || kind == SV_GATE_U2 || kind == SV_GATE_CY ||
-           kind == SV_GATE_ISWAP || kind == SV_GATE_DCX || kind == SV_GATE_CRZ ||
-           kind == SV_GATE_RZZ || kind == SV_GATE_CU1;
+    switch (kind) {
+    case SV_GATE_CNOT: case SV_GATE_CZ: case SV_GATE_SWAP: case SV_GATE_CPHASE: case SV_GATE_U2:
+    case SV_GATE_CY: case SV_GATE_ISWAP: case SV_GATE_DCX: case SV_GATE_CRZ: case SV_GATE_RZZ:
+    case SV_GATE_CU1: case SV_GATE_RXX: case SV_GATE_RYY: case SV_GATE_RZX: case SV_GATE_ECR:
+    case SV_GATE_CH: case SV_GATE_CSX: case SV_GATE_CU3: case SV_GATE_CU:
+        return true;
+    default:
+        return false;
+    }
+}
+// Angles a several-angle gate reads from the parameter table (0: none).
+static size_t multi_angles(int kind) {
+    switch (kind) {
+    case SV_GATE_R: return 2;
+    case SV_GATE_U: case SV_GATE_CU3: return 3;
+    case SV_GATE_CU: return 4;
+    default: return 0;
+    }
 }
 static bool is_3q(int kind) { return kind == SV_GATE_CCX || kind == SV_GATE_CSWAP; }
 // Reals a matrix gate reads from the parameter table (0: not a matrix gate).
@@ -90,6 +105,13 @@ bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params
                 snprintf(buf, sizeof buf,
                          "gate %zu: U%d needs %zu matrix reals from parameter %d (n_params = %zu)",
                          i, g.kind == SV_GATE_U1 ? 1 : 2, matrix_reals(g.kind), g.param, n_params);
+                err = buf;
+                return false;
+            }
+        } else if (multi_angles(g.kind)) {
+            if (g.param < 0 || !params_given || (size_t)g.param + multi_angles(g.kind) > n_params) {
+                snprintf(buf, sizeof buf, "gate %zu: kind %d needs %zu angles from parameter %d (n_params = %zu)",
+                         i, g.kind, multi_angles(g.kind), g.param, n_params);
                 err = buf;
                 return false;
             }

@@ -23,7 +23,8 @@ GATE_KIND = {
     "I": 0, "X": 1, "Y": 2, "Z": 3, "H": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "RX": 9, "RY": 10, "RZ": 11, "P": 12, "CNOT": 13, "CZ": 14, "SWAP": 15,
     "CPHASE": 16, "MARK": 17, "U1": 18, "U2": 19, "CY": 20, "ISWAP": 21, "DCX": 22,
-    "CRZ": 23, "RZZ": 24, "CU1": 25, "CCX": 26, "CSWAP": 27,
+    "CRZ": 23, "RZZ": 24, "CU1": 25, "CCX": 26, "CSWAP": 27, "SX": 28, "SXDG": 29, "R": 30,
+    "U": 31, "RXX": 32, "RYY": 33, "RZX": 34, "ECR": 35, "CH": 36, "CSX": 37, "CU3": 38, "CU": 39,
 }
 THREE_QUBIT_KINDS = ("CCX", "CSWAP")
 
