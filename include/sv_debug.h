@@ -16,7 +16,7 @@ extern "C" {
 /* Build the pass plan that sv_apply_circuit would run for `gates` on an n-qubit
  * state of `dtype`, without touching a GPU, and serialize it into `out`.
  * opts (may be NULL for defaults): [0] fuse (0/1), [1] lowest qubits kept in a
- * tile (3..7), [2] dense gates per pass, [3] on-demand Hadamards (0/1),
+ * tile (3..7, or 0 for the planner's choice), [2] dense gates per pass, [3] on-demand Hadamards (0/1),
  * [4] state is a known basis state (0/1), [5] that basis index, [6] small-path
  * mode (1 or 2), [7] qubit remapping (0/1) — the meanings of the matching
  * SV_OPT_* options.
@@ -26,7 +26,8 @@ extern "C" {
  *   Hadamards, [8] gates applied, [9] k, [10] w, [11] R, [12] swizzle width,
  *   [13..17] byte offsets of the pass, layout, op, small-op and constant
  *   arrays, [18] algorithmic HBM bytes, [19] relabelled permutation gates,
- *   [20] passes that only put qubits back on their own bits,
+ *   [20] passes that only put qubits back on their own bits, [21] contiguous
+ *   low qubits of every tile (opts[1], or the planner's choice when it is 0),
  * followed by those arrays (constants in the state's precision: FP64 for
  * SV_C128, FP32 for SV_C64; batch entry 0).
  * Returns the number of bytes the dump needs (nothing is written when `out`

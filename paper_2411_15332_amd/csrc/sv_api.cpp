@@ -57,7 +57,8 @@ PlanOptions plan_options(const sv_state_s *s) {
         o.small_max = kSmallMaxQubitsC64;
         o.ud_max = kMaxUdTerms;
     }
-    o.c = s->min_low;
+    o.c = s->min_low ? s->min_low : 6;
+    o.auto_low = s->min_low == 0;
     o.w_max = s->dt == SV_C128 ? kThreadBitsC128 : kThreadBitsC64;
     o.fuse = s->fuse;
     o.max_dense = s->max_dense;
@@ -378,7 +379,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
         if (!hit) {
             s->plan_valid = false;
             lower_gates(gates, n_gates, n_params, s->plan_low);
-            s->plan = build_plan(s->n, s->plan_low.gates.data(), s->plan_low.gates.size(), po);
+            s->plan = build_plan_auto(s->n, s->plan_low.gates.data(), s->plan_low.gates.size(), po);
             s->plan_gates.assign(gates, gates + n_gates);
             s->plan_nparams = n_params;
             s->plan_opts = po;
@@ -493,7 +494,8 @@ sv_status sv_set_option(sv_state s, int option, int64_t value) {
             s->fuse = value != 0;
             return SV_OK;
         case SV_OPT_MIN_LOW_QUBITS:
-            if (value < 3 || value > 7) return fail(SV_EINVAL, "SV_OPT_MIN_LOW_QUBITS takes 3..7");
+            if (value != 0 && (value < 3 || value > 7))
+                return fail(SV_EINVAL, "SV_OPT_MIN_LOW_QUBITS takes 0 (automatic) or 3..7");
             s->min_low = (int)value;
             return SV_OK;
         case SV_OPT_MAX_DENSE:
@@ -732,7 +734,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     }
     gates = low.gates.data();
     n_gates = low.gates.size();
-    Plan p = build_plan(n, gates, n_gates, po);
+    Plan p = build_plan_auto(n, gates, n_gates, po);
     const size_t real_bytes = dtype == SV_C64 ? 4 : 8;  // constants in the state's precision
     const Layout L = plan_sections(p, 1, real_bytes);
     const size_t header = 256;
@@ -764,6 +766,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     h[18] = plan_hbm_bytes(p, n, dtype == SV_C128 ? 16 : 8);
     h[19] = p.n_relabel;
     h[20] = p.n_restore;
+    h[21] = p.low;
     serialize_plan(p, L, gates, params, n_params, 1, dtype == SV_C64, o + header);
     return (int64_t)total;
 }

@@ -61,7 +61,7 @@ struct sv_state_s {
 
     // options
     bool fuse = true;
-    int min_low = 6;
+    int min_low = 0;      // 0: chosen per circuit (build_plan_auto)
     int max_dense = 1 << 20;
     bool gen_h = true;
     int small_mode = 1;

@@ -1117,15 +1117,32 @@ struct PassCtx {
 
 bool same_options(const PlanOptions &a, const PlanOptions &b) {
     return a.R == b.R && a.v == b.v && a.m == b.m && a.c == b.c && a.w_max == b.w_max &&
-           a.fuse == b.fuse && a.remap == b.remap && a.max_dense == b.max_dense &&
+           a.fuse == b.fuse && a.remap == b.remap && a.max_dense == b.max_dense && a.auto_low == b.auto_low &&
            a.gen_h == b.gen_h && a.basis_known == b.basis_known &&
            (!a.basis_known || a.basis_j == b.basis_j) && a.ud_max == b.ud_max &&
            a.small_max == b.small_max && a.small_mode == b.small_mode;
 }
 
+Plan build_plan_auto(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt) {
+    Plan best = build_plan(n, gates, n_gates, opt);
+    if (!opt.auto_low || best.small) return best;
+    // Relative cost: a pass weighted by the streaming efficiency of its
+    // contiguous runs (about 3% per halving of the run, measured), plus the
+    // LDS exchanges (about 3% of a pass each, measured).
+    auto cost = [](const Plan &p) {
+        return (double)p.passes.size() * (1.0 + 0.03 * (6 - p.low)) + 0.03 * (double)p.n_exch;
+    };
+    PlanOptions o4 = opt;
+    o4.c = 4;
+    Plan alt = build_plan(n, gates, n_gates, o4);
+    if (cost(alt) < cost(best)) best = std::move(alt);
+    return best;
+}
+
 Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt) {
     Plan P;
     P.n = n;
+    P.low = opt.c;
     std::vector<CGate> cg;
     cg.reserve(n_gates);
     std::vector<int> kinds(n_gates);

@@ -102,6 +102,7 @@ struct PlanOptions {
     int v = 0;            // vector bits (complex64: 1, label 0 in register 0 for 16-byte I/O)
     int m = 3;            // swizzle width (3 for 16-byte slots, 4 for 8-byte)
     int c = 6;            // lowest qubits always in the tile
+    bool auto_low = false;  // build_plan_auto: choose c among 6 and 4
     int w_max = 8;        // thread bits of a full workgroup
     bool fuse = true;     // false: one pass per gate
     bool remap = true;    // permute the tile's address bits at each store (see build_plan)
@@ -128,6 +129,7 @@ struct Plan {
     int64_t gates_applied = 0;
     int64_t n_relabel = 0;             // permutation gates absorbed into layouts
     int64_t n_restore = 0;             // passes that only put qubits back on their own bits
+    int low = 0;                       // contiguous low qubits of every tile (c)
 };
 
 // Structural classification of a validated gate (independent of the angle).
@@ -139,6 +141,10 @@ bool validate_gates(int n, const sv_gate *gates, size_t n_gates, size_t n_params
 
 // Build the plan. Gates must be validated.
 Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt);
+// With opt.auto_low, the plan of lower estimated cost among c = 6 and c = 4
+// contiguous low qubits (fewer, fuller passes against shorter contiguous HBM
+// runs); otherwise build_plan.
+Plan build_plan_auto(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &opt);
 
 // Tiled path: write [batch][ops.size()] DevOp records with their payloads.
 void materialize_ops(const Plan &p, const sv_gate *gates, const double *params,

@@ -281,7 +281,8 @@ def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] 
     h = buf[:256].view(np.int64)
     out = {"small": bool(h[0]), "k": int(h[9]), "w": int(h[10]), "R": int(h[11]), "m": int(h[12]),
            "exchanges": int(h[6]), "generated_h": int(h[7]), "gates": int(h[8]),
-           "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19]), "restores": int(h[20])}
+           "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19]), "restores": int(h[20]),
+           "min_low": int(h[21])}
 
     def take(off, count, dt_):
         return buf[off: off + count * dt_.itemsize].view(dt_).copy()

@@ -273,3 +273,17 @@ def test_ccx_control_placements():
         ccx = [o for o in plan["ops"] if int(o["code"]) == 23]
         kinds = {(int(o["b"]) != 0, int(o["sa"]) != 0xFF, int(o["sb"]) != 0xFF) for o in ccx}
         assert len(kinds) >= 2, kinds
+
+
+@pytest.mark.parametrize("n,seed", [(13, 0), (15, 1)])
+def test_automatic_low_qubits(n, seed):
+    """min_low = 0: the planner picks 6 or 4 contiguous low qubits by its
+    cost estimate; the plan it picks is as correct as either."""
+    gates = synth.random_circuit(n, 8, seed)
+    ref = O.simulate(n, gates)
+    for dt in ("c128", "c64"):
+        got, plan = _emulate(n, gates, dt, min_low=0)
+        assert plan["min_low"] in (4, 6)
+        fixed = [len(P.debug_plan(n, gates, dtype=dt, min_low=c)["passes"]) for c in (6, 4)]
+        assert len(plan["passes"]) == fixed[0 if plan["min_low"] == 6 else 1]
+        assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
