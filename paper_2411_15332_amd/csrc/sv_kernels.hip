@@ -710,7 +710,13 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
                 break;
             }
             case OP_H: {
-                SV_SWITCH_A(op.a(), r_h<PA>(a))
+                // consecutive Hadamards on different register bits share one
+                // record: one dispatch for the whole run
+#pragma unroll
+                for (int bb = 0; bb < R; ++bb)
+                    if ((op.a() >> bb) & 1u) {
+                        SV_SWITCH_A(bb, r_h<PA>(a))
+                    }
                 break;
             }
             case OP_X: {

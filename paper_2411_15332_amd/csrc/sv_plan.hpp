@@ -47,7 +47,8 @@ enum OpCode : uint8_t {
     OP_D2RU = 7,     // amp *= f e[u][bit a of j], u = bit of source sa, f = 1; payload e[2][2]
     OP_DENSE1 = 8,   // a 2x2 on register bit a; payload g00 g01 g10 g11; with b = 1 the
                      // matrix is first multiplied by f, and f = 1 (b = 0: f untouched)
-    OP_H = 9,        // unscaled Hadamard butterfly (x0 + x1, x0 - x1) on register bit a
+    OP_H = 9,        // unscaled Hadamard butterflies (x0 + x1, x0 - x1) on every register
+                     // bit set in mask a
     OP_X = 10,       // swap the pairs of register bit a
     OP_CXR = 11,     // swap the pairs of register bit a where register bit b is 1
     OP_CXU = 12,     // swap the pairs of register bit a when the bit of source sa is 1

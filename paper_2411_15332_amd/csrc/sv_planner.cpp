@@ -305,6 +305,7 @@ struct PassCtx {
     int cur_layout = -1;            // pass-relative index of the materialized state, -1: not yet
     Pending pend[kLayoutRegBits];
     bool f_used = false;
+    int op_floor = 0;   // first op of the current pass (records never merge across passes)
     int h_count = 0;
     int first_payload = -1;
     // Pending uniform diagonals (thread / tile-base bits), merged into one
@@ -678,8 +679,15 @@ struct PassCtx {
                 ++P.n_relabel;
             }
         } else if (pd.cls == PC_H) {
-            HostOp &o = emit(OP_H);
-            o.hdr.a = (uint8_t)p;
+            // joins the preceding Hadamard record when that one is the last
+            // op emitted and holds other register bits
+            if (!P.ops.empty() && (int)P.ops.size() > op_floor && P.ops.back().hdr.code == OP_H &&
+                !((P.ops.back().hdr.a >> p) & 1)) {
+                P.ops.back().hdr.a |= (uint8_t)(1u << p);
+            } else {
+                HostOp &o = emit(OP_H);
+                o.hdr.a = (uint8_t)(1u << p);
+            }
             ++h_count;
         } else {
             emit_ud();
@@ -1292,6 +1300,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         dp.op_begin = (int)P.ops.size();
         dp.layout_begin = (int)P.layouts.size();
         X.layout_begin = dp.layout_begin;
+        X.op_floor = dp.op_begin;
 
         std::vector<int> rem = taken;
         const uint64_t U = X.U_labels();

@@ -244,9 +244,12 @@ def run_plan(plan, psi, n):
                 x0, x1 = a[:, :, lo], a[:, :, hi]
                 a[:, :, lo], a[:, :, hi] = m[0, 0] * x0 + m[0, 1] * x1, m[1, 0] * x0 + m[1, 1] * x1
             elif code == OP_H:
-                lo, hi = pairs(oa)
-                x0, x1 = a[:, :, lo], a[:, :, hi]
-                a[:, :, lo], a[:, :, hi] = x0 + x1, x0 - x1
+                assert oa and oa < (1 << R)
+                for bit in range(R):
+                    if (oa >> bit) & 1:
+                        lo, hi = pairs(bit)
+                        x0, x1 = a[:, :, lo], a[:, :, hi]
+                        a[:, :, lo], a[:, :, hi] = x0 + x1, x0 - x1
             elif code == OP_X:
                 lo, hi = pairs(oa)
                 a[:, :, lo], a[:, :, hi] = a[:, :, hi].copy(), a[:, :, lo].copy()
