@@ -374,16 +374,30 @@ struct PassTraits<float> {
 // thread bits at or above the workgroup's width are zero, so the loop runs
 // over every possible bit without a data-dependent trip count.
 template <int W>
-__device__ __forceinline__ void thr_part(const DevLayout &L, int tid, uint64_t &g, uint32_t &s) {
-    g = L.goff_xor;
+__device__ __forceinline__ uint64_t thr_goff(const DevLayout &L, int tid) {
+    uint64_t e[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b) e[b] = L.thr_goff[b];
+    // every entry in registers before the per-bit selects: the scalar loads
+    // issue together instead of one after another inside per-bit branches
+#pragma unroll
+    for (int b = 0; b < W; ++b) asm volatile("" : : "s"(e[b]));
+    uint64_t g = L.goff_xor;
+#pragma unroll
+    for (int b = 0; b < W; ++b) g ^= ((tid >> b) & 1) ? e[b] : 0ull;
+    return g;
+}
+template <int W>
+__device__ __forceinline__ uint32_t thr_slot(const DevLayout &L, int tid) {
+    uint32_t e[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b) e[b] = L.thr_slot[b];
+#pragma unroll
+    for (int b = 0; b < W; ++b) asm volatile("" : : "s"(e[b]));
     uint32_t sl = L.slot_xor;
 #pragma unroll
-    for (int b = 0; b < W; ++b) {
-        const bool on = (tid >> b) & 1;
-        g ^= on ? L.thr_goff[b] : 0ull;
-        sl ^= on ? L.thr_slot[b] : 0u;
-    }
-    s = sl;
+    for (int b = 0; b < W; ++b) sl ^= ((tid >> b) & 1) ? e[b] : 0u;
+    return sl;
 }
 
 // Slot index with bit `lo`-position removed (lo = 2^b - 1): the half-tile
@@ -492,11 +506,16 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
     // the tile number with zeros inserted at the tile qubits (ascending).
     // (q[] is read as aligned 32-bit words: scalar loads, not byte loads)
     const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
+    uint32_t qv[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qv[i] = qw[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));   // one batch of scalar loads
     uint64_t base = xcd_tile(blockIdx.x, gridDim.x);
 #pragma unroll
     for (int l = 0; l < 28; ++l) {
         if (l >= k) break;
-        const int b = (qw[l >> 2] >> (8 * (l & 3))) & 0xFF;
+        const int b = (qv[l >> 2] >> (8 * (l & 3))) & 0xFF;
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
 
@@ -506,10 +525,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         // accumulated along a Gray-code walk over the register bits (the
         // parts occupy disjoint bits), so only R per-bit offsets stay live.
         const DevLayout &L = LB[0];
-        uint64_t gthr;
-        uint32_t sdummy;
-        thr_part<W>(L, tid, gthr, sdummy);
-        uint64_t idx = (base | gthr) ^ L.reg_goff_xor;
+        uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
         if (P.flags & PASS_GENERATE) {
             // On-demand Hadamard-layer amplitudes of H^M |j>:
             // 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M.
@@ -555,10 +571,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
             case OP_EXCH: {
                 const uint32_t lo = (1u << op.sb()) - 1u;
                 const DevLayout &Lw = LB[op.a()], &Lr = LB[op.b()];
-                uint64_t gd;
-                uint32_t tw, tr, gw[R], gr[R];
-                thr_part<W>(Lw, tid, gd, tw);
-                thr_part<W>(Lr, tid, gd, tr);
+                uint32_t tw = thr_slot<W>(Lw, tid), tr = thr_slot<W>(Lr, tid), gw[R], gr[R];
                 tw = drop_bit(tw, lo) << SH;
                 tr = drop_bit(tr, lo) << SH;
 #pragma unroll
@@ -774,10 +787,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
     if (P.flags & PASS_SYNC_STORE) __syncthreads();
     {
         const DevLayout &L = LB[P.store_layout];
-        uint64_t gthr;
-        uint32_t sdummy;
-        thr_part<W>(L, tid, gthr, sdummy);
-        uint64_t idx = (base | gthr) ^ L.reg_goff_xor;
+        uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
         if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
 #pragma unroll
             for (int i = 0; i < NR / 2; ++i) {
