@@ -1737,7 +1737,7 @@ void materialize_consts(const Plan &p, const sv_gate *gates, const double *param
             for (uint64_t i = 0; i < p.cstride; ++i) o[i] = (float)row[i];
         } else {
             double *o = static_cast<double *>(out) + (size_t)b * p.cstride;
-            std::memcpy(o, row.data(), p.cstride * sizeof(double));
+            if (p.cstride) std::memcpy(o, row.data(), p.cstride * sizeof(double));
         }
     }
 }
