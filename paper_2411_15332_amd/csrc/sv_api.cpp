@@ -653,17 +653,36 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
             seg.clear();
             return r;
         };
-        for (size_t i = n_gates; i-- > 0;) {
-            const sv_gate &g = gates[i];
-            if (g.param >= 0) {
-                st = flush();
-                if (st != SV_OK) return st;
-                const int pauli = g.kind == SV_GATE_RX ? 1 : g.kind == SV_GATE_RY ? 2 : 3;
-                SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, g.q0, pauli, s->d_red, s->d_grad,
-                                                  n_params, (uint64_t)g.param, s->stream),
+        // A run of consecutive parametric rotations on distinct qubits shares
+        // one state pair: the generator of each (a Pauli on its own qubit)
+        // commutes with the run's later rotations, so <lambda_k| P_k |psi_k>
+        // equals <lambda| P_k |psi> taken after the run's last gate, and the
+        // whole run is then undone in one segment.
+        size_t i = n_gates;
+        while (i > 0) {
+            const sv_gate &g = gates[i - 1];
+            if (g.param < 0) {
+                seg.push_back(inverse(g));
+                --i;
+                continue;
+            }
+            size_t j = i;   // the run is gates[j .. i - 1]
+            uint64_t used = 0;
+            while (j > 0 && gates[j - 1].param >= 0 && !((used >> gates[j - 1].q0) & 1)) {
+                used |= 1ull << gates[j - 1].q0;
+                --j;
+            }
+            st = flush();
+            if (st != SV_OK) return st;
+            for (size_t k = i; k-- > j;) {
+                const sv_gate &gk = gates[k];
+                const int pauli = gk.kind == SV_GATE_RX ? 1 : gk.kind == SV_GATE_RY ? 2 : 3;
+                SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, gk.q0, pauli, s->d_red, s->d_grad,
+                                                  n_params, (uint64_t)gk.param, s->stream),
                        "launch pauli_ip");
             }
-            seg.push_back(inverse(g));
+            for (size_t k = i; k-- > j;) seg.push_back(inverse(gates[k]));
+            i = j;
         }
         st = flush();
         if (st != SV_OK) return st;
