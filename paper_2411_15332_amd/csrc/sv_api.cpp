@@ -586,10 +586,12 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
         st = ensure_device_buf(reinterpret_cast<void **>(&s->d_grad), &s->d_grad_cap,
                                ngrad * sizeof(double), "hipMalloc(grad)");
         if (st != SV_OK) return st;
-        const size_t np = reduce_partials_size(s->n) * (size_t)B + (size_t)B;
+        // partials: reductions (batch + 1 rows) and up to kMaxIpTerms fused inner products
+        const size_t np = reduce_partials_size(s->n) * (size_t)B * kMaxIpTerms + (size_t)B;
         st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap, np * sizeof(double),
                                "hipMalloc(reduce)");
         if (st != SV_OK) return st;
+        const int chunk_bits = pauli_ip_multi_chunk_bits(s->n);
         char *psi = static_cast<char *>(s->d_work);
         char *lam = psi + (size_t)B * state_bytes;
         const int dt = (int)s->dt;
@@ -674,13 +676,34 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
             }
             st = flush();
             if (st != SV_OK) return st;
+            // one read of psi and lambda for every Z term and every X / Y term
+            // whose partner amplitude lies in the same reduction chunk; the
+            // rest one term at a time
+            IpTerms terms{};
+            IpOffsets offs{};
+            int nt = 0;
             for (size_t k = i; k-- > j;) {
                 const sv_gate &gk = gates[k];
                 const int pauli = gk.kind == SV_GATE_RX ? 1 : gk.kind == SV_GATE_RY ? 2 : 3;
-                SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, gk.q0, pauli, s->d_red, s->d_grad,
-                                                  n_params, (uint64_t)gk.param, s->stream),
-                       "launch pauli_ip");
+                if (pauli == 3 || gk.q0 < chunk_bits) {
+                    terms.q[nt] = (uint8_t)gk.q0;
+                    terms.pauli[nt] = (uint8_t)pauli;
+                    offs.off[nt] = (uint64_t)gk.param;
+                    if (++nt == kMaxIpTerms) {
+                        SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad,
+                                                     n_params, s->stream),
+                               "launch pauli_ip_multi");
+                        nt = 0;
+                    }
+                } else {
+                    SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, gk.q0, pauli, s->d_red, s->d_grad,
+                                                      n_params, (uint64_t)gk.param, s->stream),
+                           "launch pauli_ip");
+                }
             }
+            SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad, n_params,
+                                         s->stream),
+                   "launch pauli_ip_multi");
             for (size_t k = i; k-- > j;) seg.push_back(inverse(gates[k]));
             i = j;
         }

@@ -1197,6 +1197,93 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_partial(const cpx<T> *
     if (threadIdx.x == 0) part[(uint64_t)blockIdx.y * nblk + blockIdx.x] = sum;
 }
 
+// Block sum with a fixed order (wave butterflies, then the waves in order);
+// the result is valid in thread 0 only, and the scratch is free on return.
+__device__ __forceinline__ double block_sum_t0(double v, double *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    __syncthreads();
+    return s;
+}
+
+// Several Im <lambda_b | P_t | psi_b> in one read of psi and lambda. The
+// chunk is walked in sub-chunks of kIpSub amplitudes staged in LDS: Z terms
+// take any qubit; X and Y terms take qubits whose partner i ^ 2^q lies in the
+// same sub-chunk (the host sends the others to k_pauli_ip_partial). Stage 1
+// per (chunk, batch entry); part[(b * nt + t) * nblk + chunk].
+constexpr int kIpSub = 4096;
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__restrict__ psi,
+                                                                const cpx<T> *__restrict__ lam,
+                                                                uint64_t n_amps, uint64_t chunk,
+                                                                IpTerms terms, int nt,
+                                                                double *__restrict__ part, int nblk) {
+    __shared__ cpx<T> buf[kIpSub];
+    __shared__ double sh[kRedThreads / 64];
+    const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
+    const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
+    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+    const uint32_t sub = chunk < (uint64_t)kIpSub ? (uint32_t)chunk : (uint32_t)kIpSub;
+    double acc[kMaxIpTerms];
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kMaxIpTerms; ++t) acc[t] = 0.0;
+    for (uint64_t s0 = lo; s0 < lo + chunk; s0 += sub) {
+        __syncthreads();   // the previous sub-chunk's reads are done
+        for (uint32_t j = threadIdx.x; j < sub; j += kRedThreads) buf[j] = ps[s0 + j];
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < sub; j += kRedThreads) {
+            const uint64_t i = s0 + j;
+            const cpx<T> l = lm[i], v = buf[j];
+            const double lx = (double)l.x, ly = (double)l.y;
+            const double base = lx * (double)v.y - ly * (double)v.x;   // Im(conj(l) v)
+#pragma clang loop unroll(full)
+            for (int t = 0; t < kMaxIpTerms; ++t) {
+                if (t >= nt) continue;   // predicated: acc stays in registers
+                const uint32_t m = 1u << terms.q[t];
+                if (terms.pauli[t] == 3) {
+                    acc[t] += ((i >> terms.q[t]) & 1) ? -base : base;
+                } else {
+                    const cpx<T> w = buf[j ^ m];
+                    double px = (double)w.x, py = (double)w.y;
+                    if (terms.pauli[t] == 2) {   // Y: (-i, +i) psi_{i ^ m} for bit 0, 1
+                        const double sgn = (j & m) ? 1.0 : -1.0;
+                        px = -sgn * (double)w.y;
+                        py = sgn * (double)w.x;
+                    }
+                    acc[t] += lx * py - ly * px;
+                }
+            }
+        }
+    }
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kMaxIpTerms; ++t) {
+        if (t >= nt) continue;
+        const double sum = block_sum_t0(acc[t], sh);
+        if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
+    }
+}
+
+// Stage 2: one block per batch entry adds each term's chunk sums, in order,
+// to out[b * out_stride + off[t]] (terms sharing a parameter add in turn).
+__global__ __launch_bounds__(kRedThreads) void k_accumulate_multi(const double *__restrict__ part, int nblk,
+                                                                  int nt, double *__restrict__ out,
+                                                                  uint64_t out_stride, IpOffsets offs) {
+    __shared__ double sh[kRedThreads / 64];
+    const uint64_t b = blockIdx.x;
+    for (int t = 0; t < nt; ++t) {
+        const double *p = part + (b * nt + t) * nblk;
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += p[i];
+        const double s = block_sum_t0(acc, sh);
+        if (threadIdx.x == 0) out[b * out_stride + offs.off[t]] += s;
+    }
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_accumulate_final(const double *__restrict__ part,
                                                                   int nblk, double *__restrict__ out,
                                                                   uint64_t out_stride, uint64_t out_off) {
@@ -1344,6 +1431,38 @@ hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, 
     hipLaunchKernelGGL(k_accumulate_final, dim3(batch), dim3(kRedThreads), 0, st,
                        (const double *)d_partials, nblk, d_grad, grad_stride, grad_off);
     return hipGetLastError();
+}
+
+hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n, int batch,
+                                 const IpTerms &terms, const IpOffsets &offs, int nt, double *d_partials,
+                                 double *d_grad, uint64_t grad_stride, hipStream_t st) {
+    if (nt <= 0) return hipSuccess;
+    if (nt > kMaxIpTerms) return hipErrorInvalidValue;
+    const uint64_t N = 1ull << n;
+    const int nblk = reduce_blocks(n);
+    const uint64_t chunk = N / (uint64_t)nblk;
+    const uint64_t sub = chunk < (uint64_t)kIpSub ? chunk : (uint64_t)kIpSub;
+    for (int t = 0; t < nt; ++t)   // partners must stay inside the staged sub-chunk
+        if (terms.q[t] >= n || (terms.pauli[t] != 3 && (1ull << terms.q[t]) >= sub)) return hipErrorInvalidValue;
+    if (dt == 2)
+        hipLaunchKernelGGL(k_pauli_ip_multi<double>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
+                           (const cpx<double> *)psi, (const cpx<double> *)lam, N, chunk, terms, nt, d_partials,
+                           nblk);
+    else
+        hipLaunchKernelGGL(k_pauli_ip_multi<float>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
+                           (const cpx<float> *)psi, (const cpx<float> *)lam, N, chunk, terms, nt, d_partials,
+                           nblk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_accumulate_multi, dim3(batch), dim3(kRedThreads), 0, st, (const double *)d_partials,
+                       nblk, nt, d_grad, grad_stride, offs);
+    return hipGetLastError();
+}
+
+int pauli_ip_multi_chunk_bits(int n) {
+    const uint64_t chunk = (1ull << n) / (uint64_t)reduce_blocks(n);
+    const uint64_t sub = chunk < (uint64_t)kIpSub ? chunk : (uint64_t)kIpSub;
+    return 63 - __builtin_clzll(sub);
 }
 
 hipError_t launch_small_jobs(int dt, const SmallJob *d_jobs, int n_jobs, const SmallOp *d_ops,

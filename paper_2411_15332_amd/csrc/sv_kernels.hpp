@@ -58,6 +58,24 @@ hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, in
 
 // grad[b * grad_stride + grad_off] += Im <lam_b | P_q | psi_b>, P = X (1), Y (2), Z (3),
 // accumulated in FP64 in a fixed order. d_partials: reduce_partials_size(n) * batch.
+// Several (qubit, Pauli) terms of one adjoint run, by value in the launch.
+constexpr int kMaxIpTerms = 24;
+struct IpTerms {
+    uint8_t q[kMaxIpTerms];
+    uint8_t pauli[kMaxIpTerms];   // 1 = X, 2 = Y, 3 = Z
+};
+struct IpOffsets {
+    uint64_t off[kMaxIpTerms];    // gradient index of each term within a batch row
+};
+// grad[b * grad_stride + off[t]] += Im <lambda_b | P_t | psi_b> for nt <= kMaxIpTerms
+// terms in one read of the states. Z terms take any qubit; X and Y terms need
+// qubit < pauli_ip_multi_chunk_bits(n) (hipErrorInvalidValue otherwise).
+// d_partials holds batch * nt * reduce_partials_size(n) doubles.
+hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n, int batch,
+                                 const IpTerms &terms, const IpOffsets &offs, int nt, double *d_partials,
+                                 double *d_grad, uint64_t grad_stride, hipStream_t st);
+int pauli_ip_multi_chunk_bits(int n);
+
 hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, int n, int batch,
                                       int q, int pauli, double *d_partials, double *d_grad,
                                       uint64_t grad_stride, uint64_t grad_off, hipStream_t st);
