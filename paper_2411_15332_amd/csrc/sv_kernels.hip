@@ -277,11 +277,6 @@ __device__ __forceinline__ void r_d1_quarter(cpx<T> (&a)[NR], cpx<T> d, uint32_t
         if (((j >> P) & 1) == V && (((uint32_t)j >> pb) & 1u) == xb) cmul_ip(a[j], d);
 }
 
-template <int PA, int PB, typename T, int NR>
-__device__ __forceinline__ void r_d2_regreg(cpx<T> (&a)[NR], const cpx<T> (&d)[4]) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) cmul_ip(a[j], d[(((j >> PA) & 1) << 1) | ((j >> PB) & 1)]);
-}
 
 template <typename T, int NR>
 __device__ __forceinline__ void r_mul_all(cpx<T> (&a)[NR], cpx<T> d) {
@@ -681,21 +676,6 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
             case OP_APPLYF: {
                 r_mul_all(a, f);
                 f = mk<T>((T)1, (T)0);
-                break;
-            }
-            case OP_D2RR: {
-                const cpx<T> d[4] = {cmul(f, plc<T>(op, 0)), cmul(f, plc<T>(op, 1)),
-                                     cmul(f, plc<T>(op, 2)), cmul(f, plc<T>(op, 3))};
-                f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a(), SV_SWITCH_B(op.b(), if constexpr (PA != PB) r_d2_regreg<PA, PB>(a, d)))
-                break;
-            }
-            case OP_D2RU: {
-                const int u = src_bit(op.sa(), tid, base);
-                const cpx<T> e0 = cmul(f, u ? plc<T>(op, 2) : plc<T>(op, 0));
-                const cpx<T> e1 = cmul(f, u ? plc<T>(op, 3) : plc<T>(op, 1));
-                f = mk<T>((T)1, (T)0);
-                SV_SWITCH_A(op.a(), r_d1_reg<PA>(a, e0, e1))
                 break;
             }
             case OP_DENSE1: {

@@ -43,8 +43,7 @@ enum OpCode : uint8_t {
                      // (s2 != 0xFF); (s1, s2) of terms 0..3 in the bytes of `data`,
                      // of term 4 in (sa, sb); payload C, r_0 .. r_{a-1}
     OP_APPLYF = 5,   // amp *= f for every slot; f = 1
-    OP_D2RR = 6,     // amp *= f d[(bit a of j << 1) | bit b of j], f = 1; payload d[4]
-    OP_D2RU = 7,     // amp *= f e[u][bit a of j], u = bit of source sa, f = 1; payload e[2][2]
+    // 4, 6 and 7: not used
     OP_DENSE1 = 8,   // a 2x2 on register bit a; payload g00 g01 g10 g11; with b = 1 the
                      // matrix is first multiplied by f, and f = 1 (b = 0: f untouched)
     OP_H = 9,        // unscaled Hadamard butterflies (x0 + x1, x0 - x1) on every register

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-(OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, OP_D2RR, OP_D2RU, OP_DENSE1, OP_H, OP_X,
+(OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, _UNUSED6, _UNUSED7, OP_DENSE1, OP_H, OP_X,
  OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU, OP_RPERM, OP_DENSE2,
  OP_CONT, OP_DENSE1RI, OP_CCX) = range(1, 24)
 NO_SOURCE = 0xFF
@@ -221,12 +221,6 @@ def run_plan(plan, psi, n):
                 a = np.where(sel, a * d[0], a)
             elif code == OP_APPLYF:
                 a = a * f
-                f = np.ones_like(f)
-            elif code == OP_D2RR:
-                a = a * f * d[:4][(((j_idx >> oa) & 1) << 1) | ((j_idx >> ob) & 1)]
-                f = np.ones_like(f)
-            elif code == OP_D2RU:
-                a = a * f * d[:4][(src_bit(sa) << 1) | ((j_idx >> oa) & 1)]
                 f = np.ones_like(f)
             elif code == OP_DENSE1:
                 lo, hi = pairs(oa)
