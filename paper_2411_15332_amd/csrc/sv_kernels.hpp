@@ -16,7 +16,9 @@ namespace sv {
 //   complex128: R = 4, W = 8: 4096 amplitudes, 32 KiB of LDS per workgroup
 //   complex64:  R = 5, W = 8: 8192 amplitudes, 32 KiB of LDS per workgroup
 // (512-thread workgroups with 8192-amplitude complex128 tiles save passes but
-// ran each pass about twice as long on gfx950.)
+// ran each pass about twice as long on gfx950. Complex128 with R = 5, W = 7
+// saves exchanges but needs 174 VGPRs: measured 3% slower on a depth-100
+// random circuit and 16% slower on latency-bound Grover passes.)
 constexpr int kRegBitsC128 = 4;
 constexpr int kThreadBitsC128 = 8;
 constexpr int kRegBitsC64 = 5;
