@@ -203,6 +203,10 @@ def capacity_section(P, synth):
     return out
 
 
+SECTIONS = {"serving": serving_section, "differentiation": adjoint_section,
+            "grover_n20": grover_section, "capacity": capacity_section}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +220,8 @@ def main():
                     help="skip the serving, differentiation and Grover measurements")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of the state's size (counter calibration)")
+    ap.add_argument("--section", choices=sorted(SECTIONS),
+                    help="run only this secondary measurement and print its JSON (for profiling)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -228,6 +234,10 @@ def main():
     import paper_2411_15332_amd as P
 
     torch.cuda.set_device(0)
+    if args.section:
+        res = SECTIONS[args.section](P, synth)
+        print(json.dumps({"section": args.section, "result": res}), flush=True)
+        return
     n = args.n
     gates = synth.random_circuit(n, args.depth, args.seed)
     arr = P.gate_array(gates)
