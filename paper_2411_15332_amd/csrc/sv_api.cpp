@@ -677,11 +677,13 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
             st = flush();
             if (st != SV_OK) return st;
             // one read of psi and lambda for every Z term and every X / Y term
-            // whose partner amplitude lies in the same reduction chunk; the
-            // rest one term at a time
+            // whose partner amplitude lies in the same 2^12-amplitude chunk;
+            // one more read per group of up to 8 X / Y terms on higher qubits
+            // (the run's qubits are distinct, so a group is up to 8 qubits)
             IpTerms terms{};
             IpOffsets offs{};
             int nt = 0;
+            std::vector<size_t> high;   // gate indices of X / Y terms on qubits >= chunk_bits
             for (size_t k = i; k-- > j;) {
                 const sv_gate &gk = gates[k];
                 const int pauli = gk.kind == SV_GATE_RX ? 1 : gk.kind == SV_GATE_RY ? 2 : 3;
@@ -696,14 +698,35 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
                         nt = 0;
                     }
                 } else {
-                    SV_HIP(launch_pauli_ip_accumulate(dt, psi, lam, s->n, B, gk.q0, pauli, s->d_red, s->d_grad,
-                                                      n_params, (uint64_t)gk.param, s->stream),
-                           "launch pauli_ip");
+                    high.push_back(k);
                 }
             }
             SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad, n_params,
                                          s->stream),
                    "launch pauli_ip_multi");
+            for (size_t g0 = 0; g0 < high.size(); g0 += 8) {
+                const size_t g1 = std::min(high.size(), g0 + 8);
+                std::vector<int> qs;
+                for (size_t t = g0; t < g1; ++t) qs.push_back(gates[high[t]].q0);
+                std::sort(qs.begin(), qs.end());
+                IpHiMap map{};
+                map.h = (int32_t)qs.size();
+                for (int k = 0; k < map.h; ++k) map.hq[k] = (uint8_t)qs[(size_t)k];
+                IpTerms ht{};
+                IpOffsets ho{};
+                int hn = 0;
+                for (size_t t = g0; t < g1; ++t) {
+                    const sv_gate &gk = gates[high[t]];
+                    const int pos = (int)(std::lower_bound(qs.begin(), qs.end(), (int)gk.q0) - qs.begin());
+                    ht.q[hn] = (uint8_t)(12 - map.h + pos);   // the qubit's bit inside the staged sub-chunk
+                    ht.pauli[hn] = (uint8_t)(gk.kind == SV_GATE_RX ? 1 : 2);
+                    ho.off[hn] = (uint64_t)gk.param;
+                    ++hn;
+                }
+                SV_HIP(launch_pauli_ip_hi(dt, psi, lam, s->n, B, ht, ho, hn, map, s->d_red, s->d_grad, n_params,
+                                          s->stream),
+                       "launch pauli_ip_hi");
+            }
             for (size_t k = i; k-- > j;) seg.push_back(inverse(gates[k]));
             i = j;
         }

@@ -1136,49 +1136,9 @@ __global__ __launch_bounds__(256) void k_copy_z(const cpx<T> *__restrict__ psi, 
     }
 }
 
-// Im <lambda_b | P_q | psi_b>, P in {X = 1, Y = 2, Z = 3}, FP64, fixed order:
-// stage 1 per (chunk, batch entry), stage 2 adds the sum to grad[b * stride + p].
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_pauli_ip_partial(const cpx<T> *__restrict__ psi,
-                                                                  const cpx<T> *__restrict__ lam,
-                                                                  uint64_t n_amps, uint64_t chunk,
-                                                                  int q, int pauli,
-                                                                  double *__restrict__ part, int nblk) {
-    __shared__ double sh[kRedThreads];
-    const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
-    const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
-    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
-    const uint64_t m = 1ull << q;
-    double acc = 0.0;
-    for (uint64_t i = lo + threadIdx.x; i < lo + chunk; i += kRedThreads) {
-        const cpx<T> l = lm[i];
-        const double lx = (double)l.x, ly = (double)l.y;
-        double px, py;   // (P psi)_i
-        if (pauli == 3) {
-            const cpx<T> v = ps[i];
-            const double sgn = (i & m) ? -1.0 : 1.0;
-            px = sgn * (double)v.x;
-            py = sgn * (double)v.y;
-        } else {
-            const cpx<T> v = ps[i ^ m];
-            if (pauli == 1) {
-                px = (double)v.x;
-                py = (double)v.y;
-            } else {  // Y: (-i, +i) psi_{i ^ m} for bit 0, 1
-                const double sgn = (i & m) ? 1.0 : -1.0;
-                px = -sgn * (double)v.y;
-                py = sgn * (double)v.x;
-            }
-        }
-        // Im(conj(l) * p) = lx * py - ly * px
-        acc += lx * py - ly * px;
-    }
-    const double sum = block_tree_sum(acc, sh);
-    if (threadIdx.x == 0) part[(uint64_t)blockIdx.y * nblk + blockIdx.x] = sum;
-}
-
 // Block sum with a fixed order (wave butterflies, then the waves in order);
 // the result is valid in thread 0 only, and the scratch is free on return.
+template <int NTH = kRedThreads>
 __device__ __forceinline__ double block_sum_t0(double v, double *sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -1186,17 +1146,47 @@ __device__ __forceinline__ double block_sum_t0(double v, double *sh) {
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+        for (int w = 0; w < NTH / 64; ++w) s += sh[w];
     __syncthreads();
     return s;
+}
+
+constexpr int kIpSub = 4096;   // amplitudes staged per sub-chunk (2^12)
+
+// The terms' contributions at global index i, staged slot j (psi_i = buf[j]):
+// Z terms use bit q of i; X and Y terms take their partner from slot j ^ 2^q,
+// where q is then the qubit's bit position inside the staged sub-chunk.
+template <int MT, typename T>
+__device__ __forceinline__ void ip_terms_at(double (&acc)[MT], uint64_t i, uint32_t j, cpx<T> l,
+                                            const cpx<T> *buf, const IpTerms &terms, int nt) {
+    const cpx<T> v = buf[j];
+    const double lx = (double)l.x, ly = (double)l.y;
+    const double base = lx * (double)v.y - ly * (double)v.x;   // Im(conj(l) v)
+#pragma clang loop unroll(full)
+    for (int t = 0; t < MT; ++t) {
+        if (t >= nt) continue;   // predicated: acc stays in registers
+        const uint32_t m = 1u << terms.q[t];
+        if (terms.pauli[t] == 3) {
+            acc[t] += ((i >> terms.q[t]) & 1) ? -base : base;
+        } else {
+            const cpx<T> w = buf[j ^ m];
+            double px = (double)w.x, py = (double)w.y;
+            if (terms.pauli[t] == 2) {   // Y: (-i, +i) psi_{i ^ m} for bit 0, 1
+                const double sgn = (j & m) ? 1.0 : -1.0;
+                px = -sgn * (double)w.y;
+                py = sgn * (double)w.x;
+            }
+            acc[t] += lx * py - ly * px;
+        }
+    }
 }
 
 // Several Im <lambda_b | P_t | psi_b> in one read of psi and lambda. The
 // chunk is walked in sub-chunks of kIpSub amplitudes staged in LDS: Z terms
 // take any qubit; X and Y terms take qubits whose partner i ^ 2^q lies in the
-// same sub-chunk (the host sends the others to k_pauli_ip_partial). Stage 1
+// same sub-chunk. It serves complex64 and states below 2^12 amplitudes;
+// k_pauli_ip_sub serves the rest and X and Y terms on higher qubits. Stage 1
 // per (chunk, batch entry); part[(b * nt + t) * nblk + chunk].
-constexpr int kIpSub = 4096;
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__restrict__ psi,
                                                                 const cpx<T> *__restrict__ lam,
@@ -1218,32 +1208,108 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
         __syncthreads();
         for (uint32_t j = threadIdx.x; j < sub; j += kRedThreads) {
             const uint64_t i = s0 + j;
-            const cpx<T> l = lm[i], v = buf[j];
-            const double lx = (double)l.x, ly = (double)l.y;
-            const double base = lx * (double)v.y - ly * (double)v.x;   // Im(conj(l) v)
-#pragma clang loop unroll(full)
-            for (int t = 0; t < kMaxIpTerms; ++t) {
-                if (t >= nt) continue;   // predicated: acc stays in registers
-                const uint32_t m = 1u << terms.q[t];
-                if (terms.pauli[t] == 3) {
-                    acc[t] += ((i >> terms.q[t]) & 1) ? -base : base;
-                } else {
-                    const cpx<T> w = buf[j ^ m];
-                    double px = (double)w.x, py = (double)w.y;
-                    if (terms.pauli[t] == 2) {   // Y: (-i, +i) psi_{i ^ m} for bit 0, 1
-                        const double sgn = (j & m) ? 1.0 : -1.0;
-                        px = -sgn * (double)w.y;
-                        py = sgn * (double)w.x;
-                    }
-                    acc[t] += lx * py - ly * px;
-                }
-            }
+            ip_terms_at<kMaxIpTerms>(acc, i, j, lm[i], buf, terms, nt);
         }
     }
 #pragma clang loop unroll(full)
     for (int t = 0; t < kMaxIpTerms; ++t) {
         if (t >= nt) continue;
         const double sum = block_sum_t0(acc[t], sh);
+        if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
+    }
+}
+
+// The same sums over sub-chunks that need not be contiguous: a sub-chunk is
+// the 2^12 amplitudes whose bits outside
+// B = {0, .., lb - 1} u {hq[0], .., hq[h - 1]} (lb = 12 - h, 0 <= h <= 8) are
+// fixed. Its slot j holds bit k < lb of j at qubit k and bit lb + k at qubit
+// hq[k], so an X or Y term on a qubit of B finds its partner inside the staged
+// sub-chunk (terms.q of an X or Y term is the qubit's bit position in B; of a
+// Z term, the qubit). psi and lambda are both staged in LDS by 1,024 threads,
+// and the next sub-chunk's loads are in flight while the current one is summed.
+// Block blockIdx.x walks sub-chunks [x * per, (x + 1) * per) of the 2^(n - 12);
+// the partial layout matches k_pauli_ip_multi's. MT accumulators per thread.
+constexpr int kIpHiThreads = 1024;
+template <typename T, int MT>
+__global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
+                                                              const cpx<T> *__restrict__ lam,
+                                                              uint64_t n_amps, uint64_t per, IpTerms terms,
+                                                              int nt, IpHiMap map, double *__restrict__ part,
+                                                              int nblk) {
+    constexpr int NRS = kIpSub / kIpHiThreads;   // slots per thread: j = r * 1024 + tid
+    static_assert(NRS == 4, "slot split: bits 10 and 11 of j select the register slot");
+    __shared__ cpx<T> buf[kIpSub], lbuf[kIpSub];
+    __shared__ double sh[kIpHiThreads / 64];
+    const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
+    const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
+    const int h = map.h, lb = 12 - h;
+    // global offset of slot j: the bits of j deposited on B (OR-linear in j)
+    auto dep = [&](uint32_t j) {
+        uint64_t o = j & ((1u << lb) - 1u);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < h) o |= (uint64_t)((j >> (lb + k)) & 1u) << map.hq[k];
+        return o;
+    };
+    const uint64_t toff = dep(threadIdx.x), g0 = dep(1u << 10), g1 = dep(1u << 11);
+    double acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = 0.0;
+    // the sub-chunk's base index: its number with zeros inserted at B
+    auto base_of = [&](uint64_t sc) {
+        uint64_t b = sc << lb;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < h) {
+                const int q = map.hq[k];
+                b = ((b >> q) << (q + 1)) | (b & ((1ull << q) - 1));
+            }
+        return b;
+    };
+    auto slot_off = [&](int r) { return toff | ((r & 1) ? g0 : 0ull) | ((r & 2) ? g1 : 0ull); };
+    // software pipeline: the next sub-chunk's loads are in flight while the
+    // current one is summed from LDS
+    const uint64_t s_beg = (uint64_t)blockIdx.x * per, s_end = s_beg + per;
+    // amplitudes in flight as 2-vectors (register arrays of plain vectors)
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 *psv = reinterpret_cast<const v2 *>(ps), *lmv = reinterpret_cast<const v2 *>(lm);
+    v2 *bufv = reinterpret_cast<v2 *>(buf), *lbufv = reinterpret_cast<v2 *>(lbuf);
+    v2 pv[NRS], lv[NRS];
+    {
+        const uint64_t b0 = base_of(s_beg);
+#pragma clang loop unroll(full)
+        for (int r = 0; r < NRS; ++r) {
+            pv[r] = psv[b0 | slot_off(r)];
+            lv[r] = lmv[b0 | slot_off(r)];
+        }
+    }
+    for (uint64_t sc = s_beg; sc < s_end; ++sc) {
+        const uint64_t base = base_of(sc);
+#pragma clang loop unroll(full)
+        for (int r = 0; r < NRS; ++r) {
+            bufv[r * kIpHiThreads + threadIdx.x] = pv[r];
+            lbufv[r * kIpHiThreads + threadIdx.x] = lv[r];
+        }
+        __syncthreads();
+        {   // the last sub-chunk reloads itself (cache hits) instead of a branch
+            const uint64_t b1 = base_of(sc + 1 < s_end ? sc + 1 : sc);
+#pragma clang loop unroll(full)
+            for (int r = 0; r < NRS; ++r) {
+                pv[r] = psv[b1 | slot_off(r)];
+                lv[r] = lmv[b1 | slot_off(r)];
+            }
+        }
+#pragma clang loop unroll(disable)
+        for (int r = 0; r < NRS; ++r) {
+            const uint32_t j = (uint32_t)(r * kIpHiThreads) + threadIdx.x;
+            ip_terms_at<MT>(acc, base | slot_off(r), j, lbuf[j], buf, terms, nt);
+        }
+        __syncthreads();   // every read of this sub-chunk is done before the next is staged
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        if (t >= nt) continue;
+        const double sum = block_sum_t0<kIpHiThreads>(acc[t], sh);
         if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
     }
 }
@@ -1262,17 +1328,6 @@ __global__ __launch_bounds__(kRedThreads) void k_accumulate_multi(const double *
         const double s = block_sum_t0(acc, sh);
         if (threadIdx.x == 0) out[b * out_stride + offs.off[t]] += s;
     }
-}
-
-__global__ __launch_bounds__(kRedThreads) void k_accumulate_final(const double *__restrict__ part,
-                                                                  int nblk, double *__restrict__ out,
-                                                                  uint64_t out_stride, uint64_t out_off) {
-    __shared__ double sh[kRedThreads];
-    const double *p = part + (uint64_t)blockIdx.x * nblk;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += p[i];
-    const double s = block_tree_sum(acc, sh);
-    if (threadIdx.x == 0) out[(uint64_t)blockIdx.x * out_stride + out_off] += s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1392,32 +1447,23 @@ hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, in
     return hipGetLastError();
 }
 
-hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, int n, int batch,
-                                      int q, int pauli, double *d_partials, double *d_grad,
-                                      uint64_t grad_stride, uint64_t grad_off, hipStream_t st) {
-    const uint64_t N = 1ull << n;
-    const int nblk = reduce_blocks(n);
-    const uint64_t chunk = N / (uint64_t)nblk;
-    if (dt == 2)
-        hipLaunchKernelGGL(k_pauli_ip_partial<double>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
-                           (const cpx<double> *)psi, (const cpx<double> *)lam, N, chunk, q, pauli,
-                           d_partials, nblk);
-    else
-        hipLaunchKernelGGL(k_pauli_ip_partial<float>, dim3(nblk, batch), dim3(kRedThreads), 0, st,
-                           (const cpx<float> *)psi, (const cpx<float> *)lam, N, chunk, q, pauli,
-                           d_partials, nblk);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_accumulate_final, dim3(batch), dim3(kRedThreads), 0, st,
-                       (const double *)d_partials, nblk, d_grad, grad_stride, grad_off);
-    return hipGetLastError();
-}
+static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, int n, int batch,
+                                      const IpTerms &terms, const IpOffsets &offs, int nt, const IpHiMap &map,
+                                      double *d_partials, double *d_grad, uint64_t grad_stride, hipStream_t st);
 
 hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n, int batch,
                                  const IpTerms &terms, const IpOffsets &offs, int nt, double *d_partials,
                                  double *d_grad, uint64_t grad_stride, hipStream_t st) {
     if (nt <= 0) return hipSuccess;
     if (nt > kMaxIpTerms) return hipErrorInvalidValue;
+    if (n >= 12 && dt == 2) {
+        // complex128: contiguous 2^12-amplitude sub-chunks (h = 0) of the
+        // pipelined kernel, measured faster here. complex64 keeps this kernel:
+        // with 24 accumulators the pipelined one holds one block per CU.
+        IpHiMap map{};
+        return launch_pauli_ip_sub(dt, psi, lam, n, batch, terms, offs, nt, map, d_partials, d_grad, grad_stride,
+                                   st);
+    }
     const uint64_t N = 1ull << n;
     const int nblk = reduce_blocks(n);
     const uint64_t chunk = N / (uint64_t)nblk;
@@ -1437,6 +1483,60 @@ hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n
     hipLaunchKernelGGL(k_accumulate_multi, dim3(batch), dim3(kRedThreads), 0, st, (const double *)d_partials,
                        nblk, nt, d_grad, grad_stride, offs);
     return hipGetLastError();
+}
+
+// Sub-chunk sums (k_pauli_ip_sub) for n >= 12 and 0 <= h <= 8.
+static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, int n, int batch,
+                                      const IpTerms &terms, const IpOffsets &offs, int nt, const IpHiMap &map,
+                                      double *d_partials, double *d_grad, uint64_t grad_stride, hipStream_t st) {
+    if (nt <= 0) return hipSuccess;
+    if (nt > kMaxIpTerms || n < 12 || n > 62 || map.h < 0 || map.h > 8) return hipErrorInvalidValue;
+    const int lb = 12 - map.h;
+    for (int k = 0; k < map.h; ++k)   // ascending, above the low bits, inside the state
+        if (map.hq[k] < lb || map.hq[k] >= n || (k && map.hq[k] <= map.hq[k - 1])) return hipErrorInvalidValue;
+    for (int t = 0; t < nt; ++t)
+        if (terms.pauli[t] < 1 || terms.pauli[t] > 3 || terms.q[t] >= (terms.pauli[t] == 3 ? n : 12))
+            return hipErrorInvalidValue;
+    const uint64_t N = 1ull << n;
+    // a quarter of the reduction blocks, each pipelining 4+ sub-chunks
+    const int nblk = reduce_blocks(n) >= 4 ? reduce_blocks(n) / 4 : 1;
+    const uint64_t per = (N >> 12) / (uint64_t)nblk;   // sub-chunks per block (>= 1)
+    if (per == 0 || per * (uint64_t)nblk != (N >> 12)) return hipErrorInvalidValue;
+    const dim3 grid(nblk, batch), block(kIpHiThreads);
+    const bool few = nt <= kMaxIpHiTerms;   // fewer accumulators, fewer registers
+    if (dt == 2) {
+        if (few)
+            hipLaunchKernelGGL((k_pauli_ip_sub<double, kMaxIpHiTerms>), grid, block, 0, st,
+                               (const cpx<double> *)psi, (const cpx<double> *)lam, N, per, terms, nt, map,
+                               d_partials, nblk);
+        else
+            hipLaunchKernelGGL((k_pauli_ip_sub<double, kMaxIpTerms>), grid, block, 0, st,
+                               (const cpx<double> *)psi, (const cpx<double> *)lam, N, per, terms, nt, map,
+                               d_partials, nblk);
+    } else {
+        if (few)
+            hipLaunchKernelGGL((k_pauli_ip_sub<float, kMaxIpHiTerms>), grid, block, 0, st,
+                               (const cpx<float> *)psi, (const cpx<float> *)lam, N, per, terms, nt, map,
+                               d_partials, nblk);
+        else
+            hipLaunchKernelGGL((k_pauli_ip_sub<float, kMaxIpTerms>), grid, block, 0, st,
+                               (const cpx<float> *)psi, (const cpx<float> *)lam, N, per, terms, nt, map,
+                               d_partials, nblk);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_accumulate_multi, dim3(batch), dim3(kRedThreads), 0, st, (const double *)d_partials,
+                       nblk, nt, d_grad, grad_stride, offs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_ip_hi(int dt, const void *psi, const void *lam, int n, int batch,
+                              const IpTerms &terms, const IpOffsets &offs, int nt, const IpHiMap &map,
+                              double *d_partials, double *d_grad, uint64_t grad_stride, hipStream_t st) {
+    if (nt > kMaxIpHiTerms || n < 13 || map.h < 1) return hipErrorInvalidValue;
+    for (int t = 0; t < nt; ++t)
+        if (terms.pauli[t] == 3) return hipErrorInvalidValue;
+    return launch_pauli_ip_sub(dt, psi, lam, n, batch, terms, offs, nt, map, d_partials, d_grad, grad_stride, st);
 }
 
 int pauli_ip_multi_chunk_bits(int n) {

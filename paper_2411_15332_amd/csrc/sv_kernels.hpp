@@ -58,9 +58,9 @@ hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_
 hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, int batch, int q,
                          hipStream_t st);
 
-// grad[b * grad_stride + grad_off] += Im <lam_b | P_q | psi_b>, P = X (1), Y (2), Z (3),
-// accumulated in FP64 in a fixed order. d_partials: reduce_partials_size(n) * batch.
-// Several (qubit, Pauli) terms of one adjoint run, by value in the launch.
+// Adjoint inner products Im <lambda_b | P | psi_b>, P = X (1), Y (2) or Z (3)
+// on one qubit, accumulated in FP64 in a fixed order. Several (qubit, Pauli)
+// terms of one adjoint run go by value in one launch.
 constexpr int kMaxIpTerms = 24;
 struct IpTerms {
     uint8_t q[kMaxIpTerms];
@@ -78,9 +78,19 @@ hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n
                                  double *d_grad, uint64_t grad_stride, hipStream_t st);
 int pauli_ip_multi_chunk_bits(int n);
 
-hipError_t launch_pauli_ip_accumulate(int dt, const void *psi, const void *lam, int n, int batch,
-                                      int q, int pauli, double *d_partials, double *d_grad,
-                                      uint64_t grad_stride, uint64_t grad_off, hipStream_t st);
+// The same for up to kMaxIpHiTerms X and Y terms on qubits at or above bit
+// 12: the sub-chunks staged in LDS are the 2^12 amplitudes spanned by qubits
+// 0 .. 11 - h and the h <= 8 qubits hq[] (ascending). A term's q is its
+// qubit's position in that set (q < 12 - h for a low qubit, 12 - h + k for
+// hq[k]). Needs n >= 13 (hipErrorInvalidValue otherwise).
+constexpr int kMaxIpHiTerms = 8;
+struct IpHiMap {
+    uint8_t hq[8];
+    int32_t h;
+};
+hipError_t launch_pauli_ip_hi(int dt, const void *psi, const void *lam, int n, int batch,
+                              const IpTerms &terms, const IpOffsets &offs, int nt, const IpHiMap &map,
+                              double *d_partials, double *d_grad, uint64_t grad_stride, hipStream_t st);
 
 // One workgroup per job: |0...0> in LDS, the job's small ops, out[j] = <Z_qubit>.
 hipError_t launch_small_jobs(int dt, const SmallJob *d_jobs, int n_jobs, const SmallOp *d_ops,

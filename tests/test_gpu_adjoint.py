@@ -59,6 +59,55 @@ def test_adjoint_general_circuit(P):
         assert np.max(np.abs(g[b] - ps)) <= 1e-10
 
 
+def _rotation_layers(n, layers, seed):
+    """Layers of RX / RY / RZ (random axis) on every qubit, each with its own
+    parameter, separated by CNOT chains; returns (gates, number of parameters)."""
+    rng = np.random.default_rng(seed)
+    gates, k = [], 0
+    for layer in range(layers):
+        for q in range(n):
+            gates.append(synth.Gate(("RX", "RY", "RZ")[int(rng.integers(3))], q, -1, 0.0, k))
+            k += 1
+        for q in range(layer % 2, n - 1, 2):
+            gates.append(synth.Gate("CNOT", q, q + 1))
+    return gates, k
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_high_qubit_terms(P, dtype):
+    """X and Y generators on qubits >= 12, whose partners lie outside a
+    2^12-amplitude chunk (the fused high-qubit inner products), next to Z terms
+    and low-qubit terms of the same runs; gradient on a high qubit."""
+    n = 16
+    gates, k = _rotation_layers(n, 3, 11)
+    params = np.random.default_rng(12).uniform(-3, 3, size=(2, k))
+    high_xy = [g.param for g in gates if g.param >= 0 and g.q0 >= 12 and g.name != "RZ"]
+    assert len(high_xy) >= 6
+    which = high_xy + [g.param for g in gates if g.param >= 0 and g.q0 < 12][::9]
+    with P.StateVector(n, dtype, batch=2) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=13)
+    for b in range(2):
+        assert abs(f[b] - O.loss_z(n, gates, params[b], qubit=13)) <= TOL_PS[dtype]
+        ps = O.grad_param_shift(n, gates, params[b], which, qubit=13)
+        assert np.max(np.abs(g[b, which] - ps)) <= TOL_PS[dtype]
+
+
+def test_adjoint_more_than_eight_high_qubits(P):
+    """A run with X / Y generators on 9 qubits >= 12 takes two fused launches
+    (8 qubits, then 1); every high-qubit gradient against parameter shift."""
+    n = 21
+    gates = [synth.Gate("RY", q, -1, 0.0, q) for q in range(n)]
+    gates += [synth.Gate("CNOT", q, q + 1) for q in range(n - 1)]
+    gates += [synth.Gate("RX" if q % 2 else "RY", q, -1, 0.0, n + q) for q in range(n)]
+    params = np.random.default_rng(21).uniform(-3, 3, size=(1, 2 * n))
+    which = [n + q for q in range(12, n)] + [q for q in (12, 16, 20)] + [n + 3]
+    with P.StateVector(n, "c128", batch=1) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=20)
+    assert abs(f[0] - O.loss_z(n, gates, params[0], qubit=20)) <= 1e-10
+    ps = O.grad_param_shift(n, gates, params[0], which, qubit=20)
+    assert np.max(np.abs(g[0, which] - ps)) <= 1e-10
+
+
 def test_adjoint_rejects_nonrotation_parameters(P):
     gates = [synth.Gate("P", 0, -1, 0.0, 0)]
     with P.StateVector(4, "c128") as sv:
