@@ -182,10 +182,13 @@ __device__ __forceinline__ void r_dense1_ri(cpx<T> (&a)[NR], T r00, T r01, T r10
         const int j1 = j | (1 << P);
         const cpx<T> x0 = a[j], x1 = a[j1];
         const T y1r = BT ? -x1.y : x1.x, y1i = BT ? x1.x : x1.y;   // i^BT x1
-        const T z0r = r00 * x0.x + r01 * y1r, z0i = r00 * x0.y + r01 * y1i;
-        const T z1r = r10 * x0.x + r11 * y1r, z1i = r10 * x0.y + r11 * y1i;
-        a[j] = G0 ? mk<T>(-z0i, z0r) : mk<T>(z0r, z0i);
-        a[j1] = G1 ? mk<T>(-z1i, z1r) : mk<T>(z1r, z1i);
+        const T z0r = r00 * x0.x + r01 * y1r, z1r = r10 * x0.x + r11 * y1r;
+        // a factor i on an output: (re, im) <- (-im, re), the sign taken into
+        // the products (a negated operand costs no instruction)
+        if constexpr (G0) a[j] = mk<T>(-r00 * x0.y - r01 * y1i, z0r);
+        else a[j] = mk<T>(z0r, r00 * x0.y + r01 * y1i);
+        if constexpr (G1) a[j1] = mk<T>(-r10 * x0.y - r11 * y1i, z1r);
+        else a[j1] = mk<T>(z1r, r10 * x0.y + r11 * y1i);
     }
 }
 
