@@ -1209,9 +1209,14 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
         __syncthreads();   // the previous sub-chunk's reads are done
         for (uint32_t j = threadIdx.x; j < sub; j += kRedThreads) buf[j] = ps[s0 + j];
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < sub; j += kRedThreads) {
-            const uint64_t i = s0 + j;
-            ip_terms_at<kMaxIpTerms>(acc, i, j, lm[i], buf, terms, nt);
+        // lambda one step ahead: the next load is in flight during the terms
+        uint32_t j = threadIdx.x;
+        cpx<T> l = j < sub ? lm[s0 + j] : mk<T>((T)0, (T)0);
+        for (; j < sub; j += kRedThreads) {
+            const uint32_t jn = j + kRedThreads;
+            const cpx<T> ln = jn < sub ? lm[s0 + jn] : l;
+            ip_terms_at<kMaxIpTerms>(acc, s0 + j, j, l, buf, terms, nt);
+            l = ln;
         }
     }
 #pragma clang loop unroll(full)
@@ -1228,21 +1233,22 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
 // fixed. Its slot j holds bit k < lb of j at qubit k and bit lb + k at qubit
 // hq[k], so an X or Y term on a qubit of B finds its partner inside the staged
 // sub-chunk (terms.q of an X or Y term is the qubit's bit position in B; of a
-// Z term, the qubit). psi and lambda are both staged in LDS by 1,024 threads,
-// and the next sub-chunk's loads are in flight while the current one is summed.
+// Z term, the qubit). psi and lambda are both staged in LDS by TH threads, and
+// the next sub-chunk's loads are in flight while the current one is summed.
 // Block blockIdx.x walks sub-chunks [x * per, (x + 1) * per) of the 2^(n - 12);
 // the partial layout matches k_pauli_ip_multi's. MT accumulators per thread.
-constexpr int kIpHiThreads = 1024;
-template <typename T, int MT>
-__global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
-                                                              const cpx<T> *__restrict__ lam,
-                                                              uint64_t n_amps, uint64_t per, IpTerms terms,
-                                                              int nt, IpHiMap map, double *__restrict__ part,
-                                                              int nblk) {
-    constexpr int NRS = kIpSub / kIpHiThreads;   // slots per thread: j = r * 1024 + tid
-    static_assert(NRS == 4, "slot split: bits 10 and 11 of j select the register slot");
+constexpr int kIpSubThreadsC128 = 1024;
+constexpr int kIpSubThreadsC64 = 1024;
+template <typename T, int MT, int TH>
+__global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
+                                                    const cpx<T> *__restrict__ lam, uint64_t n_amps,
+                                                    uint64_t per, IpTerms terms, int nt, IpHiMap map,
+                                                    double *__restrict__ part, int nblk) {
+    constexpr int NRS = kIpSub / TH;              // slots per thread: j = r * TH + tid
+    constexpr int RB = __builtin_ctz(NRS);        // bits of r: bits log2(TH) .. 11 of j
+    static_assert((TH & (TH - 1)) == 0 && TH >= 256 && TH <= 1024, "thread count");
     __shared__ cpx<T> buf[kIpSub], lbuf[kIpSub];
-    __shared__ double sh[kIpHiThreads / 64];
+    __shared__ double sh[TH / 64];
     const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
     const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
     const int h = map.h, lb = 12 - h;
@@ -1254,7 +1260,10 @@ __global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__r
             if (k < h) o |= (uint64_t)((j >> (lb + k)) & 1u) << map.hq[k];
         return o;
     };
-    const uint64_t toff = dep(threadIdx.x), g0 = dep(1u << 10), g1 = dep(1u << 11);
+    const uint64_t toff = dep(threadIdx.x);
+    uint64_t gr[RB];   // offsets of the register-slot bits of j
+#pragma unroll
+    for (int b = 0; b < RB; ++b) gr[b] = dep((uint32_t)TH << b);
     double acc[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = 0.0;
@@ -1269,7 +1278,12 @@ __global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__r
             }
         return b;
     };
-    auto slot_off = [&](int r) { return toff | ((r & 1) ? g0 : 0ull) | ((r & 2) ? g1 : 0ull); };
+    auto slot_off = [&](int r) {
+        uint64_t o = toff;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) o |= ((r >> b) & 1) ? gr[b] : 0ull;
+        return o;
+    };
     // software pipeline: the next sub-chunk's loads are in flight while the
     // current one is summed from LDS
     const uint64_t s_beg = (uint64_t)blockIdx.x * per, s_end = s_beg + per;
@@ -1290,8 +1304,8 @@ __global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__r
         const uint64_t base = base_of(sc);
 #pragma clang loop unroll(full)
         for (int r = 0; r < NRS; ++r) {
-            bufv[r * kIpHiThreads + threadIdx.x] = pv[r];
-            lbufv[r * kIpHiThreads + threadIdx.x] = lv[r];
+            bufv[r * TH + threadIdx.x] = pv[r];
+            lbufv[r * TH + threadIdx.x] = lv[r];
         }
         __syncthreads();
         {   // the last sub-chunk reloads itself (cache hits) instead of a branch
@@ -1304,7 +1318,7 @@ __global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__r
         }
 #pragma clang loop unroll(disable)
         for (int r = 0; r < NRS; ++r) {
-            const uint32_t j = (uint32_t)(r * kIpHiThreads) + threadIdx.x;
+            const uint32_t j = (uint32_t)(r * TH) + threadIdx.x;
             ip_terms_at<MT>(acc, base | slot_off(r), j, lbuf[j], buf, terms, nt);
         }
         __syncthreads();   // every read of this sub-chunk is done before the next is staged
@@ -1312,7 +1326,7 @@ __global__ __launch_bounds__(kIpHiThreads) void k_pauli_ip_sub(const cpx<T> *__r
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
         if (t >= nt) continue;
-        const double sum = block_sum_t0<kIpHiThreads>(acc[t], sh);
+        const double sum = block_sum_t0<TH>(acc[t], sh);
         if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
     }
 }
@@ -1505,27 +1519,19 @@ static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, 
     const int nblk = reduce_blocks(n) >= 4 ? reduce_blocks(n) / 4 : 1;
     const uint64_t per = (N >> 12) / (uint64_t)nblk;   // sub-chunks per block (>= 1)
     if (per == 0 || per * (uint64_t)nblk != (N >> 12)) return hipErrorInvalidValue;
-    const dim3 grid(nblk, batch), block(kIpHiThreads);
+    const dim3 grid(nblk, batch);
     const bool few = nt <= kMaxIpHiTerms;   // fewer accumulators, fewer registers
+#define SV_IP_SUB(TT, MTT, THH)                                                                   \
+    hipLaunchKernelGGL((k_pauli_ip_sub<TT, MTT, THH>), grid, dim3(THH), 0, st, (const cpx<TT> *)psi, \
+                       (const cpx<TT> *)lam, N, per, terms, nt, map, d_partials, nblk)
     if (dt == 2) {
-        if (few)
-            hipLaunchKernelGGL((k_pauli_ip_sub<double, kMaxIpHiTerms>), grid, block, 0, st,
-                               (const cpx<double> *)psi, (const cpx<double> *)lam, N, per, terms, nt, map,
-                               d_partials, nblk);
-        else
-            hipLaunchKernelGGL((k_pauli_ip_sub<double, kMaxIpTerms>), grid, block, 0, st,
-                               (const cpx<double> *)psi, (const cpx<double> *)lam, N, per, terms, nt, map,
-                               d_partials, nblk);
+        if (few) SV_IP_SUB(double, kMaxIpHiTerms, kIpSubThreadsC128);
+        else SV_IP_SUB(double, kMaxIpTerms, kIpSubThreadsC128);
     } else {
-        if (few)
-            hipLaunchKernelGGL((k_pauli_ip_sub<float, kMaxIpHiTerms>), grid, block, 0, st,
-                               (const cpx<float> *)psi, (const cpx<float> *)lam, N, per, terms, nt, map,
-                               d_partials, nblk);
-        else
-            hipLaunchKernelGGL((k_pauli_ip_sub<float, kMaxIpTerms>), grid, block, 0, st,
-                               (const cpx<float> *)psi, (const cpx<float> *)lam, N, per, terms, nt, map,
-                               d_partials, nblk);
+        if (few) SV_IP_SUB(float, kMaxIpHiTerms, kIpSubThreadsC64);
+        else SV_IP_SUB(float, kMaxIpTerms, kIpSubThreadsC64);
     }
+#undef SV_IP_SUB
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_accumulate_multi, dim3(batch), dim3(kRedThreads), 0, st, (const double *)d_partials,
