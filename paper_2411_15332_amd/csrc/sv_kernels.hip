@@ -480,8 +480,11 @@ __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
 }
 
 // D2: the variant that also executes OP_DENSE2 (its 4x4 needs many more
-// registers; passes without it run the lean variant).
-template <typename T, bool D2>
+// registers; passes without it run the lean variant). FX: exchanges move the
+// whole tile through a full-tile LDS buffer (2 barriers each instead of 4);
+// for launches too small to fill the chip, where the pass is latency-bound
+// and LDS does not limit occupancy.
+template <typename T, bool D2, bool FX>
 __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
                                               const DevPass *__restrict__ passes, int pass_idx,
                                               const DevLayout *__restrict__ layouts,
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
     constexpr int W = PassTraits<T>::W;
     constexpr int NR = 1 << R;
     constexpr int SH = sizeof(T) == 8 ? 4 : 3;   // log2 of the slot size in bytes
-    __shared__ cpx<T> lds[(NR << W) / 2];        // half a tile
+    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];   // a tile, or half a tile
     char *const ldsb = reinterpret_cast<char *>(lds);
 
     const DevPass &P = passes[pass_idx];
@@ -567,8 +570,31 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
             OpRec nxt = recs[oi + 1 < oe ? oi + 1 : oi];   // prefetch the next record
             switch (op.code()) {
             case OP_EXCH: {
-                const uint32_t lo = (1u << op.sb()) - 1u;
                 const DevLayout &Lw = LB[op.a()], &Lr = LB[op.b()];
+                if constexpr (FX) {
+                    // every register at once: slot addresses without a half bit
+                    uint32_t aw = thr_slot<W>(Lw, tid) << SH, ar = thr_slot<W>(Lr, tid) << SH;
+                    uint32_t gw[R], gr[R];
+#pragma unroll
+                    for (int b = 0; b < R; ++b) {
+                        gw[b] = Lw.reg_slot[b] << SH;
+                        gr[b] = Lr.reg_slot[b] << SH;
+                    }
+                    __syncthreads();   // the previous exchange's reads are done
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) {
+                        if (i) aw ^= gw[__builtin_ctz(i)];
+                        *reinterpret_cast<cpx<T> *>(ldsb + aw) = a[i ^ (i >> 1)];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < NR; ++i) {
+                        if (i) ar ^= gr[__builtin_ctz(i)];
+                        a[i ^ (i >> 1)] = *reinterpret_cast<const cpx<T> *>(ldsb + ar);
+                    }
+                    break;
+                }
+                const uint32_t lo = (1u << op.sb()) - 1u;
                 uint32_t tw = thr_slot<W>(Lw, tid), tr = thr_slot<W>(Lr, tid), gw[R], gr[R];
                 tw = drop_bit(tw, lo) << SH;
                 tr = drop_bit(tr, lo) << SH;
@@ -1364,6 +1390,9 @@ hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch, ui
     return hipGetLastError();
 }
 
+// Launches of at most this many workgroups (two per CU) use full-tile exchanges.
+constexpr uint64_t kFullExchangeMaxBlocks = 512;
+
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const DevPass *d_passes,
                        int pass_idx, const DevPass &h_pass, const DevLayout *d_layouts,
                        const DevOp *d_ops, uint64_t ops_stride, hipStream_t st) {
@@ -1377,21 +1406,28 @@ hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const De
     const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
     const dim3 block(1u << h_pass.w);
     const bool d2 = (h_pass.flags & PASS_DENSE2) != 0;
+    const bool fx = h_pass.tiles * (uint64_t)batch <= kFullExchangeMaxBlocks;
+#define SV_PASS(TT, D2V, FXV)                                                                         \
+    hipLaunchKernelGGL((k_pass<TT, D2V, FXV>), grid, block, 0, st, (cpx<TT> *)state, n_amps, d_passes, \
+                       pass_idx, d_layouts, d_ops, ops_stride)
     if (dt == 2) {
-        if (d2)
-            hipLaunchKernelGGL((k_pass<double, true>), grid, block, 0, st, (cpx<double> *)state,
-                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
-        else
-            hipLaunchKernelGGL((k_pass<double, false>), grid, block, 0, st, (cpx<double> *)state,
-                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+        if (d2) {
+            if (fx) SV_PASS(double, true, true);
+            else SV_PASS(double, true, false);
+        } else {
+            if (fx) SV_PASS(double, false, true);
+            else SV_PASS(double, false, false);
+        }
     } else {
-        if (d2)
-            hipLaunchKernelGGL((k_pass<float, true>), grid, block, 0, st, (cpx<float> *)state,
-                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
-        else
-            hipLaunchKernelGGL((k_pass<float, false>), grid, block, 0, st, (cpx<float> *)state,
-                               n_amps, d_passes, pass_idx, d_layouts, d_ops, ops_stride);
+        if (d2) {
+            if (fx) SV_PASS(float, true, true);
+            else SV_PASS(float, true, false);
+        } else {
+            if (fx) SV_PASS(float, false, true);
+            else SV_PASS(float, false, false);
+        }
     }
+#undef SV_PASS
     return hipGetLastError();
 }
 
