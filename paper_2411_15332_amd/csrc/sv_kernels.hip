@@ -520,6 +520,15 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
 
+    // Bring the pass's op records into L2 with one vector load per 64-byte
+    // line, issued before the tile loads: the interpreter then reads them one
+    // after another through the scalar cache without waiting on HBM.
+    uint32_t warm = 0;
+    {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(opb + P.op_begin);
+        const uint32_t nw = (uint32_t)(P.op_end - P.op_begin) * (uint32_t)(sizeof(DevOp) / 4);
+        for (uint32_t i = (uint32_t)tid * 16u; i < nw; i += (1u << W) * 16u) warm ^= w[i];
+    }
     cpx<T> a[NR];
     {
         // Global index of slot j: (base | thread part) XOR the register part,
@@ -560,6 +569,7 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         }
     }
 
+    asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
     cpx<T> f = mk<T>((T)1, (T)0);   // per-thread diagonal factor (OP_UDN)
     const int oe = P.op_end;
     int oi = P.op_begin;
@@ -822,6 +832,21 @@ __device__ __forceinline__ uint32_t ins0(uint32_t x, int q) {
     return ((x >> q) << (q + 1)) | (x & ((1u << q) - 1));
 }
 
+// Bring a small plan's op records and the first constant of every op that has
+// constants into L2, all threads at once: the op loop then reads them one op
+// at a time without waiting on HBM. Returns a value to be consumed.
+template <typename T>
+__device__ __forceinline__ T small_warm(const SmallOp *ops, int n_ops, const T *cst, int tid, int nt) {
+    T w = (T)0;
+    for (int oi = tid; oi < n_ops; oi += nt) {
+        const SmallOp o = ops[oi];
+        const bool has_consts = o.code == SOP_D1 || o.code == SOP_D2 || o.code == SOP_DENSE1 ||
+                                o.code == SOP_DENSE2 || o.code == SOP_SCALE;
+        if (has_consts) w += cst[o.data];
+    }
+    return w;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_small(cpx<T> *__restrict__ state, int n,
                                                const SmallOp *__restrict__ ops, int n_ops,
@@ -834,7 +859,9 @@ __global__ __launch_bounds__(256) void k_small(cpx<T> *__restrict__ state, int n
     const int nt = blockDim.x;
     cpx<T> *st = state + (uint64_t)blockIdx.x * N;
     const T *cst = consts + (uint64_t)blockIdx.x * const_stride;
+    const T warm = small_warm(ops, n_ops, cst, tid, nt);
     for (uint32_t i = tid; i < N; i += nt) s[i] = st[i];
+    asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
     __syncthreads();
     for (int oi = 0; oi < n_ops; ++oi) {
         const SmallOp op = ops[oi];
@@ -1132,9 +1159,11 @@ __global__ __launch_bounds__(256) void k_small_jobs(const SmallJob *__restrict__
     const SmallJob J = jobs[blockIdx.x];
     const uint32_t N = 1u << J.n;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (uint32_t i = tid; i < N; i += nt) s[i] = mk<T>(i == 0 ? (T)1 : (T)0, (T)0);
-    __syncthreads();
     const T *cst = consts + J.const_begin;
+    const T warm = small_warm(ops + J.op_begin, J.n_ops, cst, tid, nt);
+    for (uint32_t i = tid; i < N; i += nt) s[i] = mk<T>(i == 0 ? (T)1 : (T)0, (T)0);
+    asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
+    __syncthreads();
     for (int oi = 0; oi < J.n_ops; ++oi) {
         const SmallOp op = ops[J.op_begin + oi];
         small_apply<T>(s, N, op, cst + op.data, tid, nt);
