@@ -105,7 +105,8 @@ def serving_section(P, synth, seconds=4.0):
         mu128 = saturated(eng, reqs[:220], 20)
     sweep = []
     for name, kw, mults in (("c128_one_at_a_time", dict(dtype="c128", max_batch=1, n_streams=1), (0.5, 1.0)),
-                            ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=4), (1.0, 4.0, 8.0, 16.0))):
+                            ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=4),
+                             (1.0, 4.0, 8.0, 10.0, 12.0, 14.0, 16.0))):
         for m in mults:
             lam = m * mu128
             count = int(min(4000, max(300, lam * seconds)))
@@ -308,7 +309,7 @@ def main():
         },
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {
-            "bound": "hbm", "kernel": "k_pass<double, false>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "bound": "hbm", "kernel": "k_pass<double, false, false>", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": tr, "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms, "launches": k_launches,
