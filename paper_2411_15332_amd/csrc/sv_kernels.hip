@@ -520,14 +520,18 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
 
-    // Bring the pass's op records into L2 with one vector load per 64-byte
-    // line, issued before the tile loads: the interpreter then reads them one
-    // after another through the scalar cache without waiting on HBM.
+    // Bring the pass's op records and layout tables into L2 with one vector
+    // load per 64-byte line, issued before the tile loads: the interpreter
+    // then reads them one after another through the scalar cache without
+    // waiting on HBM.
     uint32_t warm = 0;
     {
         const uint32_t *w = reinterpret_cast<const uint32_t *>(opb + P.op_begin);
         const uint32_t nw = (uint32_t)(P.op_end - P.op_begin) * (uint32_t)(sizeof(DevOp) / 4);
         for (uint32_t i = (uint32_t)tid * 16u; i < nw; i += (1u << W) * 16u) warm ^= w[i];
+        const uint32_t *wl = reinterpret_cast<const uint32_t *>(LB);
+        const uint32_t nl = (uint32_t)P.n_layouts * (uint32_t)(sizeof(DevLayout) / 4);
+        for (uint32_t i = (uint32_t)tid * 16u; i < nl; i += (1u << W) * 16u) warm ^= wl[i];
     }
     cpx<T> a[NR];
     {

@@ -136,7 +136,8 @@ struct DevPass {      // 96 bytes
     double gen_scale;       // generation: magnitude 2^(-|M|/2) times folded scale
     int32_t store_layout;   // pass-relative index of the layout the tile is stored from
     uint8_t q[28];          // global qubit of tile-local bit l (ascending)
-    uint8_t pad[8];
+    int32_t n_layouts;      // layouts of this pass: [layout_begin, layout_begin + n_layouts)
+    uint8_t pad[4];
 };
 
 static_assert(sizeof(DevOp) == 80, "DevOp layout");

@@ -1491,6 +1491,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             }
         }
         dp.op_end = (int)P.ops.size();
+        dp.n_layouts = (int)P.layouts.size() - dp.layout_begin;
         P.passes.push_back(dp);
         if (restoring) ++P.n_restore;
         first = false;

@@ -242,7 +242,8 @@ class StateVector:
 PASS_DTYPE = np.dtype([("k", "<i4"), ("w", "<i4"), ("op_begin", "<i4"), ("op_end", "<i4"),
                        ("layout_begin", "<i4"), ("flags", "<u4"), ("tiles", "<u8"),
                        ("gen_j", "<u8"), ("gen_mask", "<u8"), ("gen_scale", "<f8"),
-                       ("store_layout", "<i4"), ("q", "u1", (28,)), ("pad", "u1", (8,))])
+                       ("store_layout", "<i4"), ("q", "u1", (28,)), ("n_layouts", "<i4"),
+                       ("pad", "u1", (4,))])
 LAYOUT_DTYPE = np.dtype([("thr_goff", "<u8", (10,)), ("reg_goff", "<u8", (6,)),
                          ("goff_xor", "<u8"), ("reg_goff_xor", "<u8"),
                          ("thr_slot", "<u4", (10,)), ("reg_slot", "<u4", (6,)),

@@ -14,7 +14,7 @@ from oracle import oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 P = pytest.importorskip("paper_2411_15332_amd")
-from plan_emulator import run_plan  # noqa: E402
+from plan_emulator import OP_EXCH, run_plan  # noqa: E402
 
 
 def _declared_symbols():
@@ -287,3 +287,25 @@ def test_automatic_low_qubits(n, seed):
         fixed = [len(P.debug_plan(n, gates, dtype=dt, min_low=c)["passes"]) for c in (6, 4)]
         assert len(plan["passes"]) == fixed[0 if plan["min_low"] == 6 else 1]
         assert np.max(np.abs(got - ref)) < EMU_TOL[dt]
+
+
+@pytest.mark.parametrize("n,dtype", [(16, "c128"), (20, "c64"), (28, "c128")])
+def test_pass_layout_ranges(n, dtype):
+    """Each pass's [layout_begin, layout_begin + n_layouts) holds every layout
+    its exchanges and its store use, and the ranges tile the layout array (the
+    kernel warms exactly that range)."""
+    gates = synth.random_circuit(n, 6, 7)
+    d = P.debug_plan(n, gates, dtype=dtype, min_low=0)
+    passes, ops = d["passes"], d["ops"]
+    assert len(passes) > 0
+    nxt = 0
+    for p in passes:
+        lb, nl = int(p["layout_begin"]), int(p["n_layouts"])
+        assert lb == nxt and nl >= 1
+        nxt = lb + nl
+        used = [int(p["store_layout"])]
+        for o in ops[int(p["op_begin"]):int(p["op_end"])]:
+            if int(o["code"]) == OP_EXCH:
+                used += [int(o["a"]), int(o["b"])]
+        assert max(used) < nl
+    assert nxt == len(d["layouts"])
