@@ -1218,7 +1218,9 @@ constexpr int kIpSub = 4096;   // amplitudes staged per sub-chunk (2^12)
 // The terms' contributions at global index i, staged slot j (psi_i = buf[j]):
 // Z terms use bit q of i; X and Y terms take their partner from slot j ^ 2^q,
 // where q is then the qubit's bit position inside the staged sub-chunk.
-template <int MT, typename T>
+// ZT = false: Z terms are left to the caller (summed per thread, see
+// k_pauli_ip_sub).
+template <int MT, typename T, bool ZT = true>
 __device__ __forceinline__ void ip_terms_at(double (&acc)[MT], uint64_t i, uint32_t j, cpx<T> l,
                                             const cpx<T> *buf, const IpTerms &terms, int nt) {
     const cpx<T> v = buf[j];
@@ -1229,7 +1231,7 @@ __device__ __forceinline__ void ip_terms_at(double (&acc)[MT], uint64_t i, uint3
         if (t >= nt) continue;   // predicated: acc stays in registers
         const uint32_t m = 1u << terms.q[t];
         if (terms.pauli[t] == 3) {
-            acc[t] += ((i >> terms.q[t]) & 1) ? -base : base;
+            if constexpr (ZT) acc[t] += ((i >> terms.q[t]) & 1) ? -base : base;
         } else {
             const cpx<T> w = buf[j ^ m];
             double px = (double)w.x, py = (double)w.y;
@@ -1375,10 +1377,34 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
                 lv[r] = lmv[b1 | slot_off(r)];
             }
         }
+        // X and Y terms per amplitude. Z terms: a slot's sign is its bit of
+        // the term's qubit, which is uniform over the thread's slots unless
+        // the qubit is one of the slot bits; so the thread sums
+        // Im(conj(l) v) over its slots once, and once per slot bit with that
+        // bit's sign, and each Z term takes the matching sum.
+        double zs[1 + RB];
+#pragma unroll
+        for (int k = 0; k <= RB; ++k) zs[k] = 0.0;
 #pragma clang loop unroll(disable)
         for (int r = 0; r < NRS; ++r) {
             const uint32_t j = (uint32_t)(r * TH) + threadIdx.x;
-            ip_terms_at<MT>(acc, base | slot_off(r), j, lbuf[j], buf, terms, nt);
+            const cpx<T> l = lbuf[j], v = buf[j];
+            ip_terms_at<MT, T, false>(acc, base | slot_off(r), j, l, buf, terms, nt);
+            const double b = (double)l.x * (double)v.y - (double)l.y * (double)v.x;
+            zs[0] += b;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) zs[1 + k] += ((r >> k) & 1) ? -b : b;
+        }
+        const uint64_t ib = base | toff;   // the bits of i outside the slot bits
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            if (t >= nt || terms.pauli[t] != 3) continue;
+            const uint64_t m = 1ull << terms.q[t];
+            double z = (ib & m) ? -zs[0] : zs[0];
+#pragma unroll
+            for (int k = 0; k < RB; ++k)
+                if (gr[k] == m) z = zs[1 + k];
+            acc[t] += z;
         }
         __syncthreads();   // every read of this sub-chunk is done before the next is staged
     }
