@@ -172,10 +172,6 @@ def inner(a: np.ndarray, b: np.ndarray) -> complex:
     return complex(re.value, im.value)
 
 
-def amplitudes(psi: np.ndarray, idx: Sequence[int]) -> np.ndarray:
-    return psi[np.asarray(idx, dtype=np.int64)]
-
-
 def loss_z(n: int, gates: Sequence, params: np.ndarray, qubit: int = 0) -> float:
     """f(params) = <Z_qubit> of the circuit applied to |0...0>."""
     return expect_z(simulate(n, gates, params), qubit)

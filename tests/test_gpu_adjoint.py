@@ -92,6 +92,34 @@ def test_adjoint_high_qubit_terms(P, dtype):
         assert np.max(np.abs(g[b, which] - ps)) <= TOL_PS[dtype]
 
 
+def test_adjoint_z_terms_on_every_bit_class(P):
+    """complex128 Z generators (RZ) on thread bits (q < 10), on register-slot
+    bits of the sub-chunk kernel (q = 10, 11) and on chunk-base bits
+    (q >= 12), in the same runs as X / Y generators; every RZ gradient against
+    parameter shift."""
+    n = 16
+    gates, k = [], 0
+    for layer in range(3):
+        for q in range(n):
+            gates.append(synth.Gate(("RY", "RX")[(q + layer) % 2], q, -1, 0.0, k))
+            k += 1
+        for q in range(n):
+            gates.append(synth.Gate("RZ", q, -1, 0.0, k))
+            k += 1
+        for q in range(layer % 2, n - 1, 2):
+            gates.append(synth.Gate("CNOT", q, q + 1))
+    params = np.random.default_rng(31).uniform(-3, 3, size=(2, k))
+    rz = [g for g in gates if g.name == "RZ"]
+    which = [g.param for g in rz if g.q0 in (3, 10, 11, 12, 13, 15)]
+    assert {g.q0 for g in rz if g.param in which} >= {10, 12, 15}
+    with P.StateVector(n, "c128", batch=2) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=2)
+    for b in range(2):
+        assert abs(f[b] - O.loss_z(n, gates, params[b], qubit=2)) <= 1e-12
+        ps = O.grad_param_shift(n, gates, params[b], which, qubit=2)
+        assert np.max(np.abs(g[b, which] - ps)) <= 1e-10
+
+
 def test_adjoint_more_than_eight_high_qubits(P):
     """A run with X / Y generators on 9 qubits >= 12 takes two fused launches
     (8 qubits, then 1); every high-qubit gradient against parameter shift."""
@@ -133,18 +161,40 @@ def test_qnn_autograd_function(P):
         assert np.max(np.abs(got - w[b].item() * ps)) <= 1e-10
 
 
-def test_adjoint_differentiation_config_n20(P):
-    """The differentiation workload: n = 20, 10 layers, 400 rotation angles,
-    256 parameter sets; sampled sets and angles against parameter shift."""
-    n, L, B = 20, 10, 256
+C4 = dict(n=20, L=10, B=256, seed=0)
+
+
+@pytest.fixture(scope="module")
+def c4_reference():
+    """Oracle gradients of the differentiation workload for parameter sets 0
+    and 1: 32 seeded angles each by parameter shift, the first 8 of them by
+    central differences (h = 1e-6), and the loss."""
+    n, L, B = C4["n"], C4["L"], C4["B"]
     gates = synth.qnn_ansatz(n, L)
-    params = synth.qnn_params(n, L, B, 0)
-    with P.StateVector(n, "c64", batch=B) as sv:
-        f, g = sv.adjoint_expect_z(gates, params, qubit=0)
-    assert g.shape == (B, n + 2 * n * L) and np.all(np.isfinite(g))
-    rng = np.random.default_rng(1)
-    for b in (0, 255):
-        which = sorted(rng.choice(np.arange(n, n + 2 * n * L), size=3, replace=False).tolist())
-        assert abs(f[b] - O.loss_z(n, gates, params[b])) <= 1e-5
+    params = synth.qnn_params(n, L, B, C4["seed"])
+    rng = np.random.default_rng(4)
+    ref = {}
+    for b in (0, 1):
+        which = sorted(rng.choice(np.arange(n + 2 * n * L), size=32, replace=False).tolist())
         ps = O.grad_param_shift(n, gates, params[b], which)
-        assert np.max(np.abs(g[b, which] - ps)) <= 1e-4
+        fd = O.grad_fd(n, gates, params[b], which[:8], h=1e-6)
+        ref[b] = (which, ps, fd, O.loss_z(n, gates, params[b]))
+    return gates, params, ref
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_adjoint_differentiation_config_n20(P, c4_reference, dtype):
+    """The differentiation workload as the benchmark runs it: n = 20, 10
+    layers, 400 rotation angles plus 20 encoding angles, 256 parameter sets in
+    one call; sets 0 and 1 against the oracle's parameter shift (32 angles
+    each) and central differences (8 angles each)."""
+    gates, params, ref = c4_reference
+    n, B = C4["n"], C4["B"]
+    with P.StateVector(n, dtype, batch=B) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=0)
+    assert g.shape == (B, params.shape[1]) and np.all(np.isfinite(g))
+    tol_fd = 1e-7 if dtype == "c128" else 1e-4
+    for b, (which, ps, fd, loss) in ref.items():
+        assert abs(f[b] - loss) <= TOL_PS[dtype]
+        assert np.max(np.abs(g[b, which] - ps)) <= TOL_PS[dtype]
+        assert np.max(np.abs(g[b, which[:8]] - fd)) <= tol_fd

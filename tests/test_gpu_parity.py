@@ -250,26 +250,48 @@ def test_empty_identity_and_errors(P):
 
 
 def test_plain_method_at_scale_n28(P):
-    """The n = 28, depth-100 workload in the benchmark's launch configuration:
-    norm after the circuit, the mirror circuit C^dagger C returning |0...0>, and
-    the first layer against the oracle on sampled amplitudes."""
-    n = 28
-    gates = synth.random_circuit(n, 100, 0)
+    """The n = 28, depth-100 workload in the benchmark's launch configuration
+    (seed 0, default planner options), against the oracle's gate-by-gate result
+    stored by tests/golden/make_golden.py: 16,384 sampled amplitudes at 1e-12,
+    every amplitude through the whole-state digest (4,096 block sums with two
+    hash weights each), the norm and <Z_q> of every qubit; then the mirror
+    circuit C^dagger C returns |0...0>."""
+    from state_digest import digest
+    g = np.load(os.path.join(GOLDEN, "random_n28_d100_s0.npz"))
+    n = int(g["n"])
+    gates = synth.random_circuit(n, int(g["depth"]), int(g["seed"]))
+    assert len(gates) == int(g["gates"])
     with P.StateVector(n, "c128") as sv:
         sv.apply(gates)
+        st = sv.plan_stats()
         nrm = sv.norm()[0]
+        zs = np.array([sv.expect_z(q)[0] for q in range(n)])
+        amp = sv.amplitudes(g["idx"])
+        psi = sv.numpy()[0]
+        dg = digest(psi)
+        del psi
         sv.apply(synth.inverse_circuit(gates))
         back = sv.amplitudes([0, 1, 12345, (1 << n) - 1])
-        nrm2 = sv.norm()[0]
-    assert abs(nrm - 1) <= 1e-12 and abs(nrm2 - 1) <= 1e-12
+    print(f"n=28 d100: passes {st['passes']}, max|d amp| {np.max(np.abs(amp - g['amp'])):.2e}, "
+          f"max|d digest| {np.max(np.abs(dg - g['digest'])):.2e}", flush=True)
+    assert np.max(np.abs(amp - g["amp"])) <= 1e-12
+    assert np.max(np.abs(dg - g["digest"])) <= 1e-12
+    assert abs(nrm - float(g["norm"])) <= 1e-12
+    assert np.max(np.abs(zs - g["z"])) <= 1e-12
     assert abs(back[0] - 1) <= 1e-10 and np.max(np.abs(back[1:])) <= 1e-10
-    layer = synth.random_circuit(n, 1, 0)
-    ref = O.simulate(n, layer)
-    idx = np.random.default_rng(1).integers(0, 1 << n, size=4096)
-    with P.StateVector(n, "c128") as sv:
-        sv.apply(layer)
-        amp = sv.amplitudes(idx)
-    assert np.max(np.abs(amp - ref[idx])) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_deep_circuit_half_tile_exchanges_n24(P, dtype):
+    """A depth-20 random circuit at n = 24: 4,096 tiles per pass, so every
+    pass runs the half-tile exchange variant of the pass kernel; whole state
+    against the oracle."""
+    n = 24
+    gates = synth.random_circuit(n, 20, 2424)
+    ref = O.simulate(n, gates)
+    got, st = run(P, n, gates, dtype)
+    assert st["passes"] > 5 and st["exchanges"] > 0
+    assert maxdiff(got, ref) <= TOL[dtype]
 
 
 def test_relabel_passes_race_free_n27(P):
