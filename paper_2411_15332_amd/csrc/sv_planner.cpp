@@ -170,7 +170,9 @@ CGate classify(const sv_gate &g, int n, int src) {
     case G_D1: c.diag = true; c.support = bit(c.q0); break;
     case G_D2: c.diag = true; c.support = bit(c.q0) | bit(c.q1); break;
     case G_MARK: c.diag = true; c.support = (n >= 64) ? ~0ull : (bit(n) - 1); break;
-    case G_X: case G_Y: c.support = c.qneed = bit(c.q0); break;
+    // X and Y on a qubit outside the tile flip a bit of the global XOR
+    // translation of addresses (no data moves), so they need no tile slot
+    case G_X: case G_Y: c.support = bit(c.q0); break;
     case G_H: case G_DENSE1: c.support = c.qneed = c.rneed = bit(c.q0); break;
     case G_CX: c.support = bit(c.q0) | bit(c.q1); c.qneed = c.rneed = bit(c.q1); break;
     case G_SWAP: c.support = c.qneed = bit(c.q0) | bit(c.q1); break;
@@ -212,29 +214,46 @@ struct GateQueue {
 
 // One pass: take gates in order (moving a gate past deferred ones only where
 // they commute) while the union of their tile needs fits k qubits, starting
-// from the qubits that must be in every tile (`low`). Returns the tile set.
-// With `commit`, the taken gates go to `taken` and `pend` keeps the rest;
-// without, `pend` is left unchanged (a look-ahead).
+// from the physical bits every tile holds (`low`). Tile sets are physical
+// bits: ph / lg map logical qubits to physical bits and back, and a taken
+// SWAP that is not inside the tile exchanges its qubits' bits (a relabel:
+// the data stays where it is). Returns the tile set; ph / lg end as the map
+// after the taken gates. With `commit`, the taken gates go to `taken` and
+// `pend` keeps the rest; without, `pend` is left unchanged (a look-ahead).
 static uint64_t form_one_pass(const std::vector<CGate> &cg, GateQueue &pend, int n, int k,
                               const PlanOptions &opt, uint64_t low, bool commit,
-                              std::vector<int> &taken) {
+                              std::vector<int> &taken, std::vector<int> &ph, std::vector<int> &lg) {
     const uint64_t all = (n >= 64) ? ~0ull : (bit(n) - 1);
     uint64_t Q = low & all;
     Blocker blk;
     int dense = 0;
     bool closed = false;
     std::vector<int> new_head;
+    auto need_of = [&](uint64_t qm) {
+        uint64_t r = 0;
+        for (; qm; qm &= qm - 1) r |= bit(ph[__builtin_ctzll(qm)]);
+        return r;
+    };
     auto visit = [&](int gi) {
         const CGate &g = cg[gi];
         bool take = false;
         if (!blk.conflicts(g)) {
             const bool dense_ok = g.cls != G_DENSE1 || dense < opt.max_dense;
-            if (dense_ok && (g.qneed & ~Q) == 0) take = true;
-            else if (dense_ok && popc(Q | g.qneed) <= k) { Q |= g.qneed; take = true; }
+            const uint64_t need = need_of(g.qneed);
+            if (dense_ok && (need & ~Q) == 0) take = true;
+            else if (dense_ok && popc(Q | need) <= k) { Q |= need; take = true; }
         }
         if (take) {
             if (commit) taken.push_back(gi);
             if (g.cls == G_DENSE1) ++dense;
+            if (g.cls == G_SWAP && g.qneed == 0) {
+                const int pa = ph[g.q0], pb = ph[g.q1];
+                if (!(((Q >> pa) & 1) && ((Q >> pb) & 1))) {
+                    std::swap(ph[g.q0], ph[g.q1]);
+                    lg[pa] = g.q1;
+                    lg[pb] = g.q0;
+                }
+            }
             if (!opt.fuse) closed = true;
         } else {
             if (commit) new_head.push_back(gi);
@@ -294,8 +313,22 @@ struct PassCtx {
     int n, k, w;
     uint8_t q[32];          // physical bit position of label l (ascending): the tile's bits
     uint8_t gpos[32];       // physical bit each label is addressed at by the layout being built
-    const int *phys = nullptr;   // physical bit of every logical qubit (qubits off the tile)
-    const int *logi = nullptr;   // logical qubit at every physical bit
+    // Physical bit of every logical qubit off the tile (ph) and the logical
+    // qubit at every physical bit off the tile (lg); SWAPs that leave the
+    // tile change them during the pass. label_logi: logical qubit of every
+    // tile label (label_of is its inverse, -1 off the tile).
+    std::vector<int> ph, lg;
+    int label_logi[32];
+    // Global XOR translation: physical address a holds the amplitude of
+    // (remapped) index a ^ gx. The load layout's addresses carry all of
+    // gx_start, every later layout's its bits off the tile (a workgroup
+    // stores in place, to the addresses it loaded, with the tile's own bits
+    // canonical). X / Y on a qubit off the tile flips its bit in gxd: the
+    // tile base the ops see (the kernel's `base`, the logical base at the
+    // pass's start) then differs from the data's by gxd, which the tile
+    // sources take as an inversion.
+    uint64_t gx_start = 0, gx_off = 0, gxd = 0;
+    uint64_t addr_xor = 0;          // physical address XOR of the next layout record
     int label_of[64];
     // layout state: position of every label and the XOR mask
     int reg_label[kLayoutRegBits], thr_label[kLayoutThreadBits];
@@ -581,8 +614,9 @@ struct PassCtx {
             }
         }
         L.xor_local = xmask;
+        L.reg_goff_xor ^= addr_xor;
         // complex64 16-byte I/O: register bit 0 addresses physical bit 0
-        if (opt.v && gpos[reg_label[0]] == 0 && !((xmask >> reg_label[0]) & 1))
+        if (opt.v && gpos[reg_label[0]] == 0 && !((xmask >> reg_label[0]) & 1) && !(addr_xor & 1))
             L.flags |= LAYOUT_PAIR_IO;
         P.layouts.push_back(L);
         cur_layout = (int)P.layouts.size() - 1 - layout_begin;
@@ -593,8 +627,8 @@ struct PassCtx {
         Src s{};
         const int l = label_of[qubit];
         if (l < 0) {
-            s.code = (uint8_t)(SRC_TILE | phys[qubit]);
-            s.inv = 0;
+            s.code = (uint8_t)(SRC_TILE | ph[qubit]);
+            s.inv = (int)((gxd >> ph[qubit]) & 1);
             s.reg = false;
             return s;
         }
@@ -960,15 +994,12 @@ struct PassCtx {
         }
         case G_MARK: {
             for (int p = 0; p < opt.R; ++p) flush_nondiag(p);
-            uint64_t qmask = 0;
-            uint32_t lm = 0;
-            uint64_t pidx = 0;   // the marked index with its bits at their physical positions
+            uint32_t lm = 0;     // the marked index's bits on the tile labels
+            uint64_t pidx = 0;   // its bits off the tile, at their physical positions
+            for (int l = 0; l < k; ++l)
+                if ((g.index >> label_logi[l]) & 1) lm |= 1u << l;
             for (int qq = 0; qq < n; ++qq)
-                if ((g.index >> qq) & 1) pidx |= bit(phys[qq]);
-            for (int l = 0; l < k; ++l) {
-                qmask |= bit(q[l]);
-                if ((pidx >> q[l]) & 1) lm |= 1u << l;
-            }
+                if (label_of[qq] < 0 && ((g.index >> qq) & 1)) pidx |= bit(ph[qq]);
             const uint32_t phys = lm ^ xmask;
             int t = 0, j = 0;
             for (int s = 0; s < w; ++s) if ((phys >> thr_label[s]) & 1) t |= 1 << s;
@@ -977,12 +1008,15 @@ struct PassCtx {
             o.hdr.a = (uint8_t)j;
             o.hdr.sa = (uint8_t)(t & 0xFF);   // thread index: up to 2^10 threads
             o.hdr.sb = (uint8_t)(t >> 8);
-            o.hdr.data = pidx & ~qmask;
+            o.hdr.data = pidx ^ gxd;
             break;
         }
         case G_X: {
             const Src s = src_of(g.q0);
-            if (s.reg) {
+            if (label_of[g.q0] < 0) {
+                gxd ^= bit(ph[g.q0]);   // off the tile: the global XOR, no data moves
+                ++P.n_relabel;
+            } else if (s.reg) {
                 compose(s.p, Factor{FK_X, false, -1}, PC_A, true);
             } else {
                 xmask ^= 1u << label_of[g.q0];
@@ -997,9 +1031,14 @@ struct PassCtx {
                 compose(s.p, Factor{FK_GATE, s.inv != 0, g.src}, PC_A, false);
             } else {
                 // Y = X diag(i, -i): the phases first, then the label flip
+                // (off the tile: the global XOR bit)
                 add_ud1(s, -1, UC_YDIAG);
-                xmask ^= 1u << label_of[g.q0];
-                cur_layout = -1;
+                if (label_of[g.q0] < 0) {
+                    gxd ^= bit(ph[g.q0]);
+                } else {
+                    xmask ^= 1u << label_of[g.q0];
+                    cur_layout = -1;
+                }
                 ++P.n_relabel;
             }
             break;
@@ -1103,6 +1142,26 @@ struct PassCtx {
         }
         case G_SWAP: {
             const int l0 = label_of[g.q0], l1 = label_of[g.q1];
+            if (l0 < 0 || l1 < 0) {
+                // a qubit off the tile: exchange the two qubits' places (the
+                // tile label, or the physical bit off the tile) instead of
+                // their data; the XOR bits stay with the places
+                const int a = g.q0, b = g.q1;
+                if (l0 >= 0) {          // a on label l0, b off the tile
+                    const int pb = ph[b];
+                    label_of[b] = l0; label_logi[l0] = b; label_of[a] = -1;
+                    ph[a] = pb; lg[pb] = a; ph[b] = -1;
+                } else if (l1 >= 0) {   // b on label l1, a off the tile
+                    const int pa = ph[a];
+                    label_of[a] = l1; label_logi[l1] = a; label_of[b] = -1;
+                    ph[b] = pa; lg[pa] = b; ph[a] = -1;
+                } else {
+                    const int pa = ph[a], pb = ph[b];
+                    ph[a] = pb; ph[b] = pa; lg[pa] = b; lg[pb] = a;
+                }
+                ++P.n_relabel;
+                break;
+            }
             const int r0 = pos_reg[l0], r1 = pos_reg[l1], t0 = pos_thr[l0], t1 = pos_thr[l1];
             if (r0 >= 0) reg_label[r0] = l1; else thr_label[t0] = l1;
             if (r1 >= 0) reg_label[r1] = l0; else thr_label[t1] = l0;
@@ -1223,25 +1282,57 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
     // a pass may store its tile under any permutation of the tile's own
     // physical bits, so the store puts on the low bits the qubits the next
     // pass needs. Passes at the end put every qubit back (phys = identity).
+    // A SWAP is a relabel (the two qubits exchange physical bits, no data
+    // moves) wherever the pass's tile does not hold both of its qubits; that
+    // needs the general qubit-to-bit map, which remapping maintains.
     std::vector<int> phys(n), logi(n);
     for (int q = 0; q < n; ++q) phys[q] = logi[q] = q;
     const bool remap = opt.remap && opt.fuse && n > k;
-    auto low_set = [&]() {
-        uint64_t m = 0;
-        for (int p = 0; p < c; ++p) m |= bit(logi[p]);
-        return m;
-    };
+    if (remap)
+        for (CGate &g : cg)
+            if (g.cls == G_SWAP) g.qneed = 0;
+    const uint64_t low_bits = bit(c) - 1;   // physical bits every tile holds
     auto identity = [&]() {
         for (int q = 0; q < n; ++q) if (phys[q] != q) return false;
         return true;
     };
 
-    // Tile set of a restoring pass: the low bits and the qubits homed there
-    // (every displacement is a pair of a low bit and a high bit).
+    // Global XOR translation of addresses (physical bits): address a holds
+    // the amplitude of index a ^ gx. X / Y on qubits off a pass's tile set
+    // bits; a pass clears the bits of its tile (it stores them canonical).
+    uint64_t gx = 0;
+    // Spare tile slots (physical bits) take the bits set in gx.
+    auto add_gx = [&](uint64_t Q) {
+        for (int p = 0; p < n && popc(Q) < k; ++p)
+            if ((gx >> p) & 1) Q |= bit(p);
+        return Q;
+    };
+    // Spare tile slots take displaced qubits' home bits, following each
+    // chain (the qubit at a home bit in the tile is displaced too: its own
+    // home bit next), so that the store can put them home.
+    auto add_homes = [&](uint64_t Q) {
+        bool grew = true;
+        while (grew && popc(Q) < k) {
+            grew = false;
+            for (int p = 0; p < n && popc(Q) < k; ++p) {
+                if (!((Q >> p) & 1)) continue;
+                const int x = logi[p];   // the qubit at p; its home bit is x
+                if (x != p && !((Q >> x) & 1)) { Q |= bit(x); grew = true; }
+            }
+        }
+        return Q;
+    };
+
+    // Tile set of a restoring pass: the low bits and the displacement chains
+    // through them, then chains of the other displaced qubits, then bits of gx.
     auto restore_set = [&]() {
-        uint64_t Q = low_set();
-        for (int a = 0; a < c; ++a) Q |= bit(a);
-        for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(logi[p]);
+        uint64_t Q = add_homes(low_bits);
+        for (int p = 0; p < n && popc(Q) < k; ++p) {
+            if (logi[p] == p || ((Q >> p) & 1)) continue;
+            Q = add_homes(Q | bit(p));
+        }
+        Q = add_gx(Q);
+        for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(p);
         return Q;
     };
 
@@ -1254,22 +1345,35 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         uint64_t want = 0;
         bool home_lanes = false;
         if (!pending.empty() || (first && generate)) {
-            Q = form_one_pass(cg, pending, n, k, opt, low_set(), true, taken);
+            std::vector<int> ph_end = phys, lg_end = logi;   // the map after the pass's relabels
+            Q = form_one_pass(cg, pending, n, k, opt, low_bits, true, taken, ph_end, lg_end);
             if (remap) {
                 // qubits the next pass wants on the low bits: spare tile
                 // slots take them so that the store can put them there
                 if (!pending.empty()) {
-                    std::vector<int> t2;
-                    want = form_one_pass(cg, pending, n, k, opt, 0, false, t2);
+                    std::vector<int> t2, ph2 = ph_end, lg2 = lg_end;
+                    const uint64_t wp = form_one_pass(cg, pending, n, k, opt, 0, false, t2, ph2, lg2);
+                    for (int p = 0; p < n; ++p)
+                        if ((wp >> p) & 1) want |= bit(lg_end[p]);
                     for (int qq = 0; qq < n && popc(Q) < k; ++qq)
-                        if (((want >> qq) & 1) && phys[qq] == qq) Q |= bit(qq);
+                        if ((want >> qq) & 1) Q |= bit(ph_end[qq]);
                 } else {
                     home_lanes = true;   // last gate pass: head home
-                    for (int a = 0; a < c && popc(Q) < k; ++a) Q |= bit(a);
                 }
             }
-            for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(logi[p]);
-        } else if (remap && !identity()) {
+            if (pending.empty()) {
+                // last gate pass: clear what it can of the XOR bits and the
+                // displacements (chains through the end-of-pass map)
+                Q = add_gx(Q);
+                if (remap) {
+                    std::vector<int> keep = logi;
+                    logi = lg_end;
+                    Q = add_homes(Q);
+                    logi.swap(keep);
+                }
+            }
+            for (int p = 0; p < n && popc(Q) < k; ++p) Q |= bit(p);
+        } else if ((remap && !identity()) || gx != 0) {
             if (++restores > 2 * n) throw std::logic_error("qubit order not restored");
             Q = restore_set();
             restoring = true;
@@ -1280,14 +1384,20 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
 
         PassCtx X(opt, P, cg, n, k, w);
         X.gkinds = kinds.data();
-        X.phys = phys.data();
-        X.logi = logi.data();
+        X.ph = phys;
+        X.lg = logi;
         for (int qq = 0; qq < 64; ++qq) X.label_of[qq] = -1;
         std::memset(X.q, 0, sizeof X.q);
         {
             int l = 0;
             for (int p = 0; p < n; ++p)   // labels in ascending physical order
-                if ((Q >> logi[p]) & 1) { X.q[l] = (uint8_t)p; X.label_of[logi[p]] = l; ++l; }
+                if ((Q >> p) & 1) {
+                    X.q[l] = (uint8_t)p;
+                    X.label_of[logi[p]] = l;
+                    X.label_logi[l] = logi[p];
+                    X.ph[logi[p]] = -1;   // on the tile: placed by its label
+                    ++l;
+                }
         }
         for (int l = 0; l < k; ++l) X.gpos[l] = X.q[l];
 
@@ -1308,8 +1418,13 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         auto labels_of = [&](uint64_t qmask) {
             uint64_t r = 0;
             for (int qq = 0; qq < n; ++qq)
-                if ((qmask >> qq) & 1) r |= bit(X.label_of[qq]);
+                if (((qmask >> qq) & 1) && X.label_of[qq] >= 0) r |= bit(X.label_of[qq]);
             return r;
+        };
+        // a SWAP with a qubit off the tile relabels: the labels of later
+        // gates on its qubits are known only once it is applied
+        auto relabels = [&](const CGate &g) {
+            return g.cls == G_SWAP && (X.label_of[g.q0] < 0 || X.label_of[g.q1] < 0);
         };
 
         // load layout: register labels from U, first-needed first
@@ -1318,7 +1433,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             Blocker blk;
             for (int gi : rem) {
                 const CGate &g = cg[gi];
-                if (blk.conflicts(g)) { blk.defer(g); continue; }
+                if (blk.conflicts(g) || relabels(g)) { blk.defer(g); continue; }
                 const uint64_t nl = labels_of(X.rneed_of(g)) & U;
                 if (popc(S0 | nl) <= ru) S0 |= nl;
                 else blk.defer(g);
@@ -1327,8 +1442,15 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             for (int lb = 0; lb < k && popc(S0) < ru; ++lb)
                 if ((U >> lb) & 1) S0 |= bit(lb);
         }
+        uint64_t tilemask = 0;   // the tile's physical bits
+        for (int l = 0; l < k; ++l) tilemask |= bit(X.q[l]);
+        X.gx_start = gx;
+        X.gx_off = gx & ~tilemask;
+        X.addr_xor = gx;          // the load reads the translated addresses
         X.load(X.storable(S0));
         X.layout_index();
+        X.addr_xor = X.gx_off;    // later layouts: the tile's own bits canonical
+        if (gx & tilemask) X.cur_layout = -1;
 
         while (!rem.empty()) {
             Blocker blk;
@@ -1351,7 +1473,7 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             Blocker b2;
             for (int gi : rem) {
                 const CGate &g = cg[gi];
-                if (b2.conflicts(g)) { b2.defer(g); all_fit = false; continue; }
+                if (b2.conflicts(g) || relabels(g)) { b2.defer(g); all_fit = false; continue; }
                 const uint64_t nl = labels_of(X.rneed_of(g));
                 if (popc(S | nl) <= opt.R) S |= nl;
                 else { b2.defer(g); all_fit = false; }
@@ -1385,58 +1507,55 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
                 X.exchange_to(X.storable(su));
             }
         } else {
-            // Remapping keeps every displaced qubit in a pair: the low bit a
-            // holds the qubit homed at a high bit h, and qubit a sits at h.
-            // The store may undo pairs (both bits in the tile) and make new
-            // ones (a wanted qubit at its home h in the tile takes a low bit
-            // whose own qubit moves to h). Unchanged qubits stay put.
-            for (int a = 0; a < n; ++a) {
-                const int h = logi[a];
-                if (h == a) continue;
-                const bool ok = (a < c && h >= c && phys[a] == h) || (a >= c && h < c && logi[h] == a);
-                if (!ok) throw std::logic_error("qubit pair invariant broken");
-            }
-            uint64_t inP = 0;
-            for (int l = 0; l < k; ++l) inP |= bit(X.q[l]);
-            std::vector<int> dest(n, -1);   // new physical bit of moved logical qubits
+            // The store may put the tile's qubits on any permutation of the
+            // tile's physical bits. Qubits the next pass wants go to the low
+            // bits (those already there stay); every other qubit goes home
+            // when its home bit is in the tile; the rest keep their bits, or
+            // take the bits left free. With `lanes_fixed` the labels on the
+            // lane bits (the tile's lowest bits, which the store layout's
+            // lanes address) keep them, so the store needs no exchange.
+            uint64_t inP = tilemask;
             const bool free_exch = !X.is_storable();
             const uint64_t Wm = home_lanes ? 0 : want;
-            int undone = 0, made = 0;
-            for (int a = 0; a < c; ++a) {
-                const int h = logi[a];
-                if (h == a || !((inP >> h) & 1)) continue;   // no pair, or qubit a off the tile
-                if (!home_lanes && ((Wm >> h) & 1)) continue;  // the next pass wants h low
-                dest[h] = h;
-                dest[a] = a;
-                ++undone;
-            }
-            if (!home_lanes) {
-                uint64_t taken_low = 0;
-                for (int hq = 0; hq < n; ++hq) {
-                    if (!((Wm >> hq) & 1) || hq < c || phys[hq] != hq || !((inP >> hq) & 1)) continue;
-                    int slot = -1;
-                    for (int a = 0; a < c && slot < 0; ++a) {
-                        if ((taken_low >> a) & 1) continue;
-                        // low bit a holds (or gets back, after an undo) its own qubit
-                        const bool own = dest[a] == a || (logi[a] == a && dest[a] < 0);
-                        if (own && !((Wm >> a) & 1)) slot = a;
+            const int nlane = opt.v + 6;
+            auto build_sigma = [&](bool lanes_fixed, int *dst) {
+                uint64_t used = 0;
+                int made = 0;
+                for (int l = 0; l < k; ++l) dst[l] = -1;
+                auto put = [&](int l, int pos) { dst[l] = pos; used |= bit(pos); };
+                if (lanes_fixed)
+                    for (int l = 0; l < nlane && l < k; ++l) put(l, X.q[l]);
+                if (!lanes_fixed) {
+                    for (int l = 0; l < k; ++l)
+                        if (((Wm >> X.label_logi[l]) & 1) && X.q[l] < c) put(l, X.q[l]);
+                    for (int l = 0; l < k; ++l) {
+                        if (dst[l] >= 0 || !((Wm >> X.label_logi[l]) & 1)) continue;
+                        int a = 0;
+                        while (a < c && ((used >> a) & 1)) ++a;
+                        if (a == c) break;
+                        put(l, a);
+                        ++made;
                     }
-                    if (slot < 0) break;
-                    dest[hq] = slot;
-                    dest[slot] = hq;
-                    taken_low |= bit(slot);
-                    ++made;
                 }
-            }
+                for (int l = 0; l < k; ++l) {
+                    const int x = X.label_logi[l];
+                    if (dst[l] < 0 && ((inP >> x) & 1) && !((used >> x) & 1)) put(l, x);
+                }
+                for (int l = 0; l < k; ++l)
+                    if (dst[l] < 0 && !((used >> X.q[l]) & 1)) put(l, X.q[l]);
+                for (int l = 0; l < k; ++l) {
+                    if (dst[l] >= 0) continue;
+                    int pos = 0;
+                    while (!((inP >> pos) & 1) || ((used >> pos) & 1)) ++pos;
+                    put(l, pos);
+                }
+                return made;
+            };
+            const int made = build_sigma(false, sigma);
+            bool lanes_move = false;
+            for (int l = 0; l < nlane && l < k; ++l) lanes_move |= sigma[l] != X.q[l];
             // A lane change costs an exchange unless the pass ends with one.
-            if (!home_lanes && !free_exch && made < 2) {
-                std::fill(dest.begin(), dest.end(), -1);
-                undone = made = 0;
-            }
-            for (int l = 0; l < k; ++l) {
-                const int x = logi[X.q[l]];
-                sigma[l] = dest[x] >= 0 ? dest[x] : X.q[l];
-            }
+            if (lanes_move && !home_lanes && !free_exch && made < 2) build_sigma(true, sigma);
             uint64_t hit = 0;
             for (int l = 0; l < k; ++l) hit |= bit(sigma[l]);
             if (hit != inP) throw std::logic_error("store permutation is not a bijection of the tile");
@@ -1455,14 +1574,20 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             X.cur_layout = -1;
         }
         dp.store_layout = X.layout_index();
-        if (remap) {
-            std::vector<int> moved(k);
-            for (int l = 0; l < k; ++l) moved[l] = logi[X.q[l]];
-            for (int l = 0; l < k; ++l) {
-                phys[moved[l]] = sigma[l];
-                logi[sigma[l]] = moved[l];
+        // the map after the pass: qubits off the tile where the pass's
+        // relabels left them, the tile's qubits at their labels' store bits
+        for (int qq = 0; qq < n; ++qq)
+            if (X.label_of[qq] < 0) {
+                phys[qq] = X.ph[qq];
+                logi[X.ph[qq]] = qq;
             }
+        for (int l = 0; l < k; ++l) {
+            phys[X.label_logi[l]] = sigma[l];
+            logi[sigma[l]] = X.label_logi[l];
         }
+        // stored in place: the tile's bits canonical, the others keep their
+        // translation, flipped by the pass's X / Y off the tile
+        gx = (gx ^ X.gxd) & ~tilemask;
         // In-place safety: without an exchange, nothing orders one wave's loads
         // before another wave's stores to the same tile.
         bool exch_in_pass = false;
@@ -1577,11 +1702,54 @@ static void write_payload(DevOp &rec, const double *v, int count) {
     for (int i = 0; i < count; ++i) dst[i] = (R)v[i];
 }
 
+// FP32 rounding of unit-modulus constants (phases) with error diffusion.
+// Rounding e^{i phi} to the nearest FP32 pair leaves a modulus error of a
+// fixed sign for a given angle (fl32(cos pi/4)^2 + fl32(sin pi/4)^2 is
+// 1 - 3.4e-8), so a circuit of many T gates would shrink the norm steadily.
+// Among the pairs within one unit in the last place of the nearest one, take
+// the one that brings the running sum of modulus errors closest to zero
+// (ties: the closer pair). Other values round to nearest. The running sum
+// starts at zero for every batch entry, so an entry's constants do not depend
+// on the others.
+struct PhaseRounder {
+    double acc = 0.0;
+    void pair(double re, double im, float &r, float &i) {
+        const double m2 = re * re + im * im;
+        r = (float)re;
+        i = (float)im;
+        if (std::fabs(m2 - 1.0) > 1e-12) return;
+        float br = r, bi = i;
+        double be = 0.0, bd = 0.0;
+        bool have = false;
+        for (int dr = -1; dr <= 1; ++dr) {
+            for (int di = -1; di <= 1; ++di) {
+                const float cr = dr ? std::nextafter(r, dr > 0 ? 2.0f : -2.0f) : r;
+                const float ci = di ? std::nextafter(i, di > 0 ? 2.0f : -2.0f) : i;
+                const double e = (double)cr * cr + (double)ci * ci - 1.0;
+                const double d = std::fabs(cr - re) + std::fabs(ci - im);
+                const double key = std::fabs(acc + e);
+                if (!have || key < be || (key == be && d < bd)) {
+                    br = cr; bi = ci; be = key; bd = d; have = true;
+                }
+            }
+        }
+        r = br;
+        i = bi;
+        acc += (double)r * r + (double)i * i - 1.0;
+    }
+    // `count` reals as (re, im) pairs
+    void pairs(const double *v, int count, float *dst) {
+        for (int k = 0; k + 1 < count; k += 2) pair(v[k], v[k + 1], dst[k], dst[k + 1]);
+        if (count & 1) dst[count - 1] = (float)v[count - 1];
+    }
+};
+
 void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, size_t n_params,
                      int batch, bool f32, void *out) {
     DevOp *o = static_cast<DevOp *>(out);
     const size_t nops = p.ops.size();
     for (int b = 0; b < batch; ++b) {
+        PhaseRounder ph;
         for (size_t i = 0; i < nops; ++i) {
             const HostOp &h = p.ops[i];
             DevOp rec = h.hdr;
@@ -1700,8 +1868,16 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
             }
             default: break;
             }
-            if (f32) write_payload<float>(rec, v, count);
-            else write_payload<double>(rec, v, count);
+            if (f32 && h.pk != PK_MAT2RI && h.pk != PK_SCALE) {
+                // complex entries: phases through the error-diffusing rounding
+                if ((size_t)count * sizeof(float) > sizeof rec.payload)
+                    throw std::logic_error("operation payload larger than its record");
+                ph.pairs(v, count, reinterpret_cast<float *>(rec.payload));
+            } else if (f32) {
+                write_payload<float>(rec, v, count);
+            } else {
+                write_payload<double>(rec, v, count);
+            }
             o[(size_t)b * nops + i] = rec;
         }
     }
@@ -1734,8 +1910,10 @@ void materialize_consts(const Plan &p, const sv_gate *gates, const double *param
             }
         }
         if (f32) {
+            // every constant block holds (re, im) pairs
             float *o = static_cast<float *>(out) + (size_t)b * p.cstride;
-            for (uint64_t i = 0; i < p.cstride; ++i) o[i] = (float)row[i];
+            PhaseRounder ph;
+            ph.pairs(row.data(), (int)p.cstride, o);
         } else {
             double *o = static_cast<double *>(out) + (size_t)b * p.cstride;
             if (p.cstride) std::memcpy(o, row.data(), p.cstride * sizeof(double));

@@ -108,12 +108,18 @@ def run_plan(plan, psi, n):
                 on = ((j_idx >> p) & 1).astype(bool)
                 gr = np.where(on, gr ^ int(L["reg_goff"][p]), gr)
                 sr = np.where(on, sr ^ int(L["reg_slot"][p]), sr)
-            assert np.all((g & gr) == 0)
-            return g | gr, s ^ sr
+            return (g, gr), s ^ sr
 
-        goff, _ = tables(0)
-        gidx = base | goff
-        assert np.all((goff & base) == 0)
+        def addresses(li):
+            # (tile base | thread part) XOR register part: the register part
+            # may carry the global XOR translation of bits off the tile
+            (g, gr), _ = tables(li)
+            assert np.all((g & base) == 0)
+            addr = (base | g) ^ gr
+            assert all(np.unique(addr[t]).size == NT * NR for t in range(min(tiles, 4)))
+            return addr
+
+        gidx = addresses(0)
         if int(P["flags"]) & PASS_GENERATE:
             gj, gm, sc = int(P["gen_j"]), int(P["gen_mask"]), float(P["gen_scale"])
             on = ((gidx ^ gj) & ~gm) == 0
@@ -281,7 +287,9 @@ def run_plan(plan, psi, n):
             else:
                 raise NotImplementedError(code)
         assert np.all(f == 1), "pending per-thread factor at the store"
-        goff, _ = tables(int(P["store_layout"]))
-        assert np.all((goff & base) == 0)
-        psi[base | goff] = a
+        sidx = addresses(int(P["store_layout"]))
+        # in place: every workgroup stores exactly the addresses it loaded
+        assert np.array_equal(np.sort(sidx.reshape(tiles, -1), axis=1),
+                              np.sort(np.broadcast_to(gidx, sidx.shape).reshape(tiles, -1), axis=1))
+        psi[sidx] = a
     return psi

@@ -309,3 +309,52 @@ def test_pass_layout_ranges(n, dtype):
                 used += [int(o["a"]), int(o["b"])]
         assert max(used) < nl
     assert nxt == len(d["layouts"])
+
+
+def _monomial_heavy(n, layers, seed):
+    """Layers dominated by permutation gates (X, Y, SWAP, CNOT, CCX) with
+    diagonals (RZ, T, CZ, CPHASE), an occasional dense RX / H and MARK on
+    seeded indices: most of them act on qubits outside a pass's tile."""
+    rng = np.random.default_rng(seed)
+    gates = [synth.Gate("H", q) for q in range(n)]
+    for _ in range(layers):
+        for q in range(n):
+            r = rng.random()
+            if r < 0.3:
+                gates.append(synth.Gate("X", q))
+            elif r < 0.45:
+                gates.append(synth.Gate("Y", q))
+            elif r < 0.6:
+                gates.append(synth.Gate("RZ", q, -1, float(rng.uniform(0, 6))))
+            elif r < 0.7:
+                gates.append(synth.Gate("T", q))
+            elif r < 0.76:
+                gates.append(synth.Gate(("RX", "H")[int(rng.integers(2))], q, -1, float(rng.uniform(0, 6))))
+        perm = rng.permutation(n)
+        for i in range(n // 2):
+            a, b = int(perm[2 * i]), int(perm[2 * i + 1])
+            kind = ("SWAP", "SWAP", "CNOT", "CZ", "CPHASE")[int(rng.integers(5))]
+            gates.append(synth.Gate(kind, a, b, float(rng.uniform(0, 6))))
+        if rng.random() < 0.5:
+            c0, c1, t = (int(x) for x in rng.choice(n, 3, replace=False))
+            gates.append(synth.Gate("CCX", c0, c1, 0.0, -1, 0, t))
+        gates.append(synth.Gate("MARK", -1, -1, 0.0, -1, int(rng.integers(1 << n))))
+    return gates
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed,min_low", [(16, 1, 4), (17, 2, 6), (18, 3, 0)])
+def test_monomials_off_the_tile(n, seed, min_low, dtype):
+    """X / Y on qubits outside a pass's tile flip bits of the global address
+    translation, SWAPs with a qubit outside the tile exchange the qubits'
+    physical bits; diagonals, CNOT / CCX controls and MARK then read the tile
+    base through both. The emulated plans reproduce the oracle, move no data
+    for those gates (fewer passes than without remapping, where every SWAP
+    takes tile slots), and end in canonical order."""
+    gates = _monomial_heavy(n, 12, seed)
+    ref = O.simulate(n, gates)
+    got, plan = _emulate(n, gates, dtype, min_low=min_low)
+    assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
+    assert plan["relabels"] > 0
+    fixed = P.debug_plan(n, gates, dtype=dtype, remap=False, min_low=min_low or 6)
+    assert len(plan["passes"]) < len(fixed["passes"])
