@@ -150,11 +150,18 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates,
  * out: host array [batch]. Synchronizes the stream. */
 sv_status sv_expect_z(sv_state s, int qubit, double *out);
 
-/* sum_i |a_i|^2 per batch entry (should be 1), FP64. out: host [batch]. */
+/* sum_i |a_i|^2 per batch entry, FP64 in a fixed order. Sec. II-A: the
+ * probabilities |alpha_i|^2 of a valid state sum to 1, so this checks that the
+ * gates applied so far kept the state normalized. out: host [batch].
+ * Synchronizes the stream. */
 sv_status sv_norm(sv_state s, double *out);
 
 /* Amplitudes of batch entry b at k basis indices idx[0..k) (each < 2^n),
- * returned as FP64 (re, im) pairs in out[0 .. 2k). Synchronizes the stream. */
+ * returned as FP64 (re, im) pairs in out[0 .. 2k). Sec. II-A: the state is
+ * the vector of 2^n complex amplitudes alpha_i of the basis states |i>, and
+ * |alpha_i|^2 is the probability of measuring i. Complex64 states are widened
+ * exactly to FP64. Errors: SV_EINVAL for b outside the batch or an index
+ * >= 2^n (nothing launched). Synchronizes the stream. */
 sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double *out);
 
 /* Adjoint gradient of f_b = <Z_qubit> (of the circuit applied to |0...0>) with
