@@ -156,6 +156,27 @@ sv_status sv_expect_z(sv_state s, int qubit, double *out);
  * Synchronizes the stream. */
 sv_status sv_norm(sv_state s, double *out);
 
+/* sv_expect_z / sv_norm without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The same FP64 fixed-order reduction.
+ * state: device pointer to `batch` consecutive states of 2^n_qubits amplitudes
+ *        of `dtype` (the layout of sv_alloc), on the current device, read only.
+ * qubit: 0..n_qubits-1 for <Z_qubit>, -1 for the norm.
+ * out:   device pointer to `batch` doubles, written on hip_stream (a
+ *        hipStream_t, or NULL for the default stream); asynchronous, nothing
+ *        is synchronized or copied to the host.
+ * Partial sums live in a file-scope device array of 65,536 doubles (512 KiB,
+ * held on each GPU that runs this call until the process ends):
+ * batch * 2^min(max(n_qubits - 12, 0), 10) must not exceed 65,536
+ * (so batch <= 64 from n_qubits = 22 up), else SV_EINVAL.
+ * Every call on a GPU shares that array: calls that overlap on one GPU (on
+ * different streams, or from several host threads) race; serialize them.
+ * Errors: SV_EINVAL before anything is launched (NULL or misaligned pointer,
+ * dtype, n_qubits outside 1..34, batch outside 1..65535, qubit, scratch
+ * size); SV_EDEVICE when the launch fails. */
+sv_status sv_expect_z_noalloc(const void *state, int n_qubits, sv_dtype dtype, int batch, int qubit,
+                              double *out, void *hip_stream);
+
 /* Amplitudes of batch entry b at k basis indices idx[0..k) (each < 2^n),
  * returned as FP64 (re, im) pairs in out[0 .. 2k). Sec. II-A: the state is
  * the vector of 2^n complex amplitudes alpha_i of the basis states |i>, and

@@ -442,6 +442,33 @@ sv_status sv_norm(sv_state s, double *out) {
     });
 }
 
+sv_status sv_expect_z_noalloc(const void *state, int n_qubits, sv_dtype dtype, int batch, int qubit,
+                              double *out, void *hip_stream) {
+    return guarded([&]() -> sv_status {
+        // every argument is checked before any HIP call, so a rejected call
+        // launches nothing and leaves the scratch as it was
+        if (!state || !out) return fail(SV_EINVAL, "state or out is NULL");
+        if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_EINVAL, "unknown dtype %d", (int)dtype);
+        if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
+        if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch %d outside 1..65535", batch);
+        if (qubit < -1 || qubit >= n_qubits)
+            return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, n_qubits);
+        const size_t amp_bytes = dtype == SV_C128 ? 16 : 8;
+        if (reinterpret_cast<uintptr_t>(state) % amp_bytes != 0 || reinterpret_cast<uintptr_t>(out) % 8 != 0)
+            return fail(SV_EINVAL, "state or out is misaligned");
+        const size_t need = reduce_partials_size(n_qubits) * (size_t)batch;
+        if (need > kStaticPartials)
+            return fail(SV_EINVAL, "batch %d of n = %d needs %zu partial sums; the static scratch holds %zu",
+                        batch, n_qubits, need, kStaticPartials);
+        double *part = nullptr;
+        SV_HIP(static_partials(&part), "scratch address");
+        SV_HIP(launch_reduce((int)dtype, state, n_qubits, batch, qubit, part, out,
+                             static_cast<hipStream_t>(hip_stream)),
+               "launch reduce");
+        return SV_OK;
+    });
+}
+
 sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double *out) {
     return guarded([&]() -> sv_status {
         sv_status st = check_handle(s);

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "sv_kernels.hpp"
 #include "sv_plan.hpp"
@@ -1530,6 +1531,34 @@ hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
     hipLaunchKernelGGL(k_reduce_final, dim3(batch), dim3(kRedThreads), 0, st,
                        (const double *)d_partials, nblk, d_out);
     return hipGetLastError();
+}
+
+// Partial sums of the allocation-free readout: a file-scope device array, so
+// that the entry point using it never allocates. Each GPU holds its own copy
+// until the process ends, and every such call on a GPU shares it.
+static __device__ __align__(256) double scratch[kStaticPartials];
+
+hipError_t static_partials(double **out) {
+    // Host code must not pass the array's name to a kernel (it names a
+    // host-side stand-in): take the device address once per device, with that
+    // device current, and use that address from then on.
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        double *p = nullptr;
+        e = hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_t k,

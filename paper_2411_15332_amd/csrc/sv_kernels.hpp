@@ -50,6 +50,12 @@ size_t reduce_partials_size(int n);
 hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
                          double *d_partials, double *d_out, hipStream_t st);
 
+// Capacity (doubles) of the file-scope partial-sum array of the
+// allocation-free readout, and its device address on the current device
+// (looked up once per device).
+constexpr size_t kStaticPartials = size_t(1) << 16;
+hipError_t static_partials(double **out);
+
 // out[2i], out[2i+1] = FP64 (re, im) of amplitude idx[i] of the state at `state`.
 hipError_t launch_gather(int dt, const void *state, const uint64_t *d_idx, size_t k,
                          double *d_out, hipStream_t st);

@@ -68,6 +68,7 @@ def lib():
         L.sv_expect_z.argtypes = [P, I, P]
         L.sv_norm.argtypes = [P, P]
         L.sv_amplitudes.argtypes = [P, I, P, SZ, P]
+        L.sv_expect_z_noalloc.argtypes = [P, I, I, I, I, P, P]
         L.sv_adjoint_expect_z.argtypes = [P, P, SZ, P, SZ, I, P, P]
         L.sv_sync.argtypes = [P]
         L.sv_device_ptr.argtypes = [P]
@@ -81,7 +82,8 @@ def lib():
         L.sv_debug_plan.restype = I64
         for name in ("sv_alloc", "sv_free", "sv_set_stream", "sv_set_basis", "sv_apply_circuit",
                      "sv_expect_z", "sv_norm", "sv_amplitudes", "sv_adjoint_expect_z", "sv_sync",
-                     "sv_set_option", "sv_plan_stats", "sv_profile_read", "sv_mark_modified"):
+                     "sv_set_option", "sv_plan_stats", "sv_profile_read", "sv_mark_modified",
+                     "sv_expect_z_noalloc"):
             getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -104,6 +106,25 @@ def gate_array(gates: Sequence) -> np.ndarray:
         idx = g.q2 if g.name in THREE_QUBIT_KINDS else g.index
         arr[i] = (GATE_KIND[g.name], g.q0, g.q1, g.param, g.angle, idx)
     return arr
+
+
+def expect_z_noalloc(state, n: int, qubit: int, out, stream=None, batch: Optional[int] = None) -> None:
+    """<Z_qubit> (qubit >= 0) or the norm (qubit = -1) of the states in the
+    device tensor `state` ([batch, 2^n], complex64 or complex128) into the
+    device tensor `out` (float64, [batch]), asynchronously on `stream` (a
+    torch.cuda.Stream; default: the current stream), with no allocation."""
+    torch = _torch()
+    if state.dtype not in (torch.complex64, torch.complex128) or not state.is_contiguous():
+        raise ValueError("state must be a contiguous complex64 or complex128 tensor")
+    if out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor")
+    b = state.numel() >> n if batch is None else int(batch)
+    if out.numel() < b or state.numel() < (b << n):
+        raise ValueError("state or out is smaller than batch * 2^n")
+    st = stream if stream is not None else torch.cuda.current_stream(state.device)
+    dt = SV_C128 if state.dtype == torch.complex128 else SV_C64
+    _check(lib().sv_expect_z_noalloc(ctypes.c_void_p(state.data_ptr()), int(n), dt, b, int(qubit),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
 
 
 def _ptr(a: Optional[np.ndarray]):

@@ -358,3 +358,24 @@ def test_monomials_off_the_tile(n, seed, min_low, dtype):
     assert plan["relabels"] > 0
     fixed = P.debug_plan(n, gates, dtype=dtype, remap=False, min_low=min_low or 6)
     assert len(plan["passes"]) < len(fixed["passes"])
+
+
+@pytest.mark.parametrize("args,what", [
+    ((0, 20, 2, 1, 0, 4096, 0), "NULL"),            # state NULL
+    ((4096, 20, 2, 1, 0, 0, 0), "NULL"),            # out NULL
+    ((4096, 20, 3, 1, 0, 4096, 0), "dtype"),
+    ((4096, 35, 2, 1, 0, 4096, 0), "n_qubits"),
+    ((4096, 20, 2, 0, 0, 4096, 0), "batch"),
+    ((4096, 20, 2, 1, 20, 4096, 0), "qubit"),
+    ((4096, 20, 2, 1, -2, 4096, 0), "qubit"),
+    ((4100, 20, 2, 1, 0, 4096, 0), "misaligned"),
+    ((4096, 22, 1, 65, 0, 4096, 0), "scratch"),     # 65 * 1024 partial sums
+    ((4096, 10, 1, 65536, 0, 4096, 0), "batch"),
+])
+def test_noalloc_readout_rejects_before_any_launch(args, what):
+    """Argument errors of the allocation-free readout are found on the host
+    before any HIP call (the pointers here are never dereferenced)."""
+    L = P.lib()
+    st = L.sv_expect_z_noalloc(*[ctypes.c_void_p(a) if i in (0, 5, 6) else a for i, a in enumerate(args)])
+    assert st == P.sv.SV_EINVAL
+    assert what in P.last_error()
