@@ -224,7 +224,16 @@ void *sv_device_ptr(sv_state s);
  *                         next pass needs onto the contiguous low index bits
  *                         (each pass stores its tile with its own bits
  *                         permuted; the state is back in canonical order
- *                         when sv_apply_circuit's work completes); 0: off. */
+ *                         when sv_apply_circuit's work completes); 0: off.
+ *   SV_OPT_PIPELINE       0 (default): one workgroup per tile; 1: passes over
+ *                         more tiles than the device holds at once run in a
+ *                         persistent kernel whose workgroups load their next
+ *                         tile while they apply the pass to the current one
+ *                         (LDS exchanges through a half-tile buffer); 2: the
+ *                         same with a full-tile buffer. All give the same
+ *                         results; 1 and 2 hold two tiles in registers, run at
+ *                         fewer waves per SIMD and measured slower on gfx950
+ *                         (kept for timing comparisons). */
 enum sv_option {
     SV_OPT_FUSE = 1,
     SV_OPT_MIN_LOW_QUBITS = 2,
@@ -232,7 +241,8 @@ enum sv_option {
     SV_OPT_ON_DEMAND_H = 4,
     SV_OPT_SMALL_PATH = 5,
     SV_OPT_PROFILE = 6,
-    SV_OPT_REMAP = 7
+    SV_OPT_REMAP = 7,
+    SV_OPT_PIPELINE = 8
 };
 sv_status sv_set_option(sv_state s, int option, int64_t value);
 

@@ -206,7 +206,7 @@ sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const s
         SV_HIP(launch_pass((int)s->dt, state, N, batch, dpass, (int)i, p.passes[i],
                            reinterpret_cast<const DevLayout *>(d + L.layouts),
                            reinterpret_cast<const DevOp *>(d + L.ops), (uint64_t)p.ops.size(),
-                           s->stream),
+                           s->pipeline, s->stream),
                "launch k_pass");
         if (s->profile && ea && eb) {
             hipEventRecord(eb, s->stream);
@@ -544,6 +544,10 @@ sv_status sv_set_option(sv_state s, int option, int64_t value) {
         case SV_OPT_REMAP:
             if (value != 0 && value != 1) return fail(SV_EINVAL, "SV_OPT_REMAP takes 0 or 1");
             s->remap = value != 0;
+            return SV_OK;
+        case SV_OPT_PIPELINE:
+            if (value < 0 || value > 2) return fail(SV_EINVAL, "SV_OPT_PIPELINE takes 0, 1 or 2");
+            s->pipeline = (int)value;
             return SV_OK;
         default:
             return fail(SV_EINVAL, "unknown option %d", option);

@@ -66,6 +66,7 @@ struct sv_state_s {
     bool gen_h = true;
     int small_mode = 1;
     bool remap = true;
+    int pipeline = 0;   // SV_OPT_PIPELINE
     bool profile = false;
 
     // plan upload: pinned staging + device copy

@@ -480,104 +480,121 @@ __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
     return (src & ~SRC_POS_MASK) == SRC_THR ? (tid >> pos) & 1 : (int)((base >> pos) & 1);
 }
 
-// D2: the variant that also executes OP_DENSE2 (its 4x4 needs many more
-// registers; passes without it run the lean variant). FX: exchanges move the
-// whole tile through a full-tile LDS buffer (2 barriers each instead of 4);
-// for launches too small to fill the chip, where the pass is latency-bound
-// and LDS does not limit occupancy.
-template <typename T, bool D2, bool FX>
-__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
-                                              const DevPass *__restrict__ passes, int pass_idx,
-                                              const DevLayout *__restrict__ layouts,
-                                              const DevOp *__restrict__ ops, uint64_t ops_stride) {
-    constexpr int R = PassTraits<T>::R;
-    constexpr int W = PassTraits<T>::W;
-    constexpr int NR = 1 << R;
-    constexpr int SH = sizeof(T) == 8 ? 4 : 3;   // log2 of the slot size in bytes
-    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];   // a tile, or half a tile
-    char *const ldsb = reinterpret_cast<char *>(lds);
-
-    const DevPass &P = passes[pass_idx];
-    const int tid = threadIdx.x;
-    const int k = P.k;
-    const DevLayout *LB = layouts + P.layout_begin;
-    cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
-    const DevOp *opb = ops + (uint64_t)blockIdx.y * ops_stride;
-
-    // Global index of the tile's amplitude with all tile-local bits zero:
-    // the tile number with zeros inserted at the tile qubits (ascending).
-    // (q[] is read as aligned 32-bit words: scalar loads, not byte loads)
-    const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
-    uint32_t qv[7];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) qv[i] = qw[i];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));   // one batch of scalar loads
-    uint64_t base = xcd_tile(blockIdx.x, gridDim.x);
+// Global index of a tile's amplitude with all tile-local bits zero: the tile
+// number with zeros inserted at the tile qubits (ascending). qv holds the
+// pass's qubit list as aligned 32-bit words (scalar loads, not byte loads).
+__device__ __forceinline__ uint64_t tile_base(const uint32_t (&qv)[7], int k, uint64_t tile) {
+    uint64_t base = tile;
 #pragma unroll
     for (int l = 0; l < 28; ++l) {
         if (l >= k) break;
         const int b = (qv[l >> 2] >> (8 * (l & 3))) & 0xFF;
         base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
     }
+    return base;
+}
 
-    // Bring the pass's op records and layout tables into L2 with one vector
-    // load per 64-byte line, issued before the tile loads: the interpreter
-    // then reads them one after another through the scalar cache without
-    // waiting on HBM.
+// Bring the pass's op records and layout tables into L2 with one vector load
+// per 64-byte line: the interpreter then reads them one after another through
+// the scalar cache without waiting on HBM. Returns a value for the caller to
+// consume (after its tile loads are issued).
+template <int W>
+__device__ __forceinline__ uint32_t warm_records(const DevOp *opb, const DevPass &P, const DevLayout *LB,
+                                                 int tid) {
     uint32_t warm = 0;
-    {
-        const uint32_t *w = reinterpret_cast<const uint32_t *>(opb + P.op_begin);
-        const uint32_t nw = (uint32_t)(P.op_end - P.op_begin) * (uint32_t)(sizeof(DevOp) / 4);
-        for (uint32_t i = (uint32_t)tid * 16u; i < nw; i += (1u << W) * 16u) warm ^= w[i];
-        const uint32_t *wl = reinterpret_cast<const uint32_t *>(LB);
-        const uint32_t nl = (uint32_t)P.n_layouts * (uint32_t)(sizeof(DevLayout) / 4);
-        for (uint32_t i = (uint32_t)tid * 16u; i < nl; i += (1u << W) * 16u) warm ^= wl[i];
-    }
-    cpx<T> a[NR];
-    {
-        // Global index of slot j: (base | thread part) XOR the register part,
-        // accumulated along a Gray-code walk over the register bits (the
-        // parts occupy disjoint bits), so only R per-bit offsets stay live.
-        const DevLayout &L = LB[0];
-        uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
-        if (P.flags & PASS_GENERATE) {
-            // On-demand Hadamard-layer amplitudes of H^M |j>:
-            // 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M.
-            const uint64_t gm = P.gen_mask, gj = P.gen_j;
-            const T mag = (T)P.gen_scale;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(opb + P.op_begin);
+    const uint32_t nw = (uint32_t)(P.op_end - P.op_begin) * (uint32_t)(sizeof(DevOp) / 4);
+    for (uint32_t i = (uint32_t)tid * 16u; i < nw; i += (1u << W) * 16u) warm ^= w[i];
+    const uint32_t *wl = reinterpret_cast<const uint32_t *>(LB);
+    const uint32_t nl = (uint32_t)P.n_layouts * (uint32_t)(sizeof(DevLayout) / 4);
+    for (uint32_t i = (uint32_t)tid * 16u; i < nl; i += (1u << W) * 16u) warm ^= wl[i];
+    return warm;
+}
+
+// Load the thread's register slots of the tile at `base` in layout L. The
+// global index of slot j is (base | thread part) XOR the register part,
+// accumulated along a Gray-code walk over the register bits (the parts occupy
+// disjoint bits), so only R per-bit offsets stay live.
+template <typename T, int R, int W>
+__device__ __forceinline__ void load_tile(cpx<T> (&a)[1 << R], const cpx<T> *st, const DevLayout &L,
+                                          uint64_t base, int tid) {
+    constexpr int NR = 1 << R;
+    uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
+    if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
+        // slots 2m and 2m + 1 are adjacent in memory (register bit 0 is
+        // label 0): one 16-byte access; walk the other register bits
 #pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
-                const bool on = ((idx ^ gj) & ~gm) == 0;
-                const T v = (__popcll(idx & gj & gm) & 1) ? -mag : mag;
-                a[i ^ (i >> 1)] = mk<T>(on ? v : (T)0, (T)0);
-            }
-        } else if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
-            // slots 2m and 2m + 1 are adjacent in memory (register bit 0 is
-            // label 0): one 16-byte access; walk the other register bits
+        for (int i = 0; i < NR / 2; ++i) {
+            if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
+            const int j = (i ^ (i >> 1)) << 1;
+            cpx<float> a0, a1;
+            ld_stream2(reinterpret_cast<const cpx<float> *>(st + idx), a0, a1);
+            a[j] = mk<T>((T)a0.x, (T)a0.y);
+            a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
+        }
+    } else {
 #pragma unroll
-            for (int i = 0; i < NR / 2; ++i) {
-                if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
-                const int j = (i ^ (i >> 1)) << 1;
-                cpx<float> a0, a1;
-                ld_stream2(reinterpret_cast<const cpx<float> *>(st + idx), a0, a1);
-                a[j] = mk<T>((T)a0.x, (T)a0.y);
-                a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
-                a[i ^ (i >> 1)] = ld_stream(st + idx);
-            }
+        for (int i = 0; i < NR; ++i) {
+            if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+            a[i ^ (i >> 1)] = ld_stream(st + idx);
         }
     }
+}
 
-    asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
+// On-demand Hadamard-layer amplitudes of H^M |j> in place of a load:
+// 2^(-|M|/2) (-1)^popcount(i & j & M) where i agrees with j off M, else 0.
+template <typename T, int R, int W>
+__device__ __forceinline__ void generate_tile(cpx<T> (&a)[1 << R], const DevPass &P, const DevLayout &L,
+                                              uint64_t base, int tid) {
+    constexpr int NR = 1 << R;
+    uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
+    const uint64_t gm = P.gen_mask, gj = P.gen_j;
+    const T mag = (T)P.gen_scale;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+        const bool on = ((idx ^ gj) & ~gm) == 0;
+        const T v = (__popcll(idx & gj & gm) & 1) ? -mag : mag;
+        a[i ^ (i >> 1)] = mk<T>(on ? v : (T)0, (T)0);
+    }
+}
+
+template <typename T, int R, int W>
+__device__ __forceinline__ void store_tile(const cpx<T> (&a)[1 << R], cpx<T> *st, const DevLayout &L,
+                                           uint64_t base, int tid) {
+    constexpr int NR = 1 << R;
+    uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
+    if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
+#pragma unroll
+        for (int i = 0; i < NR / 2; ++i) {
+            if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
+            const int j = (i ^ (i >> 1)) << 1;
+            st_stream2(reinterpret_cast<cpx<float> *>(st + idx), mk<float>((float)a[j].x, (float)a[j].y),
+                       mk<float>((float)a[j + 1].x, (float)a[j + 1].y));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < NR; ++i) {
+            if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
+            st_stream(st + idx, a[i ^ (i >> 1)]);
+        }
+    }
+}
+
+// The pass's operation list on one register tile: a host-built program read
+// record by record (the next one prefetched) through the scalar cache.
+// D2: the variant that also executes OP_DENSE2 (its 4x4 needs many more
+// registers; passes without it run the lean variant). FX: exchanges move the
+// whole tile through a full-tile LDS buffer (2 barriers each instead of 4).
+template <typename T, bool D2, bool FX>
+__device__ __forceinline__ void run_ops(cpx<T> (&a)[1 << PassTraits<T>::R], const DevOp *opb, int oi,
+                                        const int oe, const DevLayout *LB, const uint64_t base,
+                                        const int tid, char *const ldsb) {
+    constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
+    constexpr int NR = 1 << R;
+    constexpr int SH = sizeof(T) == 8 ? 4 : 3;   // log2 of the slot size in bytes
     cpx<T> f = mk<T>((T)1, (T)0);   // per-thread diagonal factor (OP_UDN)
-    const int oe = P.op_end;
-    int oi = P.op_begin;
     if (oi < oe) {
         const OpRec *recs = reinterpret_cast<const OpRec *>(opb);
         OpRec op = recs[oi];
@@ -807,26 +824,145 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
             op = nxt;
         }
     }
+}
+
+// One workgroup per tile (grid: tiles x batch). FX: full-tile exchanges, for
+// launches too small to fill the chip, where the pass is latency-bound and LDS
+// does not limit occupancy.
+template <typename T, bool D2, bool FX>
+__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
+                                              const DevPass *__restrict__ passes, int pass_idx,
+                                              const DevLayout *__restrict__ layouts,
+                                              const DevOp *__restrict__ ops, uint64_t ops_stride) {
+    constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
+    constexpr int NR = 1 << R;
+    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];   // a tile, or half a tile
+    char *const ldsb = reinterpret_cast<char *>(lds);
+
+    const DevPass &P = passes[pass_idx];
+    const int tid = threadIdx.x;
+    const DevLayout *LB = layouts + P.layout_begin;
+    cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
+    const DevOp *opb = ops + (uint64_t)blockIdx.y * ops_stride;
+
+    const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
+    uint32_t qv[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) qv[i] = qw[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));   // one batch of scalar loads
+    const uint64_t base = tile_base(qv, P.k, xcd_tile(blockIdx.x, gridDim.x));
+
+    const uint32_t warm = warm_records<W>(opb, P, LB, tid);
+    cpx<T> a[NR];
+    if (P.flags & PASS_GENERATE)
+        generate_tile<T, R, W>(a, P, LB[0], base, tid);
+    else
+        load_tile<T, R, W>(a, st, LB[0], base, tid);
+    asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
+
+    run_ops<T, D2, FX>(a, opb, P.op_begin, P.op_end, LB, base, tid, ldsb);
 
     if (P.flags & PASS_SYNC_STORE) __syncthreads();
-    {
-        const DevLayout &L = LB[P.store_layout];
-        uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
-        if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
+    store_tile<T, R, W>(a, st, LB[P.store_layout], base, tid);
+}
+
+// Persistent variant for launches larger than the chip holds at once. Each
+// workgroup walks a sequence of (batch entry, tile) items and issues the loads
+// of its next tile before it runs the current tile's operations, so that its
+// own HBM traffic overlaps its arithmetic (one workgroup per tile runs its
+// load, ops and store one after another, and the workgroups sharing a CU
+// drift into the same phase: all loading, then all computing). Two tiles sit
+// in registers (about 170 VGPRs: three waves per SIMD). FX: exchanges through
+// a full-tile LDS buffer (2 barriers each, two workgroups per CU by LDS) or a
+// half-tile one (4 barriers each, three workgroups per CU). Items are split into 8 contiguous eighths, one
+// per XCD (workgroup g runs on XCD g mod 8), when grid and item count allow.
+// Every workgroup leaves its loop after a bounded number of items.
+template <typename T, bool FX>
+__global__ __launch_bounds__(1 << PassTraits<T>::W) __attribute__((amdgpu_waves_per_eu(2)))
+void k_pass_pipe(cpx<T> *__restrict__ state, uint64_t n_amps, const DevPass *__restrict__ passes,
+                 int pass_idx, const DevLayout *__restrict__ layouts, const DevOp *__restrict__ ops,
+                 uint64_t ops_stride, uint64_t n_items) {
+    constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
+    constexpr int NR = 1 << R;
+    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];
+    char *const ldsb = reinterpret_cast<char *>(lds);
+
+    const DevPass &P = passes[pass_idx];
+    const int tid = threadIdx.x;
+    const DevLayout *LB = layouts + P.layout_begin;
+    const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
+    uint32_t qv[7];
 #pragma unroll
-            for (int i = 0; i < NR / 2; ++i) {
-                if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
-                const int j = (i ^ (i >> 1)) << 1;
-                st_stream2(reinterpret_cast<cpx<float> *>(st + idx), mk<float>((float)a[j].x, (float)a[j].y),
-                           mk<float>((float)a[j + 1].x, (float)a[j + 1].y));
-            }
+    for (int i = 0; i < 7; ++i) qv[i] = qw[i];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));
+    const int tshift = __builtin_ctzll(P.tiles);   // tiles is a power of two
+    const uint64_t tmask = P.tiles - 1;
+    const bool gen = (P.flags & PASS_GENERATE) != 0;
+
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    uint64_t it, step, limit;
+    if ((G & 7u) == 0 && (n_items & 7u) == 0) {
+        const uint64_t eighth = n_items >> 3;
+        it = (uint64_t)(g & 7u) * eighth + (g >> 3);
+        step = G >> 3;
+        limit = (uint64_t)(g & 7u) * eighth + eighth;
+    } else {
+        it = g;
+        step = G;
+        limit = n_items;
+    }
+    if (it >= limit) return;
+
+    cpx<T> *st = state + (it >> tshift) * n_amps;
+    const DevOp *opb = ops + (it >> tshift) * ops_stride;
+    uint64_t base = tile_base(qv, P.k, it & tmask);
+    const uint32_t warm = warm_records<W>(opb, P, LB, tid);
+    // The register tile `a` is only ever written by register moves and
+    // arithmetic, never directly by loads (the first tile goes through `b`
+    // too): with loads in flight into `a` at the op loop's entry, the
+    // compiler's wait counting would put full waits inside the op handlers,
+    // and in later iterations those would also wait for the prefetch and the
+    // previous tile's stores.
+    cpx<T> a[NR], b[NR];
+    if (gen) {
+        generate_tile<T, R, W>(a, P, LB[0], base, tid);
+    } else {
+        load_tile<T, R, W>(b, st, LB[0], base, tid);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) a[j] = b[j];
+    }
+    asm volatile("" : : "v"(warm));
+
+    for (;;) {
+        const uint64_t nit = it + step;
+        const bool more = nit < limit;
+        cpx<T> *nst = st;
+        const DevOp *nopb = opb;
+        uint64_t nbase = base;
+        if (more) {
+            nst = state + (nit >> tshift) * n_amps;
+            nopb = ops + (nit >> tshift) * ops_stride;
+            nbase = tile_base(qv, P.k, nit & tmask);
+            if (!gen) load_tile<T, R, W>(b, nst, LB[0], nbase, tid);   // in flight during the ops
+        }
+        run_ops<T, false, FX>(a, opb, P.op_begin, P.op_end, LB, base, tid, ldsb);
+        if (P.flags & PASS_SYNC_STORE) __syncthreads();
+        store_tile<T, R, W>(a, st, LB[P.store_layout], base, tid);
+        if (!more) break;
+        if (gen) {
+            generate_tile<T, R, W>(a, P, LB[0], nbase, tid);
         } else {
 #pragma unroll
-            for (int i = 0; i < NR; ++i) {
-                if (i) idx ^= L.reg_goff[__builtin_ctz(i)];
-                st_stream(st + idx, a[i ^ (i >> 1)]);
-            }
+            for (int j = 0; j < NR; ++j) a[j] = b[j];
         }
+        it = nit;
+        st = nst;
+        opb = nopb;
+        base = nbase;
     }
 }
 
@@ -1453,20 +1589,67 @@ hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch, ui
 // Launches of at most this many workgroups (two per CU) use full-tile exchanges.
 constexpr uint64_t kFullExchangeMaxBlocks = 512;
 
+// Workgroups of the persistent pass kernel that fit on the device at once
+// (occupancy x compute units), per precision; looked up once.
+template <typename T, bool FX>
+static hipError_t pipe_grid(uint64_t *out) {
+    static std::mutex mu;
+    static uint64_t cached = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(&k_pass_pipe<T, FX>), 1 << PassTraits<T>::W, 0);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+        cached = (uint64_t)per_cu * (uint64_t)cus;
+    }
+    *out = cached;
+    return hipSuccess;
+}
+
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const DevPass *d_passes,
                        int pass_idx, const DevPass &h_pass, const DevLayout *d_layouts,
-                       const DevOp *d_ops, uint64_t ops_stride, hipStream_t st) {
+                       const DevOp *d_ops, uint64_t ops_stride, int pipeline, hipStream_t st) {
     // The kernel is compiled for one tile geometry per precision; a pass that
     // does not match it is refused before launch.
     const int R = dt == 2 ? kRegBitsC128 : kRegBitsC64;
     const int W = dt == 2 ? kThreadBitsC128 : kThreadBitsC64;
     if (h_pass.w < kMinThreadBits || h_pass.w > W || h_pass.k != h_pass.w + R ||
-        h_pass.tiles != (n_amps >> h_pass.k) || (h_pass.tiles << h_pass.k) != n_amps)
+        h_pass.tiles != (n_amps >> h_pass.k) || (h_pass.tiles << h_pass.k) != n_amps ||
+        (h_pass.tiles & (h_pass.tiles - 1)) != 0)
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
     const dim3 block(1u << h_pass.w);
     const bool d2 = (h_pass.flags & PASS_DENSE2) != 0;
-    const bool fx = h_pass.tiles * (uint64_t)batch <= kFullExchangeMaxBlocks;
+    const uint64_t items = h_pass.tiles * (uint64_t)batch;
+    const bool fx = items <= kFullExchangeMaxBlocks;
+    if (pipeline && !d2 && !fx && h_pass.w == W) {
+        // persistent: as many workgroups as fit at once (a multiple of 8,
+        // so that each XCD walks its own eighth of the items)
+        const bool full = pipeline == 2;
+        uint64_t grid = 0;
+        hipError_t e = dt == 2 ? (full ? pipe_grid<double, true>(&grid) : pipe_grid<double, false>(&grid))
+                               : (full ? pipe_grid<float, true>(&grid) : pipe_grid<float, false>(&grid));
+        if (e != hipSuccess) return e;
+        if (grid >= 8) grid &= ~(uint64_t)7;
+        if (grid > items) grid = items;
+#define SV_PIPE(TT, FXV)                                                                                  \
+    hipLaunchKernelGGL((k_pass_pipe<TT, FXV>), dim3((unsigned)grid), block, 0, st, (cpx<TT> *)state, n_amps, \
+                       d_passes, pass_idx, d_layouts, d_ops, ops_stride, items)
+        if (dt == 2) {
+            if (full) SV_PIPE(double, true);
+            else SV_PIPE(double, false);
+        } else {
+            if (full) SV_PIPE(float, true);
+            else SV_PIPE(float, false);
+        }
+#undef SV_PIPE
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
 #define SV_PASS(TT, D2V, FXV)                                                                         \
     hipLaunchKernelGGL((k_pass<TT, D2V, FXV>), grid, block, 0, st, (cpx<TT> *)state, n_amps, d_passes, \
                        pass_idx, d_layouts, d_ops, ops_stride)

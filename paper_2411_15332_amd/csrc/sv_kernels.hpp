@@ -35,10 +35,15 @@ constexpr int kSmallMaxQubitsC64 = 13;
 hipError_t launch_fill_basis(int dt, void *state, uint64_t n_amps, int batch,
                              uint64_t j, hipStream_t st);
 
+// One pass over `batch` states. pipeline 1 (2): passes of more tiles than
+// fit on the device at once run in the persistent kernel that loads each
+// workgroup's next tile during the current one's operations, exchanging
+// through a half-tile (full-tile) LDS buffer; 0: one workgroup per tile.
+// Passes with a 4x4 gate and small launches always run one workgroup per tile.
 hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch,
                        const DevPass *d_passes, int pass_idx, const DevPass &h_pass,
                        const DevLayout *d_layouts, const DevOp *d_ops, uint64_t ops_stride,
-                       hipStream_t st);
+                       int pipeline, hipStream_t st);
 
 hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_ops,
                         int n_ops, const void *d_consts, uint64_t const_stride,

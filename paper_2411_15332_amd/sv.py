@@ -30,6 +30,7 @@ THREE_QUBIT_KINDS = ("CCX", "CSWAP")
 
 OPT_FUSE, OPT_MIN_LOW_QUBITS, OPT_MAX_DENSE, OPT_ON_DEMAND_H, OPT_SMALL_PATH, OPT_PROFILE, OPT_REMAP = \
     1, 2, 3, 4, 5, 6, 7
+OPT_PIPELINE = 8
 
 # struct sv_gate (32 bytes)
 GATE_DTYPE = np.dtype([("kind", "<i4"), ("q0", "<i4"), ("q1", "<i4"), ("param", "<i4"),
