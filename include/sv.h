@@ -114,6 +114,7 @@ typedef struct sv_state_s *sv_state;
  *          bytes, 256-byte aligned, that the library borrows: the caller keeps
  *          it alive until sv_free returns and the stream work has completed.
  * hip_stream: a hipStream_t or NULL (default stream).
+ * |0...0> is recorded, not written: see sv_set_basis.
  * Errors: SV_EINVAL (bad n, dtype, batch, size or alignment), SV_ENOMEM. */
 sv_status sv_alloc(int n_qubits, sv_dtype dtype, int batch, void *dev_buf,
                    size_t buf_bytes, void *hip_stream, sv_state *out);
@@ -124,7 +125,12 @@ sv_status sv_free(sv_state s);
 /* Use another HIP stream for the handle's later work. */
 sv_status sv_set_stream(sv_state s, void *hip_stream);
 
-/* Set every state of the batch to the basis state |j>, j < 2^n. */
+/* Set every state of the batch to the basis state |j>, j < 2^n.
+ * Like the |0...0> of sv_alloc, the basis state is only recorded here: the
+ * first pass of the next sv_apply_circuit generates its amplitudes instead of
+ * reading them (Sec. III-B's on-demand idea, with an empty Hadamard mask when
+ * no Hadamards lead the circuit), and a readout, sv_sync or sv_device_ptr
+ * that comes first writes them. Read the buffer directly only after sv_sync. */
 sv_status sv_set_basis(sv_state s, uint64_t j);
 
 /* The caller wrote the amplitudes through the device buffer (for example a
@@ -203,7 +209,8 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates,
 /* Wait for the handle's stream; reports asynchronous device faults. */
 sv_status sv_sync(sv_state s);
 
-/* Device pointer of batch entry 0 (amplitudes are contiguous). */
+/* Device pointer of batch entry 0 (amplitudes are contiguous). A recorded
+ * basis state is written first, asynchronously on the handle's stream. */
 void *sv_device_ptr(sv_state s);
 
 /* Tuning and testing options (values are validated, SV_EINVAL otherwise):

@@ -19,7 +19,9 @@ extern "C" {
  * tile (3..7, or 0 for the planner's choice), [2] dense gates per pass, [3] on-demand Hadamards (0/1),
  * [4] state is a known basis state (0/1), [5] that basis index, [6] small-path
  * mode (1 or 2), [7] qubit remapping (0/1) — the meanings of the matching
- * SV_OPT_* options.
+ * SV_OPT_* options — and [8] the basis state of [4]/[5] is only recorded, not
+ * yet written to memory (0/1: the first pass generates it, as after sv_alloc
+ * or sv_set_basis). opts, when given, holds these 9 values.
  * Layout of `out`: 256-byte header of int64 fields
  *   [0] small path, [1] passes, [2] layouts, [3] ops, [4] small ops,
  *   [5] constant reals per batch entry, [6] exchanges, [7] generated

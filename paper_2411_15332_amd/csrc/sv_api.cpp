@@ -65,9 +65,20 @@ PlanOptions plan_options(const sv_state_s *s) {
     o.gen_h = s->gen_h;
     o.basis_known = s->basis_known;
     o.basis_j = s->basis_j;
+    o.gen_basis = s->basis_known && s->fill_pending;
     o.small_mode = s->small_mode;
     o.remap = s->remap;
     return o;
+}
+
+// Write a recorded basis state into the buffer (sv_alloc and sv_set_basis
+// only record it, so that the next circuit's first pass can generate it
+// instead of reading a filled state).
+sv_status materialize(sv_state_s *s) {
+    if (!s->fill_pending) return SV_OK;
+    SV_HIP(launch_fill_basis((int)s->dt, s->buf, 1ull << s->n, s->batch, s->basis_j, s->stream), "launch fill");
+    s->fill_pending = false;
+    return SV_OK;
 }
 
 sv_status ensure_device_buf(void **p, size_t *cap, size_t need, const char *what) {
@@ -307,14 +318,11 @@ sv_status sv_alloc(int n_qubits, sv_dtype dtype, int batch, void *dev_buf, size_
             }
             s->owned = true;
         }
-        e = launch_fill_basis((int)dtype, s->buf, 1ull << n_qubits, batch, 0, s->stream);
-        if (e != hipSuccess) {
-            if (s->owned) hipFree(s->buf);
-            delete s;
-            return hip_fail(e, "launch fill");
-        }
+        // |0...0> is written by the first pass of the first circuit (generated,
+        // not read) or by materialize() before anything else reads the buffer
         s->basis_known = true;
         s->basis_j = 0;
+        s->fill_pending = true;
         *out = s;
         return SV_OK;
     });
@@ -347,9 +355,9 @@ sv_status sv_set_basis(sv_state s, uint64_t j) {
         sv_status st = check_handle(s);
         if (st != SV_OK) return st;
         if (j >= (1ull << s->n)) return fail(SV_EINVAL, "basis index %llu >= 2^%d", (unsigned long long)j, s->n);
-        SV_HIP(launch_fill_basis((int)s->dt, s->buf, 1ull << s->n, s->batch, j, s->stream), "launch fill");
         s->basis_known = true;
         s->basis_j = j;
+        s->fill_pending = true;
         return SV_OK;
     });
 }
@@ -358,6 +366,7 @@ sv_status sv_mark_modified(sv_state s) {
     return guarded([&]() -> sv_status {
         if (!s) return fail(SV_EINVAL, "null handle");
         s->basis_known = false;
+        s->fill_pending = false;
         return SV_OK;
     });
 }
@@ -386,12 +395,17 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
             s->plan_valid = true;
         }
         const Plan &p = s->plan;
+        if (s->fill_pending && (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATE))) {
+            st = materialize(s);   // this plan reads its input
+            if (st != SV_OK) return st;
+        }
         std::vector<double> ext;
         lower_params(s->plan_low, params, n_params, s->batch, ext);
         st = ext.empty() ? run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), params, n_params)
                          : run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), ext.data(),
                                     n_params + s->plan_low.src.size());
         if (st != SV_OK) return st;
+        s->fill_pending = false;   // the first pass generated the recorded basis state
         s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
         s->stats[1] = p.n_exch;
         s->stats[2] = p.gates_applied;
@@ -405,6 +419,8 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
 }
 
 static sv_status reduce(sv_state s, int qubit, double *out) {
+    sv_status st0 = materialize(s);
+    if (st0 != SV_OK) return st0;
     const size_t np = reduce_partials_size(s->n) * (size_t)s->batch + (size_t)s->batch;
     sv_status st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap,
                                      np * sizeof(double), "hipMalloc(reduce)");
@@ -479,6 +495,8 @@ sv_status sv_amplitudes(sv_state s, int b, const uint64_t *idx, size_t k, double
         const uint64_t N = 1ull << s->n;
         for (size_t i = 0; i < k; ++i)
             if (idx[i] >= N) return fail(SV_EINVAL, "index %llu >= 2^%d", (unsigned long long)idx[i], s->n);
+        st = materialize(s);
+        if (st != SV_OK) return st;
         const size_t need_host = std::max(k * sizeof(uint64_t), 2 * k * sizeof(double));
         st = ensure_host_buf(reinterpret_cast<void **>(&s->h_out), &s->h_out_cap, need_host, "hipHostMalloc");
         if (st != SV_OK) return st;
@@ -505,12 +523,21 @@ sv_status sv_sync(sv_state s) {
     return guarded([&]() -> sv_status {
         sv_status st = check_handle(s);
         if (st != SV_OK) return st;
+        st = materialize(s);
+        if (st != SV_OK) return st;
         SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
         return SV_OK;
     });
 }
 
-void *sv_device_ptr(sv_state s) { return s ? s->buf : nullptr; }
+void *sv_device_ptr(sv_state s) {
+    if (!s) return nullptr;
+    try {
+        materialize(s);   // a failed launch surfaces at the next synchronizing call
+    } catch (...) {
+    }
+    return s->buf;
+}
 
 sv_status sv_set_option(sv_state s, int option, int64_t value) {
     return guarded([&]() -> sv_status {
@@ -627,19 +654,23 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
         char *lam = psi + (size_t)B * state_bytes;
         const int dt = (int)s->dt;
 
-        // forward: psi = U |0...0> for every batch entry
-        SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
+        // forward: psi = U |0...0> for every batch entry (generated by the
+        // first pass when the plan has passes, else filled first)
         PlanOptions po = plan_options(s);
         po.basis_known = true;
         po.basis_j = 0;
+        po.gen_basis = true;
         {
             Plan p = build_plan(s->n, gates, n_gates, po);
+            if (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATE))
+                SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
             st = run_plan(s, psi, B, p, gates, params, n_params);
             if (st != SV_OK) return st;
         }
         SV_HIP(hipMemcpyAsync(s->buf, psi, (size_t)B * state_bytes, hipMemcpyDeviceToDevice, s->stream),
                "hipMemcpyAsync(final states)");
         s->basis_known = false;
+        s->fill_pending = false;
         // f = <Z_q> and lambda = Z_q psi
         double *d_out = s->d_red + reduce_partials_size(s->n) * (size_t)B;
         SV_HIP(launch_reduce(dt, psi, s->n, B, qubit, s->d_red, d_out, s->stream), "launch reduce");
@@ -818,6 +849,9 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
         tmp.basis_j = (uint64_t)opts[5];
         tmp.small_mode = (int)opts[6];
         tmp.remap = opts[7] != 0;
+        tmp.fill_pending = opts[8] != 0;
+    } else {
+        tmp.fill_pending = false;
     }
     const PlanOptions po = plan_options(&tmp);
     Lowering low;

@@ -58,6 +58,7 @@ struct sv_state_s {
 
     bool basis_known = true;
     uint64_t basis_j = 0;
+    bool fill_pending = false;   // basis_j recorded but not yet written to the buffer
 
     // options
     bool fuse = true;
@@ -113,6 +114,7 @@ namespace sv {
 
 PlanOptions plan_options(const sv_state_s *s);
 sv_status ensure_device_buf(void **p, size_t *cap, size_t need, const char *what);
+sv_status materialize(sv_state_s *s);
 sv_status ensure_host_buf(void **p, size_t *cap, size_t need, const char *what);
 // Upload plan `p` and launch it on `state` (`batch` states) on the handle's stream.
 sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const sv_gate *gates,

@@ -1186,7 +1186,7 @@ bool same_options(const PlanOptions &a, const PlanOptions &b) {
     return a.R == b.R && a.v == b.v && a.m == b.m && a.c == b.c && a.w_max == b.w_max &&
            a.fuse == b.fuse && a.remap == b.remap && a.max_dense == b.max_dense && a.auto_low == b.auto_low &&
            a.gen_h == b.gen_h && a.basis_known == b.basis_known &&
-           (!a.basis_known || a.basis_j == b.basis_j) && a.ud_max == b.ud_max &&
+           (!a.basis_known || a.basis_j == b.basis_j) && a.gen_basis == b.gen_basis && a.ud_max == b.ud_max &&
            a.small_max == b.small_max && a.small_mode == b.small_mode;
 }
 
@@ -1267,7 +1267,10 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             ++start;
         }
     }
-    const bool generate = opt.basis_known && opt.gen_h && gen_mask != 0;
+    // The first pass generates its input instead of reading it: the Hadamard
+    // layer of a basis state, or the basis state itself (empty mask:
+    // amp = [i == j]) when its memory was never written.
+    const bool generate = opt.basis_known && ((opt.gen_h && gen_mask != 0) || opt.gen_basis);
     P.n_gen_h = popc(gen_mask);
     P.gates_applied += P.n_gen_h;
 

@@ -110,6 +110,9 @@ struct PlanOptions {
     bool gen_h = true;    // generate leading Hadamards of a basis state
     bool basis_known = false;
     uint64_t basis_j = 0;
+    bool gen_basis = false;   // the memory does not hold that basis state yet: the
+                              // first pass generates it (an empty Hadamard mask
+                              // when no Hadamards lead the circuit)
     int ud_max = 3;       // terms of a merged uniform-diagonal operation
     int small_max = 12;   // largest n of the one-workgroup path
     int small_mode = 1;   // 1: use it below the tiled minimum; 2: whenever n allows

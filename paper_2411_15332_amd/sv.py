@@ -284,12 +284,13 @@ assert OP_DTYPE.itemsize == 80 and SOP_DTYPE.itemsize == 16
 def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] = None,
                fuse: bool = True, min_low: int = 6, max_dense: int = 1 << 20,
                gen_h: bool = True, basis: Optional[int] = 0, small_mode: int = 1,
-               remap: bool = True) -> dict:
+               remap: bool = True, basis_in_memory: bool = True) -> dict:
     """The plan sv_apply_circuit would run (no GPU needed): see include/sv_debug.h."""
     arr = np.ascontiguousarray(gate_array(gates))
     p = None if params is None else np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
     opts = np.array([int(fuse), min_low, max_dense, int(gen_h), int(basis is not None),
-                     0 if basis is None else basis, small_mode, int(remap)], dtype=np.int64)
+                     0 if basis is None else basis, small_mode, int(remap),
+                     int(basis is not None and not basis_in_memory)], dtype=np.int64)
     dt = SV_C128 if dtype == "c128" else SV_C64
     L = lib()
     need = L.sv_debug_plan(n, dt, _ptr(arr), len(arr), _ptr(p), 0 if p is None else len(p),

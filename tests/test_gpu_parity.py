@@ -140,6 +140,38 @@ def test_generation_then_gates(P):
     assert maxdiff(got, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [10, 16, 23])
+def test_recorded_basis_state(P, n, dtype):
+    """sv_set_basis only records |j>: the next circuit's first pass generates
+    it (tiled plans) or it is written first (the one-workgroup path), and a
+    readout that comes first writes it. The buffer holds another state
+    before every set_basis here, so a stale amplitude would show."""
+    tol = 1e-12 if dtype == "c128" else 1e-5
+    j = (0x5A5A5 * n) % (1 << n)
+    gates = synth.random_circuit(n, 3, 40 + n)
+    while gates[0].name == "H":
+        gates = gates[1:]
+    ref = O.simulate(n, gates, psi0=O.basis_state(n, j))
+    with P.StateVector(n, dtype) as sv:
+        sv.apply(synth.random_circuit(n, 2, 1))
+        sv.set_basis(j)
+        sv.apply(gates)
+        got = sv.numpy()[0].astype(np.complex128)
+        assert maxdiff(got, ref) <= tol
+        sv.set_basis(j)
+        amp = sv.amplitudes([j, (j + 1) % (1 << n), 0 if j else 1])
+        assert amp[0] == 1.0 and np.all(amp[1:] == 0.0)
+        sv.apply(synth.random_circuit(n, 1, 3))
+        sv.set_basis(j)
+        z = np.array([sv.expect_z(q)[0] for q in (0, n - 1)])
+        assert np.array_equal(z, np.array([1.0 - 2 * (j & 1), 1.0 - 2 * ((j >> (n - 1)) & 1)]))
+        sv.apply(synth.random_circuit(n, 1, 4))
+        sv.set_basis(j)
+        state = sv.numpy()[0]
+        assert state[j] == 1.0 and np.count_nonzero(state) == 1
+
+
 def _golden(name):
     with open(os.path.join(GOLDEN, name)) as f:
         return {ln.split()[0]: float(ln.split()[1]) for ln in f if ln.strip() and not ln.startswith("#")}

@@ -379,3 +379,24 @@ def test_noalloc_readout_rejects_before_any_launch(args, what):
     st = L.sv_expect_z_noalloc(*[ctypes.c_void_p(a) if i in (0, 5, 6) else a for i, a in enumerate(args)])
     assert st == P.sv.SV_EINVAL
     assert what in P.last_error()
+
+
+@pytest.mark.parametrize("n,dtype,basis", [(13, "c128", 0), (15, "c128", 12345), (14, "c64", 77),
+                                           (16, "c64", 0)])
+@pytest.mark.parametrize("lead_h", [False, True])
+def test_recorded_basis_state_is_generated_by_the_first_pass(n, dtype, basis, lead_h):
+    """sv_alloc / sv_set_basis only record the basis state; the plan's first
+    pass then generates it (with or without leading Hadamards), so whatever the
+    buffer held before must not leak into the result."""
+    gates = synth.random_circuit(n, 3, n + basis)
+    if lead_h:
+        gates = [synth.Gate("H", q) for q in range(0, n, 3)] + gates
+    else:
+        while gates[0].name == "H":
+            gates = gates[1:]
+    ref = O.simulate(n, gates, psi0=O.basis_state(n, basis))
+    plan = P.debug_plan(n, gates, dtype=dtype, basis=basis, basis_in_memory=False)
+    assert not plan["small"] and int(plan["passes"][0]["flags"]) & 1
+    garbage = np.random.default_rng(5).standard_normal(1 << n) * (1 + 1j)
+    got = run_plan(plan, garbage, n)
+    assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
