@@ -258,7 +258,9 @@ sv_status sv_set_option(sv_state s, int option, int64_t value);
  * out[3] = leading Hadamards generated on demand, out[4] = kernel launches,
  * out[5] = algorithmic HBM bytes of the plan (2 * 2^n * amplitude bytes per
  * pass, one read fewer when a pass generates its input), per batch entry,
- * out[6] = permutation gates applied by relabelling the tile addressing. */
+ * out[6] = permutation gates applied by relabelling the tile addressing,
+ * out[7] = leading 1-qubit gates folded into a product state that the first
+ * pass generates instead of reading (amp[i] = prod_q u_q[bit q of i]). */
 sv_status sv_plan_stats(sv_state s, int64_t out[8]);
 
 /* With SV_OPT_PROFILE on: total milliseconds and count of the pass-kernel

@@ -30,6 +30,7 @@ extern "C" {
  *   arrays, [18] algorithmic HBM bytes, [19] relabelled permutation gates,
  *   [20] passes that only put qubits back on their own bits, [21] contiguous
  *   low qubits of every tile (opts[1], or the planner's choice when it is 0),
+ *   [22] leading 1-qubit gates folded into the generated product state,
  * followed by those arrays (constants in the state's precision: FP64 for
  * SV_C128, FP32 for SV_C64; batch entry 0).
  * Returns the number of bytes the dump needs (nothing is written when `out`

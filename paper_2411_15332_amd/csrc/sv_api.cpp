@@ -221,7 +221,7 @@ sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const s
                "launch k_pass");
         if (s->profile && ea && eb) {
             hipEventRecord(eb, s->stream);
-            const bool gen = (p.passes[i].flags & PASS_GENERATE) != 0;
+            const bool gen = (p.passes[i].flags & PASS_GENERATES) != 0;
             s->timed.push_back({ea, eb, gen ? io_bytes * 0.5 : io_bytes});
         }
     }
@@ -261,7 +261,7 @@ int64_t plan_hbm_bytes(const Plan &p, int n, size_t amp_bytes) {
     if (p.small) return p.sops.empty() ? 0 : 2 * N * (int64_t)amp_bytes;
     int64_t b = 0;
     for (const DevPass &dp : p.passes)
-        b += ((dp.flags & PASS_GENERATE) ? 1 : 2) * N * (int64_t)amp_bytes;
+        b += ((dp.flags & PASS_GENERATES) ? 1 : 2) * N * (int64_t)amp_bytes;
     return b;
 }
 
@@ -395,7 +395,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
             s->plan_valid = true;
         }
         const Plan &p = s->plan;
-        if (s->fill_pending && (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATE))) {
+        if (s->fill_pending && (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATES))) {
             st = materialize(s);   // this plan reads its input
             if (st != SV_OK) return st;
         }
@@ -413,6 +413,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
         s->stats[4] = p.small ? (p.sops.empty() ? 0 : 1) : (int64_t)p.passes.size();
         s->stats[5] = plan_hbm_bytes(p, s->n, s->amp_bytes);
         s->stats[6] = p.n_relabel;
+        s->stats[7] = p.n_gen_product;
         if (p.gates_applied > 0) s->basis_known = false;
         return SV_OK;
     });
@@ -662,7 +663,7 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
         po.gen_basis = true;
         {
             Plan p = build_plan(s->n, gates, n_gates, po);
-            if (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATE))
+            if (p.small || p.passes.empty() || !(p.passes[0].flags & PASS_GENERATES))
                 SV_HIP(launch_fill_basis(dt, psi, N, B, 0, s->stream), "launch fill");
             st = run_plan(s, psi, B, p, gates, params, n_params);
             if (st != SV_OK) return st;
@@ -897,6 +898,7 @@ static int64_t debug_plan_impl(int n, int dtype, const sv_gate *gates, size_t n_
     h[19] = p.n_relabel;
     h[20] = p.n_restore;
     h[21] = p.low;
+    h[22] = p.n_gen_product;
     serialize_plan(p, L, gates, params, n_params, 1, dtype == SV_C64, o + header);
     return (int64_t)total;
 }

@@ -559,6 +559,47 @@ __device__ __forceinline__ void generate_tile(cpx<T> (&a)[1 << R], const DevPass
     }
 }
 
+// On-demand product state in place of a load: amp[i] = prod_q u_q[bit q of i]
+// with u_q = (u_q0, u_q1) read in FP64 from the pass's OP_GENP record and its
+// continuation records (`gp` points at the OP_GENP record; n qubits, two per
+// record). The factor of every qubit that no register bit holds is the same
+// for all of the thread's slots: formed in FP64 and rounded once. The register
+// bits' qubits then double a table over the slots.
+template <typename T, int R, int W>
+__device__ __forceinline__ void generate_product(cpx<T> (&a)[1 << R], const DevLayout &L, uint64_t base,
+                                                 int tid, const OpRec *gp, int n) {
+    const uint64_t idx0 = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;   // slot 0
+    uint64_t regmask = 0;
+#pragma unroll
+    for (int p = 0; p < R; ++p) regmask |= L.reg_goff[p];
+    cpx<double> c = mk<double>(1.0, 0.0);
+    for (int q = 0; q < n; ++q) {
+        if ((regmask >> q) & 1) continue;
+        const OpRec &r = gp[q >> 1];
+        const int e = (q & 1) * 4;
+        const cpx<double> u0 = mk<double>(pl<double>(r, e), pl<double>(r, e + 1));
+        const cpx<double> u1 = mk<double>(pl<double>(r, e + 2), pl<double>(r, e + 3));
+        c = cmul(c, ((idx0 >> q) & 1) ? u1 : u0);
+    }
+    a[0] = mk<T>((T)c.x, (T)c.y);
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+        const int q = __builtin_ctzll(L.reg_goff[p]);
+        const OpRec &r = gp[q >> 1];
+        const int e = (q & 1) * 4;
+        const cpx<T> u0 = mk<T>((T)pl<double>(r, e), (T)pl<double>(r, e + 1));
+        const cpx<T> u1 = mk<T>((T)pl<double>(r, e + 2), (T)pl<double>(r, e + 3));
+        // slot 0 has bit q of idx0; a slot with register bit p set has the other
+        const bool b0 = (idx0 >> q) & 1;
+        const cpx<T> lo = b0 ? u1 : u0, hi = b0 ? u0 : u1;
+#pragma unroll
+        for (int j = 0; j < (1 << p); ++j) {
+            a[j | (1 << p)] = cmul(a[j], hi);
+            a[j] = cmul(a[j], lo);
+        }
+    }
+}
+
 template <typename T, int R, int W>
 __device__ __forceinline__ void store_tile(const cpx<T> (&a)[1 << R], cpx<T> *st, const DevLayout &L,
                                            uint64_t base, int tid) {
@@ -828,8 +869,11 @@ __device__ __forceinline__ void run_ops(cpx<T> (&a)[1 << PassTraits<T>::R], cons
 
 // One workgroup per tile (grid: tiles x batch). FX: full-tile exchanges, for
 // launches too small to fill the chip, where the pass is latency-bound and LDS
-// does not limit occupancy.
-template <typename T, bool D2, bool FX>
+// does not limit occupancy. GEN: the pass generates its input (a Hadamard
+// layer or basis state, or a product state) instead of loading it; only a
+// circuit's first pass does, and the generating code lives in its own variant
+// so that it does not weigh on the register allocation of the others.
+template <typename T, bool D2, bool FX, bool GEN>
 __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
                                               const DevPass *__restrict__ passes, int pass_idx,
                                               const DevLayout *__restrict__ layouts,
@@ -856,13 +900,22 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
 
     const uint32_t warm = warm_records<W>(opb, P, LB, tid);
     cpx<T> a[NR];
-    if (P.flags & PASS_GENERATE)
-        generate_tile<T, R, W>(a, P, LB[0], base, tid);
-    else
+    int op_first = P.op_begin;
+    if constexpr (GEN) {
+        if (P.flags & PASS_GEN_PRODUCT) {
+            // the OP_GENP record and its continuations hold the product data
+            const OpRec *gp = reinterpret_cast<const OpRec *>(opb) + P.op_begin;
+            generate_product<T, R, W>(a, LB[0], base, tid, gp, gp->a());
+            op_first += 1 + (int)gp->b();
+        } else {
+            generate_tile<T, R, W>(a, P, LB[0], base, tid);
+        }
+    } else {
         load_tile<T, R, W>(a, st, LB[0], base, tid);
+    }
     asm volatile("" : : "v"(warm));   // the warming loads complete before the ops
 
-    run_ops<T, D2, FX>(a, opb, P.op_begin, P.op_end, LB, base, tid, ldsb);
+    run_ops<T, D2, FX>(a, opb, op_first, P.op_end, LB, base, tid, ldsb);
 
     if (P.flags & PASS_SYNC_STORE) __syncthreads();
     store_tile<T, R, W>(a, st, LB[P.store_layout], base, tid);
@@ -878,7 +931,8 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
 // a full-tile LDS buffer (2 barriers each, two workgroups per CU by LDS) or a
 // half-tile one (4 barriers each, three workgroups per CU). Items are split into 8 contiguous eighths, one
 // per XCD (workgroup g runs on XCD g mod 8), when grid and item count allow.
-// Every workgroup leaves its loop after a bounded number of items.
+// Every workgroup leaves its loop after a bounded number of items. Passes that
+// generate their input do not run here.
 template <typename T, bool FX>
 __global__ __launch_bounds__(1 << PassTraits<T>::W) __attribute__((amdgpu_waves_per_eu(2)))
 void k_pass_pipe(cpx<T> *__restrict__ state, uint64_t n_amps, const DevPass *__restrict__ passes,
@@ -901,7 +955,6 @@ void k_pass_pipe(cpx<T> *__restrict__ state, uint64_t n_amps, const DevPass *__r
     for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));
     const int tshift = __builtin_ctzll(P.tiles);   // tiles is a power of two
     const uint64_t tmask = P.tiles - 1;
-    const bool gen = (P.flags & PASS_GENERATE) != 0;
 
     const uint32_t G = gridDim.x, g = blockIdx.x;
     uint64_t it, step, limit;
@@ -928,13 +981,9 @@ void k_pass_pipe(cpx<T> *__restrict__ state, uint64_t n_amps, const DevPass *__r
     // and in later iterations those would also wait for the prefetch and the
     // previous tile's stores.
     cpx<T> a[NR], b[NR];
-    if (gen) {
-        generate_tile<T, R, W>(a, P, LB[0], base, tid);
-    } else {
-        load_tile<T, R, W>(b, st, LB[0], base, tid);
+    load_tile<T, R, W>(b, st, LB[0], base, tid);
 #pragma unroll
-        for (int j = 0; j < NR; ++j) a[j] = b[j];
-    }
+    for (int j = 0; j < NR; ++j) a[j] = b[j];
     asm volatile("" : : "v"(warm));
 
     for (;;) {
@@ -947,18 +996,14 @@ void k_pass_pipe(cpx<T> *__restrict__ state, uint64_t n_amps, const DevPass *__r
             nst = state + (nit >> tshift) * n_amps;
             nopb = ops + (nit >> tshift) * ops_stride;
             nbase = tile_base(qv, P.k, nit & tmask);
-            if (!gen) load_tile<T, R, W>(b, nst, LB[0], nbase, tid);   // in flight during the ops
+            load_tile<T, R, W>(b, nst, LB[0], nbase, tid);   // in flight during the ops
         }
         run_ops<T, false, FX>(a, opb, P.op_begin, P.op_end, LB, base, tid, ldsb);
         if (P.flags & PASS_SYNC_STORE) __syncthreads();
         store_tile<T, R, W>(a, st, LB[P.store_layout], base, tid);
         if (!more) break;
-        if (gen) {
-            generate_tile<T, R, W>(a, P, LB[0], nbase, tid);
-        } else {
 #pragma unroll
-            for (int j = 0; j < NR; ++j) a[j] = b[j];
-        }
+        for (int j = 0; j < NR; ++j) a[j] = b[j];
         it = nit;
         st = nst;
         opb = nopb;
@@ -1626,7 +1671,8 @@ hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const De
     const bool d2 = (h_pass.flags & PASS_DENSE2) != 0;
     const uint64_t items = h_pass.tiles * (uint64_t)batch;
     const bool fx = items <= kFullExchangeMaxBlocks;
-    if (pipeline && !d2 && !fx && h_pass.w == W) {
+    const bool gen = (h_pass.flags & PASS_GENERATES) != 0;
+    if (pipeline && !d2 && !fx && !gen && h_pass.w == W) {
         // persistent: as many workgroups as fit at once (a multiple of 8,
         // so that each XCD walks its own eighth of the items)
         const bool full = pipeline == 2;
@@ -1650,9 +1696,15 @@ hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const De
         return hipGetLastError();
     }
     const dim3 grid((unsigned)h_pass.tiles, (unsigned)batch);
-#define SV_PASS(TT, D2V, FXV)                                                                         \
-    hipLaunchKernelGGL((k_pass<TT, D2V, FXV>), grid, block, 0, st, (cpx<TT> *)state, n_amps, d_passes, \
-                       pass_idx, d_layouts, d_ops, ops_stride)
+#define SV_PASS(TT, D2V, FXV)                                                                              \
+    do {                                                                                                   \
+        if (gen)                                                                                           \
+            hipLaunchKernelGGL((k_pass<TT, D2V, FXV, true>), grid, block, 0, st, (cpx<TT> *)state, n_amps,  \
+                               d_passes, pass_idx, d_layouts, d_ops, ops_stride);                          \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_pass<TT, D2V, FXV, false>), grid, block, 0, st, (cpx<TT> *)state, n_amps, \
+                               d_passes, pass_idx, d_layouts, d_ops, ops_stride);                          \
+    } while (0)
     if (dt == 2) {
         if (d2) {
             if (fx) SV_PASS(double, true, true);

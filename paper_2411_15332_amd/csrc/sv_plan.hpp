@@ -70,6 +70,10 @@ enum OpCode : uint8_t {
     OP_CCX = 23,       // swap the pairs of register bit a in the slots j with
                        // (j & b) == data byte 0 (register controls), in the threads where
                        // the bits of sources sa, sb (0xFF: none) equal bits 0, 1 of data byte 1
+    OP_GENP = 24,      // product-state generation data of a PASS_GEN_PRODUCT pass (its first
+                       // record; not executed): for qubit q, u_q = (u_q0, u_q1) complex FP64
+                       // (both precisions) in record q / 2 at entries 4 (q % 2) .. + 3,
+                       // continued in the b OP_CONT records after it; a = n
 };
 
 constexpr uint8_t kNoSource = 0xFF;
@@ -121,6 +125,9 @@ enum : uint32_t {
     PASS_SYNC_STORE = 2u,   // barrier before the store: the store layout moves amplitudes
                             // between waves and no exchange has separated loads from stores
     PASS_DENSE2 = 4u,       // the pass holds OP_DENSE2 (run by the kernel variant with it)
+    PASS_GEN_PRODUCT = 8u,  // no load: the product state amp[i] = prod_q u_q[bit q of i]
+                            // generated in place (u from the pass's OP_GENP records)
+    PASS_GENERATES = PASS_GENERATE | PASS_GEN_PRODUCT,   // the pass reads nothing
 };
 
 struct DevPass {      // 96 bytes

@@ -1267,12 +1267,32 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
             ++start;
         }
     }
-    // The first pass generates its input instead of reading it: the Hadamard
-    // layer of a basis state, or the basis state itself (empty mask:
-    // amp = [i == j]) when its memory was never written.
-    const bool generate = opt.basis_known && ((opt.gen_h && gen_mask != 0) || opt.gen_basis);
+    // Leading 1-qubit gates of a known basis state leave a product state. When
+    // they are more than a run of Hadamards on distinct qubits, the first pass
+    // generates amp[i] = prod_q u_q[bit q of i] instead (u_q: the qubit's
+    // gates applied to its basis bit), the on-demand idea of the Hadamard
+    // layer carried to any product state.
+    bool product = false;
+    auto qgates = std::make_shared<std::vector<std::vector<int>>>();
+    if (opt.gen_h && opt.basis_known) {
+        size_t s1 = 0;
+        auto one_qubit = [](uint8_t c) { return c == G_D1 || c == G_H || c == G_DENSE1 || c == G_X || c == G_Y; };
+        while (s1 < cg.size() && one_qubit(cg[s1].cls)) ++s1;
+        if (s1 > start) {
+            product = true;
+            qgates->assign((size_t)n, {});
+            for (size_t i = 0; i < s1; ++i) (*qgates)[(size_t)cg[i].q0].push_back(cg[i].src);
+            P.n_gen_product = (int64_t)s1;
+            start = s1;
+            gen_mask = 0;
+        }
+    }
+    // The first pass generates its input instead of reading it: a product
+    // state, the Hadamard layer of a basis state, or the basis state itself
+    // (empty mask: amp = [i == j]) when its memory was never written.
+    const bool generate = opt.basis_known && ((opt.gen_h && gen_mask != 0) || opt.gen_basis || product);
     P.n_gen_h = popc(gen_mask);
-    P.gates_applied += P.n_gen_h;
+    P.gates_applied += P.n_gen_h + P.n_gen_product;
 
     std::vector<int> order;
     for (size_t i = start; i < cg.size(); ++i) order.push_back((int)i);
@@ -1413,7 +1433,28 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         dp.op_begin = (int)P.ops.size();
         dp.layout_begin = (int)P.layouts.size();
         X.layout_begin = dp.layout_begin;
-        X.op_floor = dp.op_begin;
+        if (first && product) {
+            // the product-state vectors head the pass's records (FP64 in
+            // both precisions: the product of up to n factors is formed in
+            // FP64 and rounded once)
+            const int per = 2;   // qubits per record payload
+            const int nrec = (n + per - 1) / per;
+            for (int r = 0; r < nrec; ++r) {
+                P.ops.emplace_back();
+                HostOp &o = P.ops.back();
+                o.hdr.code = r == 0 ? OP_GENP : OP_CONT;
+                if (r == 0) {
+                    o.hdr.a = (uint8_t)n;
+                    o.hdr.b = (uint8_t)(nrec - 1);
+                }
+                o.pk = PK_PROD;
+                o.qfirst = r * per;
+                o.qcount = std::min(per, n - r * per);
+                o.basis = opt.basis_j;
+                o.qgates = qgates;
+            }
+        }
+        X.op_floor = (int)P.ops.size();
 
         std::vector<int> rem = taken;
         const uint64_t U = X.U_labels();
@@ -1600,7 +1641,13 @@ Plan build_plan(int n, const sv_gate *gates, size_t n_gates, const PlanOptions &
         }
         if (!exch_in_pass && dp.store_layout != 0) dp.flags |= PASS_SYNC_STORE;
 
-        if (first && generate) {
+        if (first && product) {
+            dp.flags |= PASS_GEN_PRODUCT;
+            // the kernel reads the register bits' qubits from the load layout
+            const DevLayout &L0 = P.layouts[(size_t)dp.layout_begin];
+            for (int p = 0; p < opt.R; ++p)
+                if (popc(L0.reg_goff[p]) != 1) throw std::logic_error("product generation: register bit without one global bit");
+        } else if (first && generate) {
             dp.flags |= PASS_GENERATE;
             dp.gen_j = opt.basis_j;
             dp.gen_mask = gen_mask;
@@ -1802,6 +1849,25 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
                 break;
             }
             case PK_SCALE: v[0] = h.scale; count = 1; break;
+            case PK_PROD: {
+                for (int t = 0; t < h.qcount; ++t) {
+                    const int q = h.qfirst + t;
+                    cd M[4] = {1.0, 0.0, 0.0, 1.0};
+                    for (int gi : (*h.qgates)[(size_t)q]) {
+                        cd F[4];
+                        factor_mat(Factor{FK_GATE, false, gi}, gates, params, n_params, b, F);
+                        const cd N[4] = {F[0] * M[0] + F[1] * M[2], F[0] * M[1] + F[1] * M[3],
+                                         F[2] * M[0] + F[3] * M[2], F[2] * M[1] + F[3] * M[3]};
+                        std::copy(N, N + 4, M);
+                    }
+                    const int bq = (int)((h.basis >> q) & 1);   // u = M e_bq: column bq
+                    const cd u0 = M[bq], u1 = M[2 + bq];
+                    v[4 * t] = u0.real(); v[4 * t + 1] = u0.imag();
+                    v[4 * t + 2] = u1.real(); v[4 * t + 3] = u1.imag();
+                }
+                count = 4 * h.qcount;
+                break;
+            }
             case PK_MAT4:
             case PK_CONT: {
                 // entries e0 .. e0 + per - 1 of the row-major 4x4, physical
@@ -1871,7 +1937,9 @@ void materialize_ops(const Plan &p, const sv_gate *gates, const double *params, 
             }
             default: break;
             }
-            if (f32 && h.pk != PK_MAT2RI && h.pk != PK_SCALE) {
+            if (h.pk == PK_PROD) {
+                write_payload<double>(rec, v, count);
+            } else if (f32 && h.pk != PK_MAT2RI && h.pk != PK_SCALE) {
                 // complex entries: phases through the error-diffusing rounding
                 if ((size_t)count * sizeof(float) > sizeof rec.payload)
                     throw std::logic_error("operation payload larger than its record");

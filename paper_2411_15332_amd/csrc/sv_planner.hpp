@@ -4,6 +4,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/sv.h"
@@ -66,6 +67,8 @@ enum PayloadKind : uint8_t {
     PK_MAT4,    // a U2 gate's 4x4 matrix, rows and columns permuted by perm (16 entries,
                 // continued in the records that follow the operation)
     PK_CONT,    // continuation record of the preceding PK_MAT4 (entries from `gate` e0)
+    PK_PROD,    // product-state vectors u_q = M_q e_(bit q of basis) of the qubits
+                // qfirst .. qfirst + per - 1, M_q the product of qgates[q] in order
 };
 
 // One diagonal gate on thread or tile-base bits inside a merged OP_UDN.
@@ -92,6 +95,11 @@ struct HostOp {
     std::vector<UContrib> ucon;    // PK_UDN
     int n_terms = 0;               // PK_UDN
     double scale = 1.0;
+    int qfirst = 0;                // PK_PROD
+    int qcount = 0;
+    uint64_t basis = 0;
+    std::shared_ptr<const std::vector<std::vector<int>>> qgates;   // PK_PROD: caller gate
+                                                                   // indices per qubit
 };
 
 struct PlanOptions;
@@ -129,6 +137,7 @@ struct Plan {
     uint64_t cstride = 0;              // small path: reals per batch entry
     int64_t n_exch = 0;
     int64_t n_gen_h = 0;
+    int64_t n_gen_product = 0;         // leading 1-qubit gates folded into a generated product state
     int64_t gates_applied = 0;
     int64_t n_relabel = 0;             // permutation gates absorbed into layouts
     int64_t n_restore = 0;             // passes that only put qubits back on their own bits

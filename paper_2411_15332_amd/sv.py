@@ -246,7 +246,8 @@ class StateVector:
     def plan_stats(self) -> dict:
         out = np.zeros(8, dtype=np.int64)
         _check(lib().sv_plan_stats(self._h, _ptr(out)))
-        keys = ("passes", "exchanges", "gates", "generated_h", "launches", "hbm_bytes", "relabels")
+        keys = ("passes", "exchanges", "gates", "generated_h", "launches", "hbm_bytes", "relabels",
+                "generated_product")
         return {k: int(out[i]) for i, k in enumerate(keys)}
 
     def profile_read(self):
@@ -306,7 +307,7 @@ def debug_plan(n: int, gates, dtype: str = "c128", params: Optional[np.ndarray] 
     out = {"small": bool(h[0]), "k": int(h[9]), "w": int(h[10]), "R": int(h[11]), "m": int(h[12]),
            "exchanges": int(h[6]), "generated_h": int(h[7]), "gates": int(h[8]),
            "hbm_bytes": int(h[18]), "cstride": int(h[5]), "relabels": int(h[19]), "restores": int(h[20]),
-           "min_low": int(h[21])}
+           "min_low": int(h[21]), "generated_product": int(h[22])}
 
     def take(off, count, dt_):
         return buf[off: off + count * dt_.itemsize].view(dt_).copy()

@@ -12,12 +12,13 @@ import numpy as np
 
 (OP_EXCH, OP_D1R, OP_UDN, _UNUSED4, OP_APPLYF, _UNUSED6, _UNUSED7, OP_DENSE1, OP_H, OP_X,
  OP_CXR, OP_CXU, OP_MARK, OP_SCALE, OP_CXT, OP_D1H, OP_D2Q, OP_D1HU, OP_RPERM, OP_DENSE2,
- OP_CONT, OP_DENSE1RI, OP_CCX) = range(1, 24)
+ OP_CONT, OP_DENSE1RI, OP_CCX, OP_GENP) = range(1, 25)
 NO_SOURCE = 0xFF
 (SOP_D1, SOP_D2, SOP_MARK, SOP_DENSE1, SOP_DENSE2, SOP_X, SOP_Y, SOP_CX, SOP_SWAP, SOP_SCALE,
  SOP_CCX) = range(1, 12)
 SRC_REG, SRC_THR, SRC_TILE = 0, 1, 2
 PASS_GENERATE = 1
+PASS_GEN_PRODUCT = 8
 
 
 def _c(consts, off, count):
@@ -120,7 +121,19 @@ def run_plan(plan, psi, n):
             return addr
 
         gidx = addresses(0)
-        if int(P["flags"]) & PASS_GENERATE:
+        if int(P["flags"]) & PASS_GEN_PRODUCT:
+            # amp[i] = prod_q u_q[bit q of i], u from the OP_GENP record and
+            # its continuations (4 reals per qubit: u_q0, u_q1)
+            g0 = plan["ops"][int(P["op_begin"])]
+            assert int(g0["code"]) == OP_GENP
+            nq, ncont = int(g0["a"]), int(g0["b"])
+            recs = plan["ops"][int(P["op_begin"]): int(P["op_begin"]) + 1 + ncont]
+            vals = np.concatenate([r["payload"] for r in recs])   # FP64 in both precisions
+            u = (vals[0::2] + 1j * vals[1::2]).reshape(-1, 2)[:nq]
+            a = np.ones(gidx.shape, dtype=np.complex128)
+            for q in range(nq):
+                a = a * u[q][(gidx >> q) & 1]
+        elif int(P["flags"]) & PASS_GENERATE:
             gj, gm, sc = int(P["gen_j"]), int(P["gen_mask"]), float(P["gen_scale"])
             on = ((gidx ^ gj) & ~gm) == 0
             par = np.vectorize(lambda x: bin(x).count("1") & 1)(gidx & gj & gm)
@@ -284,6 +297,8 @@ def run_plan(plan, psi, n):
                 a = np.where(hit, -a, a)
             elif code == OP_SCALE:
                 a = a * pl[0]
+            elif code == OP_GENP:
+                assert oi == int(P["op_begin"]), "product data outside the pass's first record"
             else:
                 raise NotImplementedError(code)
         assert np.all(f == 1), "pending per-thread factor at the store"

@@ -82,7 +82,8 @@ def test_capacity_monomial_mix_sampled_vs_oracle(P, n, dt):
         sv.close()
         del sv
         _release()
-    assert st["generated_h"] == n
+    # the H layer and the 1-qubit gates after it: a generated product state
+    assert st["generated_product"] >= n
     err = np.abs(got - want)
     print(f"  passes={st['passes']} max|d|={err.max():.3e} "
           f"scaled={err.max() * 2 ** (n / 2):.3e} |norm-1|={abs(nrm - 1):.3e}", flush=True)
@@ -115,7 +116,7 @@ def test_capacity_mirror_full_state(P, n, dt):
         _release()
     print(f"  passes={st['passes']} |norm-1|={abs(nrm - 1):.3e} after mirror {abs(nrm2 - 1):.3e} "
           f"max|d|={mx:.3e} normwise={l2:.3e}", flush=True)
-    assert st["generated_h"] == n
+    assert st["generated_product"] >= n   # the H layer and the 1-qubit gates after it
     assert abs(nrm - 1.0) <= TOL[dt]["norm"]
     assert abs(nrm2 - 1.0) <= TOL[dt]["norm"]
     assert np.max(np.abs(samp - 2.0 ** (-0.5 * n))) <= TOL[dt]["amp"]
@@ -144,7 +145,7 @@ def test_capacity_mix_vs_state_oracle_n26(P, dt):
         sv.close()
         del sv
         _release()
-    assert st["generated_h"] == n
+    assert st["generated_product"] >= n
     err = np.abs(got - want)
     print(f"capacity n=26 {dt}: max|d|={err.max():.3e}", flush=True)
     assert err.max() <= TOL[dt]["amp"]

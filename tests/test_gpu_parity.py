@@ -136,7 +136,8 @@ def test_generation_then_gates(P):
     gates = [synth.Gate("H", q) for q in range(0, n, 2)] + synth.random_circuit(n, 3, 5)
     ref = O.simulate(n, gates, psi0=O.basis_state(n, 77))
     got, st = run(P, n, gates, basis=77)
-    assert st["generated_h"] == n // 2
+    # the Hadamards and the first layer's 1-qubit gates: one generated product state
+    assert st["generated_product"] == n // 2 + n
     assert maxdiff(got, ref) <= 1e-12
 
 
@@ -170,6 +171,42 @@ def test_recorded_basis_state(P, n, dtype):
         sv.set_basis(j)
         state = sv.numpy()[0]
         assert state[j] == 1.0 and np.count_nonzero(state) == 1
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [16, 23])
+def test_product_state_generation(P, n, dtype):
+    """A leading run of 1-qubit gates of every kind (several per qubit, some
+    parametric with a batch of angles) on a basis state is folded into a
+    product state that the first pass generates; against the oracle, and
+    against the same circuit with generation switched off."""
+    tol = TOL[dtype]
+    rng = np.random.default_rng(n)
+    names = ("H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "P", "SDG")
+    lead = []
+    for q in list(range(n)) + list(rng.permutation(n)[: n // 2]):
+        nm = names[int(rng.integers(len(names)))]
+        lead.append(synth.Gate(nm, int(q), -1, float(rng.uniform(0, 6.3)),
+                               len(lead) if nm in ("RX", "RY", "RZ", "P") else -1))
+    gates = lead + synth.random_circuit(n, 2, 3)
+    B = 2
+    params = rng.uniform(-3, 3, size=(B, len(lead)))
+    j = (0x2D3 * n) % (1 << n)
+    with P.StateVector(n, dtype, B) as sv:
+        sv.set_basis(j)
+        sv.apply(gates, params)
+        st = sv.plan_stats()
+        got = sv.numpy().astype(np.complex128)
+        sv.set_option(4, 0)   # no on-demand generation
+        sv.set_basis(j)
+        sv.apply(gates, params)
+        plain = sv.numpy().astype(np.complex128)
+    # the lead and the 1-qubit layer that opens the random circuit
+    assert st["generated_product"] == len(lead) + n
+    for b in range(B):
+        ref = O.simulate(n, gates, params[b], psi0=O.basis_state(n, j))
+        assert maxdiff(got[b], ref) <= tol
+        assert maxdiff(plain[b], ref) <= tol
 
 
 def _golden(name):
@@ -336,7 +373,9 @@ def test_relabel_passes_race_free_n27(P):
         gates.append(synth.Gate("RY", q % 6, -1, 0.1 * q))
     ref = O.simulate(n, gates, psi0=None)
     for _ in range(3):
-        got, st = run(P, n, gates)
+        # on-demand generation off: from |0...0> these 1-qubit gates would be
+        # folded into a generated product state and nothing would be relabelled
+        got, st = run(P, n, gates, opts={4: 0})
         assert st["relabels"] > 0
         assert maxdiff(got, ref) <= 1e-12
 
@@ -362,7 +401,8 @@ def test_plan_reuse_across_calls(P):
         sv.apply(gates, p1[None, :])        # from a2: no longer a basis state
         a3 = sv.numpy()[0].copy()
         st3 = sv.plan_stats()
-    assert st1["generated_h"] == n and st2["generated_h"] == n and st3["generated_h"] == 0
+    assert st1["generated_product"] >= n and st2["generated_product"] == st1["generated_product"]
+    assert st3["generated_product"] == 0 and st3["generated_h"] == 0
     r1 = O.simulate(n, gates, p1)
     r2 = O.simulate(n, gates, p2)
     r3 = O.simulate(n, gates, p1, psi0=r2)

@@ -112,10 +112,21 @@ def test_every_gate_kind_every_position(n):
 @pytest.mark.parametrize("j", [0, 5, 1023])
 def test_generation_prologue(j):
     n = 12
-    gates = [synth.Gate("H", q) for q in (3, 0, 7, 11, 5)] + synth.random_circuit(n, 2, 1)
+    # Hadamards on distinct qubits up to the first other gate: generated as
+    # the RH layer
+    gates = [synth.Gate("H", q) for q in (3, 0, 7, 11, 5)] + [synth.Gate("CNOT", 3, 4)] + \
+        synth.random_circuit(n, 2, 1)
     ref = O.simulate(n, gates, psi0=O.basis_state(n, j))
     got, plan = _emulate(n, gates, basis=j)
-    assert plan["generated_h"] == 5
+    assert plan["generated_h"] == 5 and plan["generated_product"] == 0
+    assert np.max(np.abs(got - ref)) < 1e-12
+    # followed by more 1-qubit gates: the whole 1-qubit prefix becomes a
+    # generated product state
+    gates = [synth.Gate("H", q) for q in (3, 0, 7, 11, 5)] + synth.random_circuit(n, 2, 1)
+    lead = 5 + next(i for i, g in enumerate(gates[5:]) if g.name in ("CNOT", "CZ", "SWAP", "CPHASE"))
+    ref = O.simulate(n, gates, psi0=O.basis_state(n, j))
+    got, plan = _emulate(n, gates, basis=j)
+    assert plan["generated_h"] == 0 and plan["generated_product"] == lead
     assert np.max(np.abs(got - ref)) < 1e-12
     only_h = [synth.Gate("H", q) for q in range(n)]
     got, plan = _emulate(n, only_h, basis=j)
@@ -147,7 +158,11 @@ def test_large_plan_statistics():
     plan = P.debug_plan(28, gates)
     npass = len(plan["passes"])
     assert plan["gates"] == len(gates)
-    assert plan["hbm_bytes"] == npass * 2 * (1 << 28) * 16 - (1 << 28) * 16 * 0
+    # the first pass generates the product state left by the leading layer of
+    # 1-qubit gates: it writes and reads nothing
+    gen = int(plan["passes"][0]["flags"]) & 8 != 0
+    assert gen and plan["generated_product"] == 28
+    assert plan["hbm_bytes"] == npass * 2 * (1 << 28) * 16 - (1 << 28) * 16
     # every gate of a pass lies on its tile qubits or is diagonal
     assert 30 < npass < 200
     assert plan["k"] == plan["R"] + plan["w"] and plan["w"] >= 8
@@ -158,11 +173,13 @@ def test_relabel_only_pass_orders_loads_before_stores():
     # store addresses; with no LDS exchange in the pass, the kernel needs a
     # barrier between the tile's loads and its permuted stores.
     n = 16
+    # (a general input state: from a known basis state the two gates would be
+    # folded into a generated product state)
     gates = [synth.Gate("X", 11), synth.Gate("Y", 10)]
-    plan = P.debug_plan(n, gates)
+    plan = P.debug_plan(n, gates, basis=None)
     assert plan["relabels"] >= 1 and plan["exchanges"] == 0
     assert all(int(p["flags"]) & 2 for p in plan["passes"] if int(p["store_layout"]) != 0)
-    plain = P.debug_plan(n, [synth.Gate("Z", 11)])
+    plain = P.debug_plan(n, [synth.Gate("Z", 11)], basis=None)
     assert not any(int(p["flags"]) & 2 for p in plain["passes"])
 
 
@@ -383,20 +400,24 @@ def test_noalloc_readout_rejects_before_any_launch(args, what):
 
 @pytest.mark.parametrize("n,dtype,basis", [(13, "c128", 0), (15, "c128", 12345), (14, "c64", 77),
                                            (16, "c64", 0)])
-@pytest.mark.parametrize("lead_h", [False, True])
-def test_recorded_basis_state_is_generated_by_the_first_pass(n, dtype, basis, lead_h):
+@pytest.mark.parametrize("lead", ["none", "h", "one_qubit"])
+def test_recorded_basis_state_is_generated_by_the_first_pass(n, dtype, basis, lead):
     """sv_alloc / sv_set_basis only record the basis state; the plan's first
-    pass then generates it (with or without leading Hadamards), so whatever the
-    buffer held before must not leak into the result."""
+    pass then generates it: the basis state itself (a 2-qubit gate first), a
+    Hadamard layer on it, or the product state of a leading run of 1-qubit
+    gates. Whatever the buffer held before must not leak into the result."""
     gates = synth.random_circuit(n, 3, n + basis)
-    if lead_h:
+    gates = [g for g in gates if g.q1 >= 0] + gates   # a 2-qubit gate first
+    if lead == "h":
         gates = [synth.Gate("H", q) for q in range(0, n, 3)] + gates
-    else:
-        while gates[0].name == "H":
-            gates = gates[1:]
+    elif lead == "one_qubit":
+        gates = synth.random_circuit(n, 1, 7)[:n] + gates
     ref = O.simulate(n, gates, psi0=O.basis_state(n, basis))
     plan = P.debug_plan(n, gates, dtype=dtype, basis=basis, basis_in_memory=False)
-    assert not plan["small"] and int(plan["passes"][0]["flags"]) & 1
+    want = {"none": 1, "h": 1, "one_qubit": 8}[lead]
+    assert not plan["small"] and int(plan["passes"][0]["flags"]) & 9 == want
+    assert (plan["generated_h"] > 0) == (lead == "h")
+    assert (plan["generated_product"] > 0) == (lead == "one_qubit")
     garbage = np.random.default_rng(5).standard_normal(1 << n) * (1 + 1j)
     got = run_plan(plan, garbage, n)
     assert np.max(np.abs(got - ref)) < EMU_TOL[dtype]
