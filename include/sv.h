@@ -294,13 +294,32 @@ typedef struct sv_engine_s *sv_engine;
 sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams,
                            size_t hbm_budget_bytes, sv_engine *out);
 
+/* Stepped engine: continuous batching at pass granularity. Small states are
+ * served as above (groups of up to max_small_batch requests on
+ * n_small_streams streams). Larger states are admitted, oldest first, while
+ * at most max_active of them are on the GPU and their state memory fits the
+ * HBM budget; then every step is one launch that runs the next pass of every
+ * admitted request, whatever its circuit, n or depth (each on its own state
+ * with its own plan), followed by one batched readout of the requests that
+ * step completes. Requests that arrive meanwhile join at the next step, so
+ * their work overlaps on the device with the requests already running. A
+ * request's first pass generates its initial product state (its leading
+ * 1-qubit gates applied to |0...0>, on demand) instead of reading a filled
+ * state. Every request runs the same code whatever shares its steps, so its
+ * result does not depend on the mix. The plan arena holds 256 MiB of op
+ * records (requests wait when it is full) and 32 MiB of distinct circuits
+ * (SV_ENOMEM beyond). */
+sv_status sv_engine_create_stepped(sv_dtype dtype, int max_active, int max_small_batch, int n_small_streams,
+                                   size_t hbm_budget_bytes, sv_engine *out);
+
 /* Waits for the groups in flight, then frees the engine. */
 sv_status sv_engine_free(sv_engine e);
 
 /* Queue one request (gates and params are copied). n_params reals of
  * parameters (may be 0 with params NULL); qubit: the measured qubit.
  * Gates are validated as in sv_apply_circuit (SV_EINVAL, nothing queued);
- * n_qubits above 30 is SV_EUNSUPPORTED. */
+ * n_qubits above 30 is SV_EUNSUPPORTED; a state larger than a nonzero HBM
+ * budget is SV_ENOMEM (it could never be admitted). */
 sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate *gates,
                            size_t n_gates, const double *params, size_t n_params, int qubit);
 

@@ -34,12 +34,76 @@ struct Template {
     size_t n_params = 0;     // caller's parameters plus derived columns
     bool small = false;
     Plan plan;
+    // stepped engine: the plan's passes and layouts in the plan arena
+    bool in_arena = false;
+    uint64_t passes_off = 0, layouts_off = 0;
 };
 
 struct Request {
     uint64_t id = 0;
     std::shared_ptr<Template> t;
     std::vector<double> params;
+};
+
+// Stepped engine: a request on the GPU. It runs pass `next` of its plan in
+// the next step; its op records sit in the plan arena's ring at ops_off.
+struct Active {
+    uint64_t id = 0;
+    std::shared_ptr<Template> t;
+    void *state = nullptr;
+    size_t bytes = 0;
+    uint64_t ops_off = 0;
+    size_t ring_entry = 0;   // its allocation in the ring (sequence number)
+    int next = 0;
+};
+
+// Ring allocator over [rb, re) of the plan arena: allocations are placed in
+// order and released in any order; space is reused once every older
+// allocation is released too (requests finish roughly in arrival order).
+struct Ring {
+    uint64_t rb = 0, re = 0, head = 0, tail = 0;
+    struct Ent { uint64_t off, size; bool freed; };
+    std::deque<Ent> live;
+    uint64_t first_seq = 0;  // sequence number of live.front()
+    bool alloc(uint64_t size, uint64_t &off, uint64_t &seq) {
+        size = (size + 255) & ~(uint64_t)255;
+        if (live.empty()) head = tail = rb;
+        if (head >= tail) {
+            if (head + size <= re) off = head;
+            else if (rb + size <= tail || (live.empty() && rb + size <= re)) off = rb;
+            else return false;
+        } else {
+            if (head + size <= tail) off = head;
+            else return false;
+        }
+        head = off + size;
+        seq = first_seq + live.size();
+        live.push_back({off, size, false});
+        return true;
+    }
+    void release(uint64_t seq) {
+        live[(size_t)(seq - first_seq)].freed = true;
+        while (!live.empty() && live.front().freed) {
+            live.pop_front();
+            ++first_seq;
+        }
+        tail = live.empty() ? head : live.front().off;
+    }
+};
+
+// One step in flight: its tables (pinned staging and device copy), the
+// requests it completes and where their results land.
+struct StepSlot {
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    char *h_buf = nullptr;
+    size_t h_cap = 0;
+    char *d_buf = nullptr;
+    size_t d_cap = 0;
+    double *h_res = nullptr;
+    size_t h_res_cap = 0;
+    std::vector<uint64_t> ids;          // results in h_res order
+    std::vector<uint64_t> ring_seqs;    // op records to release when done
 };
 
 struct Slot {
@@ -76,6 +140,18 @@ struct sv_engine_s {
     std::deque<std::pair<uint64_t, double>> finished;
     size_t bytes_held = 0;
     int64_t completed = 0, groups = 0, largest = 0, deferred = 0, small_groups = 0;
+    // stepped mode (SV_ENGINE_STEPPED): larger states advance one pass per step
+    bool stepped = false;
+    hipStream_t step_stream = nullptr;
+    char *d_arena = nullptr;
+    char *h_arena = nullptr;     // pinned mirror: records are written here, then copied
+    uint64_t arena_cap = 0, tmpl_used = 0, tmpl_cap = 0;
+    Ring ring;
+    std::deque<Active> active;   // admission order
+    std::vector<StepSlot> steps;
+    size_t next_step = 0;        // ring of step slots
+    std::deque<size_t> step_order;   // busy step slots, oldest first
+    int max_active = 64;
 };
 
 namespace {
@@ -242,10 +318,15 @@ sv_status launch_ready(sv_engine_s *e) {
         Slot &s = *sp;
         if (s.busy) continue;
         if (e->queue.empty()) break;
-        const Request &front = e->queue.front();
-        const bool small = front.t->small;
+        // stepped mode: these slots serve the small states only
+        size_t fi = 0;
+        if (e->stepped)
+            while (fi < e->queue.size() && !e->queue[fi].t->small) ++fi;
+        if (fi == e->queue.size()) break;
+        const Request &front = e->queue[fi];
+        bool small = front.t->small;
         std::vector<size_t> pick;
-        for (size_t i = 0; i < e->queue.size() && (int)pick.size() < e->max_batch; ++i) {
+        for (size_t i = fi; i < e->queue.size() && (int)pick.size() < e->max_batch; ++i) {
             const Request &r = e->queue[i];
             if (small ? r.t->small : r.t == front.t) pick.push_back(i);
         }
@@ -262,9 +343,18 @@ sv_status launch_ready(sv_engine_s *e) {
             }
             if (k == 0 || !reserve_state(e, s, k * per)) {
                 ++e->deferred;
-                break;   // wait for memory held by groups in flight
+                // the group waits for memory held by groups in flight; small
+                // states hold none, so they may go ahead of it
+                size_t si = fi;
+                while (si < e->queue.size() && !e->queue[si].t->small) ++si;
+                if (si == e->queue.size()) break;
+                pick.clear();
+                for (size_t i = si; i < e->queue.size() && (int)pick.size() < e->max_batch; ++i)
+                    if (e->queue[i].t->small) pick.push_back(i);
+                small = true;
+            } else {
+                pick.resize(k);
             }
-            pick.resize(k);
         }
         std::vector<Request> grp;
         grp.reserve(pick.size());
@@ -287,12 +377,269 @@ sv_status launch_ready(sv_engine_s *e) {
     return SV_OK;
 }
 
+// ------------------------------------------------------------------------
+// Stepped mode: continuous batching at pass granularity. Each step is one
+// launch per kernel variant that runs the next pass of every active request,
+// whatever its circuit, n or depth, plus one batched readout for the requests
+// the step completes. Requests join at the next step built after their
+// arrival; a step's tables are small, and the per-request op records go to
+// the plan arena once, at admission.
+
+constexpr int kStepSlots = 3;                   // steps in flight
+constexpr uint64_t kArenaBytes = 256ull << 20;  // plan arena (templates + op records)
+constexpr uint64_t kTemplateBytes = 32ull << 20;
+
+sv_status stepped_init(sv_engine_s *e) {
+    SV_HIP(hipStreamCreateWithFlags(&e->step_stream, hipStreamNonBlocking), "engine step stream");
+    e->arena_cap = kArenaBytes;
+    e->tmpl_cap = kTemplateBytes;
+    SV_HIP(hipMalloc(reinterpret_cast<void **>(&e->d_arena), e->arena_cap), "hipMalloc(plan arena)");
+    SV_HIP(hipHostMalloc(reinterpret_cast<void **>(&e->h_arena), e->arena_cap, hipHostMallocDefault),
+           "hipHostMalloc(plan arena)");
+    e->ring.rb = e->tmpl_cap;
+    e->ring.re = e->arena_cap;
+    e->steps.resize(kStepSlots);
+    for (StepSlot &S : e->steps) SV_HIP(hipEventCreateWithFlags(&S.done, hipEventDisableTiming), "hipEventCreate");
+    return SV_OK;
+}
+
+void stepped_release(sv_engine_s *e) {
+    if (e->step_stream) hipStreamSynchronize(e->step_stream);
+    for (Active &a : e->active)
+        if (a.state) hipFree(a.state);
+    e->active.clear();
+    for (StepSlot &S : e->steps) {
+        if (S.h_buf) hipHostFree(S.h_buf);
+        if (S.d_buf) hipFree(S.d_buf);
+        if (S.h_res) hipHostFree(S.h_res);
+        if (S.done) hipEventDestroy(S.done);
+    }
+    e->steps.clear();
+    if (e->d_arena) hipFree(e->d_arena);
+    if (e->h_arena) hipHostFree(e->h_arena);
+    e->d_arena = e->h_arena = nullptr;
+    if (e->step_stream) hipStreamDestroy(e->step_stream);
+    e->step_stream = nullptr;
+}
+
+// Copy the template's passes and layouts into the arena (once per template).
+sv_status stepped_template(sv_engine_s *e, Template &t) {
+    if (t.in_arena) return SV_OK;
+    const Plan &p = t.plan;
+    const uint64_t pb = p.passes.size() * sizeof(DevPass), lb = p.layouts.size() * sizeof(DevLayout);
+    const uint64_t need = align_up(pb, 256) + align_up(lb, 256);
+    if (e->tmpl_used + need > e->tmpl_cap) return fail(SV_ENOMEM, "serving engine: too many distinct circuits");
+    t.passes_off = e->tmpl_used;
+    t.layouts_off = t.passes_off + align_up(pb, 256);
+    std::memcpy(e->h_arena + t.passes_off, p.passes.data(), pb);
+    std::memcpy(e->h_arena + t.layouts_off, p.layouts.data(), lb);
+    SV_HIP(hipMemcpyAsync(e->d_arena + t.passes_off, e->h_arena + t.passes_off, need, hipMemcpyHostToDevice,
+                          e->step_stream),
+           "hipMemcpyAsync(template)");
+    e->tmpl_used += need;
+    t.in_arena = true;
+    return SV_OK;
+}
+
+// Admit queued larger-state requests while the active set, the HBM budget
+// and the arena allow: state memory (stream-ordered) and op records.
+sv_status stepped_admit(sv_engine_s *e) {
+    const bool f32 = e->dt == SV_C64;
+    size_t i = 0;
+    while (i < e->queue.size() && (int)e->active.size() < e->max_active) {
+        Request &r = e->queue[i];
+        if (r.t->small) {
+            ++i;
+            continue;
+        }
+        Template &t = *r.t;
+        const size_t bytes = ((size_t)1 << t.n) * e->amp_bytes;
+        if (e->budget && e->bytes_held + bytes > e->budget) {
+            ++e->deferred;
+            break;   // admission by HBM footprint: wait for running requests to finish
+        }
+        const uint64_t ob = (uint64_t)t.plan.ops.size() * sizeof(DevOp);
+        uint64_t off = 0, seq = 0;
+        if (!e->ring.alloc(std::max<uint64_t>(ob, 256), off, seq)) break;   // wait for arena space
+        sv_status st = stepped_template(e, t);
+        if (st != SV_OK) return st;
+        Active a;
+        a.id = r.id;
+        a.t = r.t;
+        a.bytes = bytes;
+        a.ops_off = off;
+        a.ring_entry = seq;
+        SV_HIP(hipMallocAsync(&a.state, bytes, e->step_stream), "hipMallocAsync(state)");
+        if (ob) {
+            materialize_ops(t.plan, t.gates.data(), r.params.data(), t.n_params, 1, f32, e->h_arena + off);
+            SV_HIP(hipMemcpyAsync(e->d_arena + off, e->h_arena + off, ob, hipMemcpyHostToDevice, e->step_stream),
+                   "hipMemcpyAsync(op records)");
+        }
+        if (t.plan.passes.empty())   // nothing to apply: the readout sees |0...0>
+            SV_HIP(launch_fill_basis((int)e->dt, a.state, 1ull << t.n, 1, 0, e->step_stream), "launch fill");
+        e->bytes_held += bytes;
+        e->active.push_back(std::move(a));
+        e->queue.erase(e->queue.begin() + (long)i);
+    }
+    return SV_OK;
+}
+
+// Build and launch one step into a free step slot.
+sv_status stepped_launch(sv_engine_s *e) {
+    StepSlot &S = e->steps[e->next_step];
+    if (S.busy) return SV_OK;
+    sv_status st = stepped_admit(e);
+    if (st != SV_OK) return st;
+    if (e->active.empty()) return SV_OK;
+
+    std::vector<StepReq> reqs;
+    std::vector<StepItem> items[4];   // bit 0: generating pass, bit 1: pass with a 4x4
+    std::vector<RedItem> reds;
+    std::vector<FinItem> fins;
+    S.ids.clear();
+    S.ring_seqs.clear();
+    std::vector<size_t> done_idx;
+    uint32_t parts = 0;
+    for (size_t ai = 0; ai < e->active.size(); ++ai) {
+        Active &a = e->active[ai];
+        const Template &t = *a.t;
+        const int np = (int)t.plan.passes.size();
+        if (a.next < np) {
+            const DevPass &P = t.plan.passes[(size_t)a.next];
+            if (P.w != (e->dt == SV_C128 ? kThreadBitsC128 : kThreadBitsC64))
+                return fail(SV_EUNSUPPORTED, "serving engine: tile geometry of a %d-qubit plan", t.n);
+            StepReq q;
+            std::memset(&q, 0, sizeof q);
+            q.state = a.state;
+            q.passes_off = t.passes_off;
+            q.layouts_off = t.layouts_off;
+            q.ops_off = a.ops_off;
+            q.pass = a.next;
+            q.n = t.n;
+            const uint32_t ri = (uint32_t)reqs.size();
+            reqs.push_back(q);
+            const int v = ((P.flags & PASS_GENERATES) ? 1 : 0) | ((P.flags & PASS_DENSE2) ? 2 : 0);
+            for (uint64_t tile = 0; tile < P.tiles; ++tile) items[v].push_back({ri, (uint32_t)tile});
+            ++a.next;
+        }
+        if (a.next >= np) {   // this step completes it: batched readout
+            const uint32_t nblk = (uint32_t)reduce_blocks(t.n);
+            const uint64_t chunk = reduce_chunk(t.n);
+            for (uint32_t b = 0; b < nblk; ++b) {
+                RedItem r;
+                std::memset(&r, 0, sizeof r);
+                r.state = a.state;
+                r.chunk = chunk;
+                r.blk = b;
+                r.qubit = t.qubit;
+                r.part = parts + b;
+                reds.push_back(r);
+            }
+            FinItem f;
+            std::memset(&f, 0, sizeof f);
+            f.first = parts;
+            f.count = nblk;
+            f.slot = (uint32_t)S.ids.size();
+            fins.push_back(f);
+            parts += nblk;
+            S.ids.push_back(a.id);
+            S.ring_seqs.push_back(a.ring_entry);
+            done_idx.push_back(ai);
+        }
+    }
+
+    // step tables: one upload; partial sums and results live on the device only
+    size_t off = 0;
+    auto sec = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
+    const size_t o_req = sec(reqs.size() * sizeof(StepReq));
+    size_t o_it[4];
+    for (int v = 0; v < 4; ++v) o_it[v] = sec(items[v].size() * sizeof(StepItem));
+    const size_t o_red = sec(reds.size() * sizeof(RedItem));
+    const size_t o_fin = sec(fins.size() * sizeof(FinItem));
+    const size_t up = off;
+    const size_t o_part = sec((size_t)parts * sizeof(double));
+    const size_t o_res = sec(fins.size() * sizeof(double));
+    const size_t total = std::max<size_t>(off, 256);
+    if (S.h_cap < up) {
+        if (S.h_buf) hipHostFree(S.h_buf);
+        S.h_buf = nullptr;
+        S.h_cap = 0;
+        SV_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.h_buf), std::max<size_t>(up, 1) * 2, hipHostMallocDefault),
+               "hipHostMalloc(step)");
+        S.h_cap = std::max<size_t>(up, 1) * 2;
+    }
+    if (S.d_cap < total) {
+        if (S.d_buf) hipFree(S.d_buf);
+        S.d_buf = nullptr;
+        S.d_cap = 0;
+        SV_HIP(hipMalloc(reinterpret_cast<void **>(&S.d_buf), total * 2), "hipMalloc(step)");
+        S.d_cap = total * 2;
+    }
+    std::memcpy(S.h_buf + o_req, reqs.data(), reqs.size() * sizeof(StepReq));
+    for (int v = 0; v < 4; ++v) std::memcpy(S.h_buf + o_it[v], items[v].data(), items[v].size() * sizeof(StepItem));
+    std::memcpy(S.h_buf + o_red, reds.data(), reds.size() * sizeof(RedItem));
+    std::memcpy(S.h_buf + o_fin, fins.data(), fins.size() * sizeof(FinItem));
+    hipStream_t ss = e->step_stream;
+    if (up) SV_HIP(hipMemcpyAsync(S.d_buf, S.h_buf, up, hipMemcpyHostToDevice, ss), "hipMemcpyAsync(step)");
+    const StepReq *d_req = reinterpret_cast<const StepReq *>(S.d_buf + o_req);
+    for (int v = 0; v < 4; ++v)
+        SV_HIP(launch_pass_multi((int)e->dt, e->d_arena, d_req, reinterpret_cast<const StepItem *>(S.d_buf + o_it[v]),
+                                 (uint32_t)items[v].size(), (v & 1) != 0, (v & 2) != 0, ss),
+               "launch step");
+    if (!fins.empty()) {
+        double *d_res = reinterpret_cast<double *>(S.d_buf + o_res);
+        SV_HIP(launch_reduce_multi((int)e->dt, reinterpret_cast<const RedItem *>(S.d_buf + o_red), (uint32_t)reds.size(),
+                                   reinterpret_cast<double *>(S.d_buf + o_part),
+                                   reinterpret_cast<const FinItem *>(S.d_buf + o_fin), (uint32_t)fins.size(), d_res, ss),
+               "launch step readout");
+        st = ensure_pinned(reinterpret_cast<void **>(&S.h_res), &S.h_res_cap, fins.size() * sizeof(double));
+        if (st != SV_OK) return st;
+        SV_HIP(hipMemcpyAsync(S.h_res, d_res, fins.size() * sizeof(double), hipMemcpyDeviceToHost, ss),
+               "hipMemcpyAsync(step results)");
+    }
+    // finished requests leave the active set; their state memory returns to
+    // the pool after the readout (stream order)
+    for (size_t k = done_idx.size(); k-- > 0;) {
+        Active &a = e->active[done_idx[k]];
+        SV_HIP(hipFreeAsync(a.state, ss), "hipFreeAsync(state)");
+        e->bytes_held -= a.bytes;
+        e->active.erase(e->active.begin() + (long)done_idx[k]);
+    }
+    SV_HIP(hipEventRecord(S.done, ss), "hipEventRecord(step)");
+    S.busy = true;
+    e->step_order.push_back(e->next_step);
+    e->next_step = (e->next_step + 1) % e->steps.size();
+    ++e->groups;
+    size_t wg = 0;
+    for (int v = 0; v < 4; ++v) wg += items[v].size();
+    e->largest = std::max<int64_t>(e->largest, (int64_t)reqs.size());
+    (void)wg;
+    return SV_OK;
+}
+
+sv_status stepped_retire(sv_engine_s *e) {
+    while (!e->step_order.empty()) {
+        StepSlot &S = e->steps[e->step_order.front()];
+        const hipError_t q = hipEventQuery(S.done);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return hip_fail(q, "engine step");
+        for (size_t i = 0; i < S.ids.size(); ++i) e->finished.emplace_back(S.ids[i], S.h_res[i]);
+        e->completed += (int64_t)S.ids.size();
+        for (uint64_t seq : S.ring_seqs) e->ring.release(seq);
+        S.ids.clear();
+        S.ring_seqs.clear();
+        S.busy = false;
+        e->step_order.pop_front();
+    }
+    return SV_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams, size_t hbm_budget_bytes,
-                           sv_engine *out) {
+static sv_status engine_create(sv_dtype dtype, int max_batch, int n_streams, size_t hbm_budget_bytes,
+                               bool stepped, int max_active, sv_engine *out) {
     return guarded([&]() -> sv_status {
         if (!out) return fail(SV_EINVAL, "out is NULL");
         *out = nullptr;
@@ -318,15 +665,38 @@ sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams, size_t 
             sv_engine_free(e);
             return hip_fail(err, "engine streams");
         }
+        if (stepped) {
+            e->stepped = true;
+            e->max_active = max_active;
+            sv_status st = stepped_init(e);
+            if (st != SV_OK) {
+                const std::string msg = sv_last_error();
+                sv_engine_free(e);
+                return fail(st, "%s", msg.c_str());
+            }
+        }
         *out = e;
         return SV_OK;
     });
+}
+
+sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams, size_t hbm_budget_bytes,
+                           sv_engine *out) {
+    return engine_create(dtype, max_batch, n_streams, hbm_budget_bytes, false, 0, out);
+}
+
+sv_status sv_engine_create_stepped(sv_dtype dtype, int max_active, int max_small_batch, int n_small_streams,
+                                   size_t hbm_budget_bytes, sv_engine *out) {
+    if (max_active < 1 || max_active > 65535)
+        return fail(SV_EINVAL, "max_active %d outside 1..65535", max_active);
+    return engine_create(dtype, max_small_batch, n_small_streams, hbm_budget_bytes, true, max_active, out);
 }
 
 sv_status sv_engine_free(sv_engine e) {
     return guarded([&]() -> sv_status {
         if (!e) return SV_OK;
         hipSetDevice(e->device);
+        stepped_release(e);
         hipError_t first = hipSuccess;
         for (auto &sp : e->slots) {
             Slot &s = *sp;
@@ -357,6 +727,8 @@ sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate
         if (!e) return fail(SV_EINVAL, "null engine");
         if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
         if (n_qubits > 30) return fail(SV_EUNSUPPORTED, "serving requests are limited to 30 qubits");
+        if (e->budget && ((size_t)1 << n_qubits) * e->amp_bytes > e->budget)
+            return fail(SV_ENOMEM, "a %d-qubit state exceeds the engine's HBM budget", n_qubits);
         if (qubit < 0 || qubit >= n_qubits) return fail(SV_EINVAL, "qubit %d out of range", qubit);
         if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
         if (n_params && !params) return fail(SV_EINVAL, "params is NULL");
@@ -399,8 +771,18 @@ sv_status sv_engine_poll(sv_engine e, int64_t wait_us, uint64_t *ids, double *va
             if (st != SV_OK) return st;
             st = launch_ready(e);
             if (st != SV_OK) return st;
+            if (e->stepped) {
+                st = stepped_retire(e);
+                if (st != SV_OK) return st;
+                for (size_t k = 0; k < e->steps.size(); ++k) {   // fill the free step slots
+                    const size_t before = e->step_order.size();
+                    st = stepped_launch(e);
+                    if (st != SV_OK) return st;
+                    if (e->step_order.size() == before) break;
+                }
+            }
             if (!e->finished.empty() || wait_us <= 0) break;
-            bool busy = false;
+            bool busy = !e->step_order.empty();
             for (auto &s : e->slots) busy = busy || s->busy;
             if (!busy && e->queue.empty()) break;
             const auto el = std::chrono::duration_cast<std::chrono::microseconds>(
@@ -423,8 +805,9 @@ sv_status sv_engine_poll(sv_engine e, int64_t wait_us, uint64_t *ids, double *va
 sv_status sv_engine_stats(sv_engine e, int64_t out[8]) {
     return guarded([&]() -> sv_status {
         if (!e || !out) return fail(SV_EINVAL, "null argument");
-        int64_t inflight = 0;
+        int64_t inflight = (int64_t)e->active.size();
         for (auto &s : e->slots) inflight += (int64_t)s->ids.size();
+        for (size_t k : e->step_order) inflight += (int64_t)e->steps[k].ids.size();
         out[0] = (int64_t)e->queue.size();
         out[1] = inflight;
         out[2] = e->completed;

@@ -873,30 +873,25 @@ __device__ __forceinline__ void run_ops(cpx<T> (&a)[1 << PassTraits<T>::R], cons
 // layer or basis state, or a product state) instead of loading it; only a
 // circuit's first pass does, and the generating code lives in its own variant
 // so that it does not weigh on the register allocation of the others.
+// One tile of a pass: load it (or generate it), run the pass's operations,
+// store it. `st` is the state, `opb` its op records, `tile` the tile number.
+// The plan records never alias the state (restrict): the compiler may then
+// read them with scalar loads even when their addresses come from memory.
 template <typename T, bool D2, bool FX, bool GEN>
-__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
-                                              const DevPass *__restrict__ passes, int pass_idx,
-                                              const DevLayout *__restrict__ layouts,
-                                              const DevOp *__restrict__ ops, uint64_t ops_stride) {
+__device__ __forceinline__ void pass_tile(cpx<T> *__restrict__ st, const DevPass *__restrict__ Pp,
+                                          const DevLayout *__restrict__ LB, const DevOp *__restrict__ opb,
+                                          uint64_t tile, int tid, char *const ldsb) {
+    const DevPass &P = *Pp;
     constexpr int R = PassTraits<T>::R;
     constexpr int W = PassTraits<T>::W;
     constexpr int NR = 1 << R;
-    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];   // a tile, or half a tile
-    char *const ldsb = reinterpret_cast<char *>(lds);
-
-    const DevPass &P = passes[pass_idx];
-    const int tid = threadIdx.x;
-    const DevLayout *LB = layouts + P.layout_begin;
-    cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
-    const DevOp *opb = ops + (uint64_t)blockIdx.y * ops_stride;
-
     const uint32_t *qw = reinterpret_cast<const uint32_t *>(P.q);
     uint32_t qv[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) qv[i] = qw[i];
 #pragma unroll
     for (int i = 0; i < 7; ++i) asm volatile("" : : "s"(qv[i]));   // one batch of scalar loads
-    const uint64_t base = tile_base(qv, P.k, xcd_tile(blockIdx.x, gridDim.x));
+    const uint64_t base = tile_base(qv, P.k, tile);
 
     const uint32_t warm = warm_records<W>(opb, P, LB, tid);
     cpx<T> a[NR];
@@ -919,6 +914,44 @@ __global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restri
 
     if (P.flags & PASS_SYNC_STORE) __syncthreads();
     store_tile<T, R, W>(a, st, LB[P.store_layout], base, tid);
+}
+
+template <typename T, bool D2, bool FX, bool GEN>
+__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass(cpx<T> *__restrict__ state, uint64_t n_amps,
+                                              const DevPass *__restrict__ passes, int pass_idx,
+                                              const DevLayout *__restrict__ layouts,
+                                              const DevOp *__restrict__ ops, uint64_t ops_stride) {
+    constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
+    constexpr int NR = 1 << R;
+    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];   // a tile, or half a tile
+    const DevPass &P = passes[pass_idx];
+    pass_tile<T, D2, FX, GEN>(state + (uint64_t)blockIdx.y * n_amps, &P, layouts + P.layout_begin,
+                              ops + (uint64_t)blockIdx.y * ops_stride, xcd_tile(blockIdx.x, gridDim.x),
+                              threadIdx.x, reinterpret_cast<char *>(lds));
+}
+
+// One pass of several independent states with their own plans (continuous
+// batching): workgroup b runs tile items[b].tile of the pass reqs[items[b].req]
+// names on that request's state. Each tile's arithmetic is the same as in
+// k_pass, so a state's result does not depend on what else shares a launch.
+// The plan records are addressed inside `arena` (a restrict argument, never
+// written by the kernel), which lets them be read through the scalar cache.
+template <typename T, bool D2, bool FX, bool GEN>
+__global__ __launch_bounds__(1 << PassTraits<T>::W) void k_pass_multi(const char *__restrict__ arena,
+                                                                      const StepReq *__restrict__ reqs,
+                                                                      const StepItem *__restrict__ items) {
+    constexpr int R = PassTraits<T>::R;
+    constexpr int W = PassTraits<T>::W;
+    constexpr int NR = 1 << R;
+    __shared__ cpx<T> lds[FX ? (NR << W) : (NR << W) / 2];
+    const StepItem it = items[blockIdx.x];
+    const StepReq &rq = reqs[it.req];
+    const DevPass *P = reinterpret_cast<const DevPass *>(arena + rq.passes_off) + rq.pass;
+    const DevLayout *LB = reinterpret_cast<const DevLayout *>(arena + rq.layouts_off) + P->layout_begin;
+    const DevOp *ops = reinterpret_cast<const DevOp *>(arena + rq.ops_off);
+    pass_tile<T, D2, FX, GEN>(reinterpret_cast<cpx<T> *>(rq.state), P, LB, ops, it.tile, threadIdx.x,
+                              reinterpret_cast<char *>(lds));
 }
 
 // Persistent variant for launches larger than the chip holds at once. Each
@@ -1215,6 +1248,39 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_final(const double *__re
     for (int i = threadIdx.x; i < nblk; i += kRedThreads) acc += p[i];
     const double s = block_tree_sum(acc, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// Several states' readouts in one launch (continuous batching): each work
+// item is one block of k_reduce_partial's decomposition of its state, summed
+// in the same order, so a request's result equals its single-state readout.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_multi(const RedItem *__restrict__ items,
+                                                              double *__restrict__ part) {
+    __shared__ double sh[kRedThreads];
+    const RedItem it = items[blockIdx.x];
+    const cpx<T> *st = static_cast<const cpx<T> *>(it.state);
+    const uint64_t lo = (uint64_t)it.blk * it.chunk;
+    double acc = 0.0;
+    for (uint64_t i = lo + threadIdx.x; i < lo + it.chunk; i += kRedThreads) {
+        const cpx<T> v = st[i];
+        const double re = (double)v.x, im = (double)v.y;
+        const double p = re * re + im * im;
+        acc += (it.qubit >= 0 && ((i >> it.qubit) & 1)) ? -p : p;
+    }
+    const double s = block_tree_sum(acc, sh);
+    if (threadIdx.x == 0) part[it.part] = s;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_final_multi(const FinItem *__restrict__ items,
+                                                             const double *__restrict__ part,
+                                                             double *__restrict__ out) {
+    __shared__ double sh[kRedThreads];
+    const FinItem it = items[blockIdx.x];
+    const double *p = part + it.first;
+    double acc = 0.0;
+    for (uint32_t i = threadIdx.x; i < it.count; i += kRedThreads) acc += p[i];
+    const double s = block_tree_sum(acc, sh);
+    if (threadIdx.x == 0) out[it.slot] = s;
 }
 
 template <typename T>
@@ -1726,6 +1792,50 @@ hipError_t launch_pass(int dt, void *state, uint64_t n_amps, int batch, const De
     return hipGetLastError();
 }
 
+hipError_t launch_pass_multi(int dt, const void *d_arena, const StepReq *d_reqs, const StepItem *d_items,
+                             uint32_t n_items, bool gen, bool d2, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    // always the half-tile exchange variant: a request runs the same code
+    // whatever the size of the launch it shares
+    const dim3 grid(n_items), block(1u << (dt == 2 ? kThreadBitsC128 : kThreadBitsC64));
+#define SV_MULTI(TT, D2V, GV) \
+    hipLaunchKernelGGL((k_pass_multi<TT, D2V, false, GV>), grid, block, 0, st, (const char *)d_arena, d_reqs, d_items)
+    if (dt == 2) {
+        if (d2) {
+            if (gen) SV_MULTI(double, true, true);
+            else SV_MULTI(double, true, false);
+        } else {
+            if (gen) SV_MULTI(double, false, true);
+            else SV_MULTI(double, false, false);
+        }
+    } else {
+        if (d2) {
+            if (gen) SV_MULTI(float, true, true);
+            else SV_MULTI(float, true, false);
+        } else {
+            if (gen) SV_MULTI(float, false, true);
+            else SV_MULTI(float, false, false);
+        }
+    }
+#undef SV_MULTI
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(int dt, const RedItem *d_items, uint32_t n_items, double *d_part,
+                               const FinItem *d_fin, uint32_t n_fin, double *d_out, hipStream_t st) {
+    if (n_items == 0 || n_fin == 0) return hipSuccess;
+    if (dt == 2)
+        hipLaunchKernelGGL(k_reduce_multi<double>, dim3(n_items), dim3(kRedThreads), 0, st, d_items, d_part);
+    else
+        hipLaunchKernelGGL(k_reduce_multi<float>, dim3(n_items), dim3(kRedThreads), 0, st, d_items, d_part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_final_multi, dim3(n_fin), dim3(kRedThreads), 0, st, d_fin, (const double *)d_part, d_out);
+    return hipGetLastError();
+}
+
+size_t reduce_chunk(int n) { return (size_t)((1ull << n) / (uint64_t)reduce_blocks(n)); }
+
 hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_ops, int n_ops,
                         const void *d_consts, uint64_t const_stride, hipStream_t st) {
     const uint32_t N = 1u << n;
@@ -1742,7 +1852,7 @@ hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_
 }
 
 // Number of stage-1 blocks per state: a function of n only (determinism).
-static int reduce_blocks(int n) {
+int reduce_blocks(int n) {
     if (n <= 12) return 1;
     const int b = n - 12;               // chunks of 4096 amplitudes ...
     return 1 << (b < 10 ? b : 10);      // ... at most 1024 blocks

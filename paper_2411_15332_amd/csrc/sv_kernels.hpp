@@ -49,6 +49,21 @@ hipError_t launch_small(int dt, void *state, int n, int batch, const SmallOp *d_
                         int n_ops, const void *d_consts, uint64_t const_stride,
                         hipStream_t st);
 
+// Continuous batching: one launch runs the current pass of several requests,
+// each on its own state with its own plan (records at byte offsets in
+// d_arena; items: one workgroup per tile; every pass of the launch generates
+// its input (gen) or none does, and holds a 4x4 gate (d2) or none does).
+hipError_t launch_pass_multi(int dt, const void *d_arena, const StepReq *d_reqs, const StepItem *d_items,
+                             uint32_t n_items, bool gen, bool d2, hipStream_t st);
+// Readouts of several states: items are (state, block) pieces of the
+// single-state reduction (reduce_blocks(n) blocks of reduce_chunk(n)
+// amplitudes each), summed in the same order; fin items give each result's
+// range of partials and its slot in d_out.
+int reduce_blocks(int n);
+size_t reduce_chunk(int n);
+hipError_t launch_reduce_multi(int dt, const RedItem *d_items, uint32_t n_items, double *d_part,
+                               const FinItem *d_fin, uint32_t n_fin, double *d_out, hipStream_t st);
+
 // Per-state sum of |a_i|^2 * (qubit < 0 ? 1 : 1 - 2 b_qubit(i)) in FP64.
 // d_partials needs reduce_partials_size(n) * batch doubles; d_out batch doubles.
 size_t reduce_partials_size(int n);

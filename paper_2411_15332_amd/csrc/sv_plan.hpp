@@ -190,4 +190,46 @@ struct SmallJob {     // 32 bytes
 };
 static_assert(sizeof(SmallJob) == 32, "SmallJob layout");
 
+// Continuous batching of tiled states: one launch advances every request
+// of a step by one pass of its own plan. StepReq: a request's state, the byte
+// offsets of its plan records in the engine's plan arena (passes and layouts
+// of its circuit, its own op records) and the pass this step runs; StepItem:
+// one workgroup's request (index into the step's StepReq table) and tile.
+struct StepReq {      // 48 bytes
+    void *state;
+    uint64_t passes_off;
+    uint64_t layouts_off;
+    uint64_t ops_off;
+    int32_t pass;
+    int32_t n;
+    uint64_t pad;
+};
+static_assert(sizeof(StepReq) == 48, "StepReq layout");
+struct StepItem {     // 8 bytes
+    uint32_t req;
+    uint32_t tile;
+};
+static_assert(sizeof(StepItem) == 8, "StepItem layout");
+
+// Readout of several states in one launch: work item b sums the amplitudes
+// [blk * chunk, (blk + 1) * chunk) of `state` with the signs of <Z_qubit>
+// into partial `part` (the same order as the single-state reduction).
+struct RedItem {      // 32 bytes
+    const void *state;
+    uint64_t chunk;
+    uint32_t blk;
+    int32_t qubit;
+    uint32_t part;
+    uint32_t pad;
+};
+static_assert(sizeof(RedItem) == 32, "RedItem layout");
+// Final sums: out[slot] = the fixed-tree sum of partials [first, first + count).
+struct FinItem {      // 16 bytes
+    uint32_t first;
+    uint32_t count;
+    uint32_t slot;
+    uint32_t pad;
+};
+static_assert(sizeof(FinItem) == 16, "FinItem layout");
+
 }  // namespace sv

@@ -21,12 +21,13 @@ def _engine_lib():
     if not getattr(L, "_engine_ready", False):
         P, I, U64, SZ, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int64
         L.sv_engine_create.argtypes = [I, I, I, SZ, ctypes.POINTER(P)]
+        L.sv_engine_create_stepped.argtypes = [I, I, I, I, SZ, ctypes.POINTER(P)]
         L.sv_engine_free.argtypes = [P]
         L.sv_engine_submit.argtypes = [P, U64, I, P, SZ, P, SZ, I]
         L.sv_engine_poll.argtypes = [P, I64, P, P, SZ, ctypes.POINTER(SZ)]
         L.sv_engine_stats.argtypes = [P, P]
-        for name in ("sv_engine_create", "sv_engine_free", "sv_engine_submit", "sv_engine_poll",
-                     "sv_engine_stats"):
+        for name in ("sv_engine_create", "sv_engine_create_stepped", "sv_engine_free", "sv_engine_submit",
+                     "sv_engine_poll", "sv_engine_stats"):
             getattr(L, name).restype = I
         L._engine_ready = True
     return L
@@ -34,14 +35,22 @@ def _engine_lib():
 
 class ServingEngine:
     """dtype "c64" or "c128"; max_batch requests per launch group; n_streams
-    groups in flight; hbm_budget_bytes of state memory (0: unlimited)."""
+    groups in flight; hbm_budget_bytes of state memory (0: unlimited).
+    stepped=True: continuous batching at pass granularity for the larger
+    states (sv_engine_create_stepped), with at most max_active of them on the
+    GPU; max_batch and n_streams then apply to the small states."""
 
     def __init__(self, dtype: str = "c64", max_batch: int = 256, n_streams: int = 4,
-                 hbm_budget_bytes: int = 0):
+                 hbm_budget_bytes: int = 0, stepped: bool = False, max_active: int = 256):
         self.L = _engine_lib()
         h = ctypes.c_void_p()
-        _check(self.L.sv_engine_create(SV_C64 if dtype == "c64" else SV_C128, int(max_batch),
-                                       int(n_streams), int(hbm_budget_bytes), ctypes.byref(h)))
+        dt = SV_C64 if dtype == "c64" else SV_C128
+        if stepped:
+            _check(self.L.sv_engine_create_stepped(dt, int(max_active), int(max_batch), int(n_streams),
+                                                   int(hbm_budget_bytes), ctypes.byref(h)))
+        else:
+            _check(self.L.sv_engine_create(dt, int(max_batch), int(n_streams), int(hbm_budget_bytes),
+                                           ctypes.byref(h)))
         self._h = h
         self.dtype = dtype
         self._ids = np.zeros(4096, dtype=np.uint64)

@@ -23,19 +23,23 @@ def _gates(P, r):
 
 
 def _drain(eng, count, timeout_us=30_000_000):
+    import time
     got = {}
+    t0 = time.perf_counter()
     while len(got) < count:
         res = eng.poll(wait_us=200_000)
         assert res or eng.stats()["in_flight"] or eng.stats()["queued"], "engine stalled"
         got.update(res)
+        assert (time.perf_counter() - t0) * 1e6 < timeout_us, f"engine did not drain: {len(got)}/{count}"
     return got
 
 
+@pytest.mark.parametrize("stepped", [False, True])
 @pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-12)])
-def test_mixed_stream_matches_oracle_and_solo(P, dtype, tol):
+def test_mixed_stream_matches_oracle_and_solo(P, dtype, tol, stepped):
     pkg, serving = P
     reqs = synth.poisson_requests(40, 1e9, seed=7, n_range=(8, 16), layer_range=(2, 5))
-    with serving.ServingEngine(dtype, max_batch=16, n_streams=4) as eng:
+    with serving.ServingEngine(dtype, max_batch=16, n_streams=4, stepped=stepped) as eng:
         for r in reqs:
             eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
         mixed = _drain(eng, len(reqs))
@@ -44,20 +48,48 @@ def test_mixed_stream_matches_oracle_and_solo(P, dtype, tol):
     for r in reqs:
         ref = O.loss_z(r.n, synth.qnn_ansatz(r.n, r.layers), r.params)
         assert abs(mixed[r.rid] - ref) <= tol, (r.n, r.layers)
-    # alone: one request per engine, one request per group
+    # alone: one request per engine, one request per group or step
     for r in reqs[:12]:
-        with serving.ServingEngine(dtype, max_batch=1, n_streams=1) as eng:
+        with serving.ServingEngine(dtype, max_batch=1, n_streams=1, stepped=stepped) as eng:
             eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
             solo = _drain(eng, 1)
         assert solo[r.rid] == mixed[r.rid]
 
 
-def test_admission_by_hbm_footprint(P):
+@pytest.mark.parametrize("dtype,tol", [("c64", 1e-5), ("c128", 1e-12)])
+def test_stepped_requests_join_while_others_run(P, dtype, tol):
+    """Requests of different n and depth submitted while earlier ones are
+    still on the GPU join at the next step: all results match the oracle and
+    equal each request's result alone, and steps held several requests."""
+    pkg, serving = P
+    reqs = synth.poisson_requests(24, 1e9, seed=21, n_range=(13, 19), layer_range=(2, 9))
+    with serving.ServingEngine(dtype, max_batch=8, n_streams=2, stepped=True, max_active=16) as eng:
+        got = {}
+        for i, r in enumerate(reqs):
+            eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
+            if i % 4 == 3:
+                got.update(eng.poll(wait_us=0))   # launch steps between arrivals
+        st0 = eng.stats()
+        got.update(_drain(eng, len(reqs) - len(got)))
+        st = eng.stats()
+    assert st["completed"] == len(reqs) and st["largest_group"] > 1 and st0["in_flight"] > 0
+    for r in reqs:
+        ref = O.loss_z(r.n, synth.qnn_ansatz(r.n, r.layers), r.params)
+        assert abs(got[r.rid] - ref) <= tol, (r.n, r.layers)
+    for r in reqs[:4]:
+        with serving.ServingEngine(dtype, max_batch=1, n_streams=1, stepped=True, max_active=1) as eng:
+            eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
+            assert _drain(eng, 1)[r.rid] == got[r.rid]
+
+
+@pytest.mark.parametrize("stepped", [False, True])
+def test_admission_by_hbm_footprint(P, stepped):
     pkg, serving = P
     n = 18                               # 2 MiB per complex64 state
     reqs = synth.poisson_requests(12, 1e9, seed=3, n_range=(n, n), layer_range=(2, 2))
     budget = 3 * (1 << n) * 8            # room for three states at a time
-    with serving.ServingEngine("c64", max_batch=8, n_streams=4, hbm_budget_bytes=budget) as eng:
+    with serving.ServingEngine("c64", max_batch=8, n_streams=4, hbm_budget_bytes=budget,
+                               stepped=stepped) as eng:
         for r in reqs:
             eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
         got = {}
@@ -83,4 +115,11 @@ def test_submit_validation(P):
         with pytest.raises(pkg.SVError) as e:
             eng.submit(3, 31, [synth.Gate("X", 0)])
         assert e.value.status == -4
+        assert eng.poll() == []
+    # a state that could never fit the HBM budget is refused at submission,
+    # and small states behind a waiting larger one still run
+    with serving.ServingEngine("c64", hbm_budget_bytes=(1 << 16) * 8) as eng:
+        with pytest.raises(pkg.SVError) as e:
+            eng.submit(4, 17, [synth.Gate("X", 0)])
+        assert e.value.status == -2
         assert eng.poll() == []
