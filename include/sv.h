@@ -323,6 +323,17 @@ sv_status sv_engine_free(sv_engine e);
 sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate *gates,
                            size_t n_gates, const double *params, size_t n_params, int qubit);
 
+/* Register a circuit with the engine once (validated and planned now, as
+ * in sv_engine_submit) for repeated submissions with other parameters:
+ * *circuit receives its handle (the same handle for the same circuit). */
+sv_status sv_engine_register(sv_engine e, int n_qubits, const sv_gate *gates, size_t n_gates, size_t n_params,
+                             int qubit, int64_t *circuit);
+
+/* Queue one evaluation of a registered circuit with its own parameters
+ * (exactly the registered n_params reals, copied). */
+sv_status sv_engine_submit_registered(sv_engine e, uint64_t id, int64_t circuit, const double *params,
+                                      size_t n_params);
+
 /* Retire finished groups, launch queued requests as streams and memory
  * allow, and return up to `cap` finished results (ids[i], values[i]) in
  * *count. wait_us > 0: wait up to that many microseconds for at least one

@@ -9,7 +9,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -45,6 +49,71 @@ struct Request {
     std::vector<double> params;
 };
 
+// A few host threads that share one batch of independent jobs with the
+// calling thread (the op records of a step's newly admitted requests).
+class JobPool {
+public:
+    explicit JobPool(int workers) {
+        for (int i = 0; i < workers; ++i) th_.emplace_back([this] { loop(); });
+    }
+    ~JobPool() {
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // Runs job(i) for i in [0, n) on the workers and the caller; returns when all are done.
+    void run(size_t n, const std::function<void(size_t)> &job) {
+        if (n == 0) return;
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            job_ = &job;
+            n_ = n;
+            next_.store(0);
+            left_ = n;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();
+        std::unique_lock<std::mutex> l(mu_);
+        done_cv_.wait(l, [this] { return left_ == 0; });
+        job_ = nullptr;
+    }
+
+private:
+    void work() {
+        for (;;) {
+            const size_t i = next_.fetch_add(1);
+            if (i >= n_) return;
+            (*job_)(i);
+            std::lock_guard<std::mutex> l(mu_);
+            if (--left_ == 0) done_cv_.notify_all();
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> l(mu_);
+                cv_.wait(l, [&] { return stop_ || (gen_ != seen && job_ != nullptr); });
+                if (stop_) return;
+                seen = gen_;
+            }
+            work();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(size_t)> *job_ = nullptr;
+    size_t n_ = 0, left_ = 0;
+    std::atomic<size_t> next_{0};
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
 // Stepped engine: a request on the GPU. It runs pass `next` of its plan in
 // the next step; its op records sit in the plan arena's ring at ops_off.
 struct Active {
@@ -54,6 +123,7 @@ struct Active {
     size_t bytes = 0;
     uint64_t ops_off = 0;
     size_t ring_entry = 0;   // its allocation in the ring (sequence number)
+    uint64_t ring_bytes = 0;
     int next = 0;
 };
 
@@ -91,13 +161,13 @@ struct Ring {
     }
 };
 
-// One step in flight: its tables (pinned staging and device copy), the
-// requests it completes and where their results land.
+// One step in flight: its device scratch (partial sums, results), the
+// requests it completes and where their results land. Its tables sit in the
+// plan arena's ring (released with the step).
 struct StepSlot {
     hipEvent_t done = nullptr;
     bool busy = false;
-    char *h_buf = nullptr;
-    size_t h_cap = 0;
+    uint64_t ops_bytes = 0;             // op record bytes of the requests it completes
     char *d_buf = nullptr;
     size_t d_cap = 0;
     double *h_res = nullptr;
@@ -135,14 +205,17 @@ struct sv_engine_s {
     int small_max = kSmallMaxQubitsC64;
     int device = 0;
     std::vector<std::unique_ptr<Slot>> slots;
-    std::deque<Request> queue;
+    std::deque<Request> queue;        // stepped mode: the larger states only
+    std::deque<Request> small_queue;  // stepped mode: the small states
     std::unordered_map<std::string, std::shared_ptr<Template>> templates;
+    std::vector<std::shared_ptr<Template>> registered;   // sv_engine_register handles
     std::deque<std::pair<uint64_t, double>> finished;
     size_t bytes_held = 0;
     int64_t completed = 0, groups = 0, largest = 0, deferred = 0, small_groups = 0;
     // stepped mode (SV_ENGINE_STEPPED): larger states advance one pass per step
     bool stepped = false;
     hipStream_t step_stream = nullptr;
+    hipMemPool_t pool = nullptr;   // state memory; keeps what is freed for the next requests
     char *d_arena = nullptr;
     char *h_arena = nullptr;     // pinned mirror: records are written here, then copied
     uint64_t arena_cap = 0, tmpl_used = 0, tmpl_cap = 0;
@@ -152,6 +225,10 @@ struct sv_engine_s {
     size_t next_step = 0;        // ring of step slots
     std::deque<size_t> step_order;   // busy step slots, oldest first
     int max_active = 64;
+    std::vector<std::pair<uint64_t, uint64_t>> uploads;   // arena ranges to copy with the next step
+    uint64_t ops_live = 0;   // ring bytes held by active requests' op records (at most half the ring,
+                             // so that step tables always find room)
+    std::unique_ptr<JobPool> jobs;   // materializes admitted requests' op records in parallel
 };
 
 namespace {
@@ -314,20 +391,18 @@ sv_status retire(sv_engine_s *e) {
 }
 
 sv_status launch_ready(sv_engine_s *e) {
+    // stepped mode: these slots serve the small states, from their own queue
+    std::deque<Request> &queue = e->stepped ? e->small_queue : e->queue;
     for (auto &sp : e->slots) {
         Slot &s = *sp;
         if (s.busy) continue;
-        if (e->queue.empty()) break;
-        // stepped mode: these slots serve the small states only
-        size_t fi = 0;
-        if (e->stepped)
-            while (fi < e->queue.size() && !e->queue[fi].t->small) ++fi;
-        if (fi == e->queue.size()) break;
-        const Request &front = e->queue[fi];
+        if (queue.empty()) break;
+        const size_t fi = 0;
+        const Request &front = queue[fi];
         bool small = front.t->small;
         std::vector<size_t> pick;
-        for (size_t i = fi; i < e->queue.size() && (int)pick.size() < e->max_batch; ++i) {
-            const Request &r = e->queue[i];
+        for (size_t i = fi; i < queue.size() && (int)pick.size() < e->max_batch; ++i) {
+            const Request &r = queue[i];
             if (small ? r.t->small : r.t == front.t) pick.push_back(i);
         }
         if (!small) {
@@ -346,11 +421,11 @@ sv_status launch_ready(sv_engine_s *e) {
                 // the group waits for memory held by groups in flight; small
                 // states hold none, so they may go ahead of it
                 size_t si = fi;
-                while (si < e->queue.size() && !e->queue[si].t->small) ++si;
-                if (si == e->queue.size()) break;
+                while (si < queue.size() && !queue[si].t->small) ++si;
+                if (si == queue.size()) break;
                 pick.clear();
-                for (size_t i = si; i < e->queue.size() && (int)pick.size() < e->max_batch; ++i)
-                    if (e->queue[i].t->small) pick.push_back(i);
+                for (size_t i = si; i < queue.size() && (int)pick.size() < e->max_batch; ++i)
+                    if (queue[i].t->small) pick.push_back(i);
                 small = true;
             } else {
                 pick.resize(k);
@@ -358,8 +433,8 @@ sv_status launch_ready(sv_engine_s *e) {
         }
         std::vector<Request> grp;
         grp.reserve(pick.size());
-        for (size_t i : pick) grp.push_back(std::move(e->queue[i]));
-        for (size_t j = pick.size(); j-- > 0;) e->queue.erase(e->queue.begin() + (long)pick[j]);
+        for (size_t i : pick) grp.push_back(std::move(queue[i]));
+        for (size_t j = pick.size(); j-- > 0;) queue.erase(queue.begin() + (long)pick[j]);
         sv_status st = small ? launch_small_group(e, s, grp) : launch_large_group(e, s, grp);
         if (st != SV_OK) return st;
         sv_status st2 = ensure_pinned(reinterpret_cast<void **>(&s.h_res), &s.h_res_cap,
@@ -385,12 +460,20 @@ sv_status launch_ready(sv_engine_s *e) {
 // arrival; a step's tables are small, and the per-request op records go to
 // the plan arena once, at admission.
 
-constexpr int kStepSlots = 3;                   // steps in flight
+constexpr int kStepSlots = 4;                   // steps in flight
 constexpr uint64_t kArenaBytes = 256ull << 20;  // plan arena (templates + op records)
 constexpr uint64_t kTemplateBytes = 32ull << 20;
 
 sv_status stepped_init(sv_engine_s *e) {
     SV_HIP(hipStreamCreateWithFlags(&e->step_stream, hipStreamNonBlocking), "engine step stream");
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof props);
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = e->device;
+    SV_HIP(hipMemPoolCreate(&e->pool, &props), "hipMemPoolCreate");
+    uint64_t keep = ~0ull;   // never hand freed state memory back to the driver
+    SV_HIP(hipMemPoolSetAttribute(e->pool, hipMemPoolAttrReleaseThreshold, &keep), "hipMemPoolSetAttribute");
     e->arena_cap = kArenaBytes;
     e->tmpl_cap = kTemplateBytes;
     SV_HIP(hipMalloc(reinterpret_cast<void **>(&e->d_arena), e->arena_cap), "hipMalloc(plan arena)");
@@ -399,17 +482,21 @@ sv_status stepped_init(sv_engine_s *e) {
     e->ring.rb = e->tmpl_cap;
     e->ring.re = e->arena_cap;
     e->steps.resize(kStepSlots);
+    e->jobs = std::make_unique<JobPool>(3);
     for (StepSlot &S : e->steps) SV_HIP(hipEventCreateWithFlags(&S.done, hipEventDisableTiming), "hipEventCreate");
     return SV_OK;
 }
 
 void stepped_release(sv_engine_s *e) {
-    if (e->step_stream) hipStreamSynchronize(e->step_stream);
-    for (Active &a : e->active)
-        if (a.state) hipFree(a.state);
+    e->jobs.reset();
+    if (e->step_stream) {
+        hipStreamSynchronize(e->step_stream);
+        for (Active &a : e->active)
+            if (a.state) hipFreeAsync(a.state, e->step_stream);
+        hipStreamSynchronize(e->step_stream);
+    }
     e->active.clear();
     for (StepSlot &S : e->steps) {
-        if (S.h_buf) hipHostFree(S.h_buf);
         if (S.d_buf) hipFree(S.d_buf);
         if (S.h_res) hipHostFree(S.h_res);
         if (S.done) hipEventDestroy(S.done);
@@ -418,6 +505,8 @@ void stepped_release(sv_engine_s *e) {
     if (e->d_arena) hipFree(e->d_arena);
     if (e->h_arena) hipHostFree(e->h_arena);
     e->d_arena = e->h_arena = nullptr;
+    if (e->pool) hipMemPoolDestroy(e->pool);
+    e->pool = nullptr;
     if (e->step_stream) hipStreamDestroy(e->step_stream);
     e->step_stream = nullptr;
 }
@@ -441,17 +530,32 @@ sv_status stepped_template(sv_engine_s *e, Template &t) {
     return SV_OK;
 }
 
+// Ring bytes written on the host this step, uploaded in one copy (two when
+// the ring wrapped) before the step's launches.
+void stepped_note_upload(sv_engine_s *e, uint64_t off, uint64_t size) {
+    auto &u = e->uploads;
+    if (!u.empty() && u.back().second == off) u.back().second = off + size;
+    else u.emplace_back(off, off + size);
+}
+
+sv_status stepped_flush_uploads(sv_engine_s *e) {
+    for (auto &r : e->uploads)
+        SV_HIP(hipMemcpyAsync(e->d_arena + r.first, e->h_arena + r.first, r.second - r.first, hipMemcpyHostToDevice,
+                              e->step_stream),
+               "hipMemcpyAsync(plan arena)");
+    e->uploads.clear();
+    return SV_OK;
+}
+
 // Admit queued larger-state requests while the active set, the HBM budget
 // and the arena allow: state memory (stream-ordered) and op records.
 sv_status stepped_admit(sv_engine_s *e) {
     const bool f32 = e->dt == SV_C64;
+    struct Mat { const Template *t; std::vector<double> params; uint64_t off; };
+    std::vector<Mat> mats;
     size_t i = 0;
     while (i < e->queue.size() && (int)e->active.size() < e->max_active) {
         Request &r = e->queue[i];
-        if (r.t->small) {
-            ++i;
-            continue;
-        }
         Template &t = *r.t;
         const size_t bytes = ((size_t)1 << t.n) * e->amp_bytes;
         if (e->budget && e->bytes_held + bytes > e->budget) {
@@ -459,8 +563,10 @@ sv_status stepped_admit(sv_engine_s *e) {
             break;   // admission by HBM footprint: wait for running requests to finish
         }
         const uint64_t ob = (uint64_t)t.plan.ops.size() * sizeof(DevOp);
+        const uint64_t held = (std::max<uint64_t>(ob, 256) + 255) & ~(uint64_t)255;
+        if (e->ops_live + held > (e->ring.re - e->ring.rb) / 2) break;   // wait for arena space
         uint64_t off = 0, seq = 0;
-        if (!e->ring.alloc(std::max<uint64_t>(ob, 256), off, seq)) break;   // wait for arena space
+        if (!e->ring.alloc(held, off, seq)) break;
         sv_status st = stepped_template(e, t);
         if (st != SV_OK) return st;
         Active a;
@@ -469,18 +575,30 @@ sv_status stepped_admit(sv_engine_s *e) {
         a.bytes = bytes;
         a.ops_off = off;
         a.ring_entry = seq;
-        SV_HIP(hipMallocAsync(&a.state, bytes, e->step_stream), "hipMallocAsync(state)");
-        if (ob) {
-            materialize_ops(t.plan, t.gates.data(), r.params.data(), t.n_params, 1, f32, e->h_arena + off);
-            SV_HIP(hipMemcpyAsync(e->d_arena + off, e->h_arena + off, ob, hipMemcpyHostToDevice, e->step_stream),
-                   "hipMemcpyAsync(op records)");
-        }
+        a.ring_bytes = held;
+        e->ops_live += held;
+        SV_HIP(hipMallocFromPoolAsync(&a.state, bytes, e->pool, e->step_stream), "hipMallocFromPoolAsync(state)");
+        if (ob) mats.push_back({&t, std::move(r.params), off});
+        stepped_note_upload(e, off, held);   // the allocation's extent: neighbours merge
         if (t.plan.passes.empty())   // nothing to apply: the readout sees |0...0>
             SV_HIP(launch_fill_basis((int)e->dt, a.state, 1ull << t.n, 1, 0, e->step_stream), "launch fill");
         e->bytes_held += bytes;
         e->active.push_back(std::move(a));
         e->queue.erase(e->queue.begin() + (long)i);
     }
+    // op records of the admitted requests, several at a time (each job writes
+    // its own ring range of the pinned mirror)
+    std::atomic<bool> bad{false};
+    e->jobs->run(mats.size(), [&](size_t k) {
+        const Mat &m = mats[k];
+        try {
+            materialize_ops(m.t->plan, m.t->gates.data(), m.params.data(), m.t->n_params, 1, f32,
+                            e->h_arena + m.off);
+        } catch (...) {   // no exception may leave a worker thread
+            bad.store(true);
+        }
+    });
+    if (bad.load()) return fail(SV_EUNSUPPORTED, "serving engine: op records could not be built");
     return SV_OK;
 }
 
@@ -496,16 +614,17 @@ sv_status stepped_launch(sv_engine_s *e) {
     std::vector<StepItem> items[4];   // bit 0: generating pass, bit 1: pass with a 4x4
     std::vector<RedItem> reds;
     std::vector<FinItem> fins;
-    S.ids.clear();
-    S.ring_seqs.clear();
-    std::vector<size_t> done_idx;
+    std::vector<uint64_t> ids, seqs;
+    std::vector<size_t> run_idx, done_idx;
+    uint64_t done_ops = 0;
     uint32_t parts = 0;
     for (size_t ai = 0; ai < e->active.size(); ++ai) {
-        Active &a = e->active[ai];
+        const Active &a = e->active[ai];
         const Template &t = *a.t;
         const int np = (int)t.plan.passes.size();
-        if (a.next < np) {
-            const DevPass &P = t.plan.passes[(size_t)a.next];
+        int next = a.next;
+        if (next < np) {
+            const DevPass &P = t.plan.passes[(size_t)next];
             if (P.w != (e->dt == SV_C128 ? kThreadBitsC128 : kThreadBitsC64))
                 return fail(SV_EUNSUPPORTED, "serving engine: tile geometry of a %d-qubit plan", t.n);
             StepReq q;
@@ -514,15 +633,16 @@ sv_status stepped_launch(sv_engine_s *e) {
             q.passes_off = t.passes_off;
             q.layouts_off = t.layouts_off;
             q.ops_off = a.ops_off;
-            q.pass = a.next;
+            q.pass = next;
             q.n = t.n;
             const uint32_t ri = (uint32_t)reqs.size();
             reqs.push_back(q);
             const int v = ((P.flags & PASS_GENERATES) ? 1 : 0) | ((P.flags & PASS_DENSE2) ? 2 : 0);
             for (uint64_t tile = 0; tile < P.tiles; ++tile) items[v].push_back({ri, (uint32_t)tile});
-            ++a.next;
+            run_idx.push_back(ai);
+            ++next;
         }
-        if (a.next >= np) {   // this step completes it: batched readout
+        if (next >= np) {   // this step completes it: batched readout
             const uint32_t nblk = (uint32_t)reduce_blocks(t.n);
             const uint64_t chunk = reduce_chunk(t.n);
             for (uint32_t b = 0; b < nblk; ++b) {
@@ -539,16 +659,18 @@ sv_status stepped_launch(sv_engine_s *e) {
             std::memset(&f, 0, sizeof f);
             f.first = parts;
             f.count = nblk;
-            f.slot = (uint32_t)S.ids.size();
+            f.slot = (uint32_t)ids.size();
             fins.push_back(f);
             parts += nblk;
-            S.ids.push_back(a.id);
-            S.ring_seqs.push_back(a.ring_entry);
+            ids.push_back(a.id);
+            seqs.push_back(a.ring_entry);
             done_idx.push_back(ai);
+            done_ops += a.ring_bytes;
         }
     }
 
-    // step tables: one upload; partial sums and results live on the device only
+    // step tables: in the ring, uploaded with the step's op records in one
+    // copy; partial sums and results live on the device only
     size_t off = 0;
     auto sec = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes, 256); return o; };
     const size_t o_req = sec(reqs.size() * sizeof(StepReq));
@@ -556,18 +678,25 @@ sv_status stepped_launch(sv_engine_s *e) {
     for (int v = 0; v < 4; ++v) o_it[v] = sec(items[v].size() * sizeof(StepItem));
     const size_t o_red = sec(reds.size() * sizeof(RedItem));
     const size_t o_fin = sec(fins.size() * sizeof(FinItem));
-    const size_t up = off;
-    const size_t o_part = sec((size_t)parts * sizeof(double));
-    const size_t o_res = sec(fins.size() * sizeof(double));
-    const size_t total = std::max<size_t>(off, 256);
-    if (S.h_cap < up) {
-        if (S.h_buf) hipHostFree(S.h_buf);
-        S.h_buf = nullptr;
-        S.h_cap = 0;
-        SV_HIP(hipHostMalloc(reinterpret_cast<void **>(&S.h_buf), std::max<size_t>(up, 1) * 2, hipHostMallocDefault),
-               "hipHostMalloc(step)");
-        S.h_cap = std::max<size_t>(up, 1) * 2;
-    }
+    const size_t up = std::max<size_t>(off, 256);
+    uint64_t toff = 0, tseq = 0;
+    if (!e->ring.alloc(up, toff, tseq))
+        return stepped_flush_uploads(e);   // no room for the tables yet: this step is built later
+    for (size_t ai : run_idx) ++e->active[ai].next;
+    S.ids = std::move(ids);
+    S.ring_seqs = std::move(seqs);
+    S.ops_bytes = done_ops;
+    S.ring_seqs.push_back(tseq);
+    const uint64_t tsize = (up + 255) & ~(uint64_t)255;
+    char *ht = e->h_arena + toff;
+    std::memcpy(ht + o_req, reqs.data(), reqs.size() * sizeof(StepReq));
+    for (int v = 0; v < 4; ++v) std::memcpy(ht + o_it[v], items[v].data(), items[v].size() * sizeof(StepItem));
+    std::memcpy(ht + o_red, reds.data(), reds.size() * sizeof(RedItem));
+    std::memcpy(ht + o_fin, fins.data(), fins.size() * sizeof(FinItem));
+    stepped_note_upload(e, toff, tsize);
+    const size_t o_part = 0;
+    const size_t o_res = align_up((size_t)parts * sizeof(double), 256);
+    const size_t total = std::max<size_t>(o_res + align_up(fins.size() * sizeof(double), 256), 256);
     if (S.d_cap < total) {
         if (S.d_buf) hipFree(S.d_buf);
         S.d_buf = nullptr;
@@ -575,22 +704,20 @@ sv_status stepped_launch(sv_engine_s *e) {
         SV_HIP(hipMalloc(reinterpret_cast<void **>(&S.d_buf), total * 2), "hipMalloc(step)");
         S.d_cap = total * 2;
     }
-    std::memcpy(S.h_buf + o_req, reqs.data(), reqs.size() * sizeof(StepReq));
-    for (int v = 0; v < 4; ++v) std::memcpy(S.h_buf + o_it[v], items[v].data(), items[v].size() * sizeof(StepItem));
-    std::memcpy(S.h_buf + o_red, reds.data(), reds.size() * sizeof(RedItem));
-    std::memcpy(S.h_buf + o_fin, fins.data(), fins.size() * sizeof(FinItem));
     hipStream_t ss = e->step_stream;
-    if (up) SV_HIP(hipMemcpyAsync(S.d_buf, S.h_buf, up, hipMemcpyHostToDevice, ss), "hipMemcpyAsync(step)");
-    const StepReq *d_req = reinterpret_cast<const StepReq *>(S.d_buf + o_req);
+    st = stepped_flush_uploads(e);
+    if (st != SV_OK) return st;
+    char *dt = e->d_arena + toff;
+    const StepReq *d_req = reinterpret_cast<const StepReq *>(dt + o_req);
     for (int v = 0; v < 4; ++v)
-        SV_HIP(launch_pass_multi((int)e->dt, e->d_arena, d_req, reinterpret_cast<const StepItem *>(S.d_buf + o_it[v]),
+        SV_HIP(launch_pass_multi((int)e->dt, e->d_arena, d_req, reinterpret_cast<const StepItem *>(dt + o_it[v]),
                                  (uint32_t)items[v].size(), (v & 1) != 0, (v & 2) != 0, ss),
                "launch step");
     if (!fins.empty()) {
         double *d_res = reinterpret_cast<double *>(S.d_buf + o_res);
-        SV_HIP(launch_reduce_multi((int)e->dt, reinterpret_cast<const RedItem *>(S.d_buf + o_red), (uint32_t)reds.size(),
+        SV_HIP(launch_reduce_multi((int)e->dt, reinterpret_cast<const RedItem *>(dt + o_red), (uint32_t)reds.size(),
                                    reinterpret_cast<double *>(S.d_buf + o_part),
-                                   reinterpret_cast<const FinItem *>(S.d_buf + o_fin), (uint32_t)fins.size(), d_res, ss),
+                                   reinterpret_cast<const FinItem *>(dt + o_fin), (uint32_t)fins.size(), d_res, ss),
                "launch step readout");
         st = ensure_pinned(reinterpret_cast<void **>(&S.h_res), &S.h_res_cap, fins.size() * sizeof(double));
         if (st != SV_OK) return st;
@@ -626,6 +753,8 @@ sv_status stepped_retire(sv_engine_s *e) {
         for (size_t i = 0; i < S.ids.size(); ++i) e->finished.emplace_back(S.ids[i], S.h_res[i]);
         e->completed += (int64_t)S.ids.size();
         for (uint64_t seq : S.ring_seqs) e->ring.release(seq);
+        e->ops_live -= S.ops_bytes;
+        S.ops_bytes = 0;
         S.ids.clear();
         S.ring_seqs.clear();
         S.busy = false;
@@ -721,39 +850,100 @@ sv_status sv_engine_free(sv_engine e) {
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// The engine's template of a circuit (planned once per distinct circuit).
+sv_status engine_template(sv_engine_s *e, int n_qubits, const sv_gate *gates, size_t n_gates,
+                          size_t n_params, bool have_params, int qubit, std::shared_ptr<Template> &out) {
+    if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
+    if (n_qubits > 30) return fail(SV_EUNSUPPORTED, "serving requests are limited to 30 qubits");
+    if (e->budget && ((size_t)1 << n_qubits) * e->amp_bytes > e->budget)
+        return fail(SV_ENOMEM, "a %d-qubit state exceeds the engine's HBM budget", n_qubits);
+    if (qubit < 0 || qubit >= n_qubits) return fail(SV_EINVAL, "qubit %d out of range", qubit);
+    if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
+    std::string err;
+    if (!validate_gates(n_qubits, gates, n_gates, n_params, have_params, err))
+        return fail(SV_EINVAL, "%s", err.c_str());
+    const std::string key = template_key(n_qubits, qubit, n_params, gates, n_gates);
+    auto it = e->templates.find(key);
+    if (it == e->templates.end()) {
+        auto t = std::make_shared<Template>();
+        t->n = n_qubits;
+        t->qubit = qubit;
+        lower_gates(gates, n_gates, n_params, t->low);
+        t->gates = t->low.gates;
+        t->n_params = n_params + t->low.src.size();
+        t->small = n_qubits <= e->small_max;
+        t->plan = build_plan(n_qubits, t->gates.data(), t->gates.size(), engine_plan_options(e, t->small));
+        if (e->stepped && !t->small && (uint64_t)t->plan.ops.size() * sizeof(DevOp) > (e->ring.re - e->ring.rb) / 4)
+            return fail(SV_ENOMEM, "serving engine: the circuit's op records exceed the plan arena");
+        it = e->templates.emplace(key, std::move(t)).first;
+    }
+    out = it->second;
+    return SV_OK;
+}
+
+void engine_enqueue(sv_engine_s *e, uint64_t id, const std::shared_ptr<Template> &t, const double *params,
+                    size_t n_params) {
+    Request r;
+    r.id = id;
+    r.t = t;
+    if (t->low.src.empty()) r.params.assign(params, params + n_params);
+    else lower_params(t->low, params, n_params, 1, r.params);
+    if (e->stepped && t->small) e->small_queue.push_back(std::move(r));
+    else e->queue.push_back(std::move(r));
+}
+
+}  // namespace
+
+extern "C" {
+
 sv_status sv_engine_submit(sv_engine e, uint64_t id, int n_qubits, const sv_gate *gates, size_t n_gates,
                            const double *params, size_t n_params, int qubit) {
     return guarded([&]() -> sv_status {
         if (!e) return fail(SV_EINVAL, "null engine");
-        if (n_qubits < 1 || n_qubits > 34) return fail(SV_EINVAL, "n_qubits %d outside 1..34", n_qubits);
-        if (n_qubits > 30) return fail(SV_EUNSUPPORTED, "serving requests are limited to 30 qubits");
-        if (e->budget && ((size_t)1 << n_qubits) * e->amp_bytes > e->budget)
-            return fail(SV_ENOMEM, "a %d-qubit state exceeds the engine's HBM budget", n_qubits);
-        if (qubit < 0 || qubit >= n_qubits) return fail(SV_EINVAL, "qubit %d out of range", qubit);
-        if (n_gates && !gates) return fail(SV_EINVAL, "gates is NULL");
         if (n_params && !params) return fail(SV_EINVAL, "params is NULL");
-        std::string err;
-        if (!validate_gates(n_qubits, gates, n_gates, n_params, params != nullptr || n_params == 0, err))
-            return fail(SV_EINVAL, "%s", err.c_str());
-        const std::string key = template_key(n_qubits, qubit, n_params, gates, n_gates);
-        auto it = e->templates.find(key);
-        if (it == e->templates.end()) {
-            auto t = std::make_shared<Template>();
-            t->n = n_qubits;
-            t->qubit = qubit;
-            lower_gates(gates, n_gates, n_params, t->low);
-            t->gates = t->low.gates;
-            t->n_params = n_params + t->low.src.size();
-            t->small = n_qubits <= e->small_max;
-            t->plan = build_plan(n_qubits, t->gates.data(), t->gates.size(), engine_plan_options(e, t->small));
-            it = e->templates.emplace(key, std::move(t)).first;
-        }
-        Request r;
-        r.id = id;
-        r.t = it->second;
-        if (it->second->low.src.empty()) r.params.assign(params, params + n_params);
-        else lower_params(it->second->low, params, n_params, 1, r.params);
-        e->queue.push_back(std::move(r));
+        std::shared_ptr<Template> t;
+        sv_status st = engine_template(e, n_qubits, gates, n_gates, n_params, params != nullptr || n_params == 0,
+                                       qubit, t);
+        if (st != SV_OK) return st;
+        engine_enqueue(e, id, t, params, n_params);
+        return SV_OK;
+    });
+}
+
+sv_status sv_engine_register(sv_engine e, int n_qubits, const sv_gate *gates, size_t n_gates, size_t n_params,
+                             int qubit, int64_t *circuit) {
+    return guarded([&]() -> sv_status {
+        if (!e || !circuit) return fail(SV_EINVAL, "null argument");
+        std::shared_ptr<Template> t;
+        sv_status st = engine_template(e, n_qubits, gates, n_gates, n_params, true, qubit, t);
+        if (st != SV_OK) return st;
+        for (size_t i = 0; i < e->registered.size(); ++i)
+            if (e->registered[i] == t) {
+                *circuit = (int64_t)i;
+                return SV_OK;
+            }
+        *circuit = (int64_t)e->registered.size();
+        e->registered.push_back(t);
+        return SV_OK;
+    });
+}
+
+sv_status sv_engine_submit_registered(sv_engine e, uint64_t id, int64_t circuit, const double *params,
+                                      size_t n_params) {
+    return guarded([&]() -> sv_status {
+        if (!e) return fail(SV_EINVAL, "null engine");
+        if (circuit < 0 || (size_t)circuit >= e->registered.size())
+            return fail(SV_EINVAL, "unknown circuit %lld", (long long)circuit);
+        const std::shared_ptr<Template> &t = e->registered[(size_t)circuit];
+        const size_t want = t->n_params - t->low.src.size();
+        if (n_params != want) return fail(SV_EINVAL, "circuit %lld takes %zu parameters, got %zu",
+                                          (long long)circuit, want, n_params);
+        if (n_params && !params) return fail(SV_EINVAL, "params is NULL");
+        engine_enqueue(e, id, t, params, n_params);
         return SV_OK;
     });
 }
@@ -782,9 +972,9 @@ sv_status sv_engine_poll(sv_engine e, int64_t wait_us, uint64_t *ids, double *va
                 }
             }
             if (!e->finished.empty() || wait_us <= 0) break;
-            bool busy = !e->step_order.empty();
+            bool busy = !e->step_order.empty() || !e->active.empty();
             for (auto &s : e->slots) busy = busy || s->busy;
-            if (!busy && e->queue.empty()) break;
+            if (!busy && e->queue.empty() && e->small_queue.empty()) break;
             const auto el = std::chrono::duration_cast<std::chrono::microseconds>(
                 std::chrono::steady_clock::now() - t0).count();
             if (el >= wait_us) break;
@@ -808,7 +998,7 @@ sv_status sv_engine_stats(sv_engine e, int64_t out[8]) {
         int64_t inflight = (int64_t)e->active.size();
         for (auto &s : e->slots) inflight += (int64_t)s->ids.size();
         for (size_t k : e->step_order) inflight += (int64_t)e->steps[k].ids.size();
-        out[0] = (int64_t)e->queue.size();
+        out[0] = (int64_t)(e->queue.size() + e->small_queue.size());
         out[1] = inflight;
         out[2] = e->completed;
         out[3] = e->groups;

@@ -26,8 +26,10 @@ def _engine_lib():
         L.sv_engine_submit.argtypes = [P, U64, I, P, SZ, P, SZ, I]
         L.sv_engine_poll.argtypes = [P, I64, P, P, SZ, ctypes.POINTER(SZ)]
         L.sv_engine_stats.argtypes = [P, P]
+        L.sv_engine_register.argtypes = [P, I, P, SZ, SZ, I, ctypes.POINTER(I64)]
+        L.sv_engine_submit_registered.argtypes = [P, U64, I64, P, SZ]
         for name in ("sv_engine_create", "sv_engine_create_stepped", "sv_engine_free", "sv_engine_submit",
-                     "sv_engine_poll", "sv_engine_stats"):
+                     "sv_engine_poll", "sv_engine_stats", "sv_engine_register", "sv_engine_submit_registered"):
             getattr(L, name).restype = I
         L._engine_ready = True
     return L
@@ -80,6 +82,19 @@ class ServingEngine:
         _check(self.L.sv_engine_submit(self._h, int(rid), int(n), _ptr(arr), len(arr), _ptr(p),
                                        0 if p is None else len(p), int(qubit)))
 
+    def register(self, n: int, gates, n_params: int, qubit: int = 0) -> int:
+        """Plan a circuit once; returns its handle for submit_registered."""
+        arr = gates if isinstance(gates, np.ndarray) and gates.dtype == GATE_DTYPE else gate_array(gates)
+        arr = np.ascontiguousarray(arr)
+        cid = ctypes.c_int64()
+        _check(self.L.sv_engine_register(self._h, int(n), _ptr(arr), len(arr), int(n_params), int(qubit),
+                                         ctypes.byref(cid)))
+        return cid.value
+
+    def submit_registered(self, rid: int, circuit: int, params: np.ndarray) -> None:
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).ravel())
+        _check(self.L.sv_engine_submit_registered(self._h, int(rid), int(circuit), _ptr(p), len(p)))
+
     def poll(self, wait_us: int = 0) -> List[Tuple[int, float]]:
         cnt = ctypes.c_size_t()
         _check(self.L.sv_engine_poll(self._h, int(wait_us), _ptr(self._ids), _ptr(self._vals),
@@ -96,11 +111,25 @@ class ServingEngine:
 
 
 def run_stream(engine: ServingEngine, requests: Sequence, gates_of, rate_scale: float = 1.0,
-               timeout_s: float = 120.0) -> Dict[str, object]:
+               timeout_s: float = 120.0, key_of=None) -> Dict[str, object]:
     """Replay ``requests`` (objects with rid, arrival_s, n, params) against the
     engine in real time: request r is submitted when the clock passes
-    r.arrival_s * rate_scale. gates_of(r) gives its sv_gate array.
+    r.arrival_s * rate_scale. gates_of(r) gives its sv_gate array; with
+    key_of(r) (a hashable circuit key), each distinct circuit is registered
+    once and requests are submitted by handle.
     Returns per-request latency (s) and result, plus the wall time."""
+    cids: Dict[object, int] = {}
+
+    def submit(r):
+        if key_of is None:
+            engine.submit(r.rid, r.n, gates_of(r), r.params, 0)
+            return
+        k = key_of(r)
+        cid = cids.get(k)
+        if cid is None:
+            cid = cids[k] = engine.register(r.n, gates_of(r), len(r.params), 0)
+        engine.submit_registered(r.rid, cid, r.params)
+
     order = sorted(requests, key=lambda r: r.arrival_s)
     arrival = {r.rid: r.arrival_s * rate_scale for r in order}
     done: Dict[int, Tuple[float, float]] = {}
@@ -111,8 +140,7 @@ def run_stream(engine: ServingEngine, requests: Sequence, gates_of, rate_scale: 
         if now > timeout_s:
             raise TimeoutError(f"stream did not drain in {timeout_s} s ({len(done)}/{len(order)})")
         while i < len(order) and arrival[order[i].rid] <= now:
-            r = order[i]
-            engine.submit(r.rid, r.n, gates_of(r), r.params, 0)
+            submit(order[i])
             i += 1
         nxt = arrival[order[i].rid] - now if i < len(order) else 1e9
         wait = int(max(0.0, min(nxt, 0.002)) * 1e6)

@@ -123,3 +123,28 @@ def test_submit_validation(P):
             eng.submit(4, 17, [synth.Gate("X", 0)])
         assert e.value.status == -2
         assert eng.poll() == []
+
+
+@pytest.mark.parametrize("stepped", [False, True])
+def test_registered_circuits(P, stepped):
+    """Requests submitted by registered circuit handle give the results of
+    the same requests submitted with their gate lists."""
+    pkg, serving = P
+    reqs = synth.poisson_requests(16, 1e9, seed=5, n_range=(10, 15), layer_range=(2, 4))
+    with serving.ServingEngine("c64", max_batch=8, n_streams=2, stepped=stepped) as eng:
+        cid = {}
+        for r in reqs:
+            k = (r.n, r.layers)
+            if k not in cid:
+                cid[k] = eng.register(r.n, _gates(pkg, r), len(r.params), 0)
+            eng.submit_registered(r.rid, cid[k], r.params)
+        by_handle = _drain(eng, len(reqs))
+        with pytest.raises(pkg.SVError):
+            eng.submit_registered(999, len(cid) + 5, reqs[0].params)
+        with pytest.raises(pkg.SVError):
+            eng.submit_registered(998, cid[(reqs[0].n, reqs[0].layers)], reqs[0].params[:-1])
+    with serving.ServingEngine("c64", max_batch=8, n_streams=2, stepped=stepped) as eng:
+        for r in reqs:
+            eng.submit(r.rid, r.n, _gates(pkg, r), r.params, 0)
+        by_gates = _drain(eng, len(reqs))
+    assert by_handle == by_gates
