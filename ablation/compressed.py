@@ -1,10 +1,9 @@
-"""DAX and DAS compressed operators, their MTP and MVM — TEST INFRASTRUCTURE ONLY.
+"""DAX and DAS compressed operators, their MTP and MVM (host ablation).
 
 The paper's whole-operator formats (Sec. III-A), written from their
 description, for the host ablations of the paper (Matrix vs DAX vs DAS,
-Figs. 6-7) and as an independent route to operator products. Only tests may
-use this module; the GPU path applies each gate in its own gate-local form
-and never builds a whole-operator structure.
+Figs. 6-7). The GPU path applies each gate in its own gate-local form and
+never builds a whole-operator structure.
 
 - DAX (Sec. III-A1): every non-zero element is an entry of (real part,
   imaginary part, index), the index being the element's position in the

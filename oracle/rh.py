@@ -14,14 +14,17 @@ the GPU path's Hadamard handling.
 - ``rh_mvm_quarter``: Method 1, signs of the upper-left quarter only.
 - ``rh_mvm_block``: Method 2 with block size b (Theorem 3's optimum is
   b = sqrt(2^(n-1))).
-- ``rh_mvm_logarithm``: Method 3 / Algorithm 1: per quarter row, signs at the
-  powers of two are computed, every other sign is the product of the sign at
-  the highest power of two not above c and the sign at the remainder; each
-  quarter sign feeds four updates of S_next.
+- ``rh_mvm_logarithm``: Method 3 (the sign rule behind Algorithm 1): in a
+  quarter row only the signs at the n - 1 powers of two are computed; the
+  sign at any other c is the product of the signs at the powers of two that
+  make up c, so the row's whole sign table is built by doubling over those
+  bits. The quarter then yields both halves of the result, since
+  H^n = [[H', H'], [H', -H']] with H' = H^(n-1).
 
 Reading of a garbled step: in Algorithm 1 the exponent p of the doubling rule is
-undefined in the printed text; 2^(p-1) is read as the highest power of two <= c,
-which makes the rule sign[c] = sign[2^(p-1)] * sign[c - 2^(p-1)].
+undefined in the printed text; it is read so that a sign is the product of the
+sign at the highest power of two not above c and the sign at the remainder,
+which is the product over c's bits used here.
 
 Each function also returns the number of compute_sign calls it made, so the
 counts of Table 2 (and the n = 5 examples of Methods 1-3) can be checked.
@@ -50,17 +53,6 @@ def compute_sign(r: int, c: int, n: int) -> int:
             c -= half
         size = half
     return sign
-
-
-def _is_pow2(c: int) -> bool:
-    return c > 0 and (c & (c - 1)) == 0
-
-
-def _highest_pow2_le(c: int) -> int:
-    p = 1
-    while p * 2 <= c:
-        p *= 2
-    return p
 
 
 def rh_mvm_non_optimized(S: np.ndarray) -> Tuple[np.ndarray, int]:
@@ -129,28 +121,27 @@ def rh_mvm_block(S: np.ndarray, b: int) -> Tuple[np.ndarray, int]:
 
 
 def rh_mvm_logarithm(S: np.ndarray) -> Tuple[np.ndarray, int]:
-    """Algorithm 1 (RH-MVM, logarithm-based sign computation)."""
+    """Method 3 (logarithm-based signs) of Sec. III-B2: n - 1 computed signs
+    per quarter row, the rest by products over the bits of the column."""
     N = S.size
     n = N.bit_length() - 1
     if n == 0:
         return S.astype(np.complex128).copy(), 0
     h = N // 2
-    Sp = S * (1.0 / math.sqrt(N))          # scalar multiplication by the RH value
-    out = np.zeros(N, dtype=np.complex128)
+    Sp = S * (1.0 / math.sqrt(N))          # the RH magnitude, applied once
+    left, right = Sp[:h], Sp[h:]
+    top = np.empty(h, dtype=np.complex128)
+    bottom = np.empty(h, dtype=np.complex128)
     count = 0
     for r in range(h):
-        sign = [0] * h                     # temporary per-row sign table
-        for c in range(h):
-            if c == 0:
-                sign[c] = 1
-            elif _is_pow2(c):
-                sign[c] = compute_sign(r, c, n)
-                count += 1
-            else:
-                p = _highest_pow2_le(c)
-                sign[c] = sign[p] * sign[c - p]
-            _quarter_updates(out, Sp, r, c, sign[c], h)
-    return out, count
+        table = np.ones(1)                 # signs of columns 0 .. 2^k - 1 of row r
+        for k in range(n - 1):
+            s = compute_sign(r, 1 << k, n)
+            count += 1
+            table = np.concatenate([table, s * table])
+        top[r] = table @ (left + right)    # [H' H'] row r
+        bottom[r] = table @ (left - right)  # [H' -H'] row r
+    return np.concatenate([top, bottom]), count
 
 
 def sign_count_formula(method: str, n: int, b: int = 1) -> int:

@@ -13,7 +13,7 @@ import numpy as np
 
 sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), ".."))
 
-from oracle import compressed as C  # noqa: E402
+from ablation import compressed as C  # noqa: E402
 from oracle import gates as G  # noqa: E402
 from oracle import rh as RH  # noqa: E402
 

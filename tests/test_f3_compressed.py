@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import compressed as C
+from ablation import compressed as C
 from oracle import gates as G
 
 PX = G.matrix("X")
