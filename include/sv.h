@@ -166,7 +166,8 @@ sv_status sv_norm(sv_state s, double *out);
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc). The same FP64 fixed-order reduction.
  * state: device pointer to `batch` consecutive states of 2^n_qubits amplitudes
- *        of `dtype` (the layout of sv_alloc), on the current device, read only.
+ *        of `dtype` (the layout of sv_alloc), 16-byte aligned, on the current
+ *        device, read only.
  * qubit: 0..n_qubits-1 for <Z_qubit>, -1 for the norm.
  * out:   device pointer to `batch` doubles, written on hip_stream (a
  *        hipStream_t, or NULL for the default stream); asynchronous, nothing

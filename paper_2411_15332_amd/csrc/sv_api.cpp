@@ -470,8 +470,8 @@ sv_status sv_expect_z_noalloc(const void *state, int n_qubits, sv_dtype dtype, i
         if (batch < 1 || batch > 65535) return fail(SV_EINVAL, "batch %d outside 1..65535", batch);
         if (qubit < -1 || qubit >= n_qubits)
             return fail(SV_EINVAL, "qubit %d out of range for n = %d", qubit, n_qubits);
-        const size_t amp_bytes = dtype == SV_C128 ? 16 : 8;
-        if (reinterpret_cast<uintptr_t>(state) % amp_bytes != 0 || reinterpret_cast<uintptr_t>(out) % 8 != 0)
+        // 16-byte loads in both precisions (two complex64 amplitudes at a time)
+        if (reinterpret_cast<uintptr_t>(state) % 16 != 0 || reinterpret_cast<uintptr_t>(out) % 8 != 0)
             return fail(SV_EINVAL, "state or out is misaligned");
         const size_t need = reduce_partials_size(n_qubits) * (size_t)batch;
         if (need > kStaticPartials)

@@ -485,11 +485,18 @@ __device__ __forceinline__ int src_bit(uint8_t src, int tid, uint64_t base) {
 // pass's qubit list as aligned 32-bit words (scalar loads, not byte loads).
 __device__ __forceinline__ uint64_t tile_base(const uint32_t (&qv)[7], int k, uint64_t tile) {
     uint64_t base = tile;
+    // compile-time indices only: a run-time index into qv would put the
+    // array in scratch memory
 #pragma unroll
-    for (int l = 0; l < 28; ++l) {
-        if (l >= k) break;
-        const int b = (qv[l >> 2] >> (8 * (l & 3))) & 0xFF;
-        base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
+    for (int w = 0; w < 7; ++w) {
+        const uint32_t word = qv[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (4 * w + j < k) {
+                const int b = (word >> (8 * j)) & 0xFF;
+                base = ((base >> b) << (b + 1)) | (base & ((1ull << b) - 1));
+            }
+        }
     }
     return base;
 }
@@ -522,15 +529,24 @@ __device__ __forceinline__ void load_tile(cpx<T> (&a)[1 << R], const cpx<T> *st,
     uint64_t idx = (base | thr_goff<W>(L, tid)) ^ L.reg_goff_xor;
     if (sizeof(T) == 4 && (L.flags & LAYOUT_PAIR_IO)) {
         // slots 2m and 2m + 1 are adjacent in memory (register bit 0 is
-        // label 0): one 16-byte access; walk the other register bits
+        // label 0): one 16-byte access; walk the other register bits.
+        // Slots are written in the order of the single-slot walk below
+        // (gray(2i) = 2 gray(i) + (i & 1)): stores in a different order
+        // get merged across the two branches with a run-time slot address,
+        // which puts the tile in scratch memory.
 #pragma unroll
         for (int i = 0; i < NR / 2; ++i) {
             if (i) idx ^= L.reg_goff[__builtin_ctz(i) + 1];
             const int j = (i ^ (i >> 1)) << 1;
             cpx<float> a0, a1;
             ld_stream2(reinterpret_cast<const cpx<float> *>(st + idx), a0, a1);
-            a[j] = mk<T>((T)a0.x, (T)a0.y);
-            a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
+            if (i & 1) {
+                a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
+                a[j] = mk<T>((T)a0.x, (T)a0.y);
+            } else {
+                a[j] = mk<T>((T)a0.x, (T)a0.y);
+                a[j + 1] = mk<T>((T)a1.x, (T)a1.y);
+            }
         }
     } else {
 #pragma unroll
@@ -1199,7 +1215,7 @@ __global__ __launch_bounds__(256) void k_fill_basis(cpx<T> *__restrict__ state, 
                                                     uint64_t total, uint64_t j) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-        const uint64_t r = i % n_amps;
+        const uint64_t r = i & (n_amps - 1);   // n_amps is a power of two
         state[i] = mk<T>(r == j ? (T)1 : (T)0, (T)0);
     }
 }
@@ -1221,6 +1237,41 @@ __device__ __forceinline__ double block_tree_sum(double v, double *sh) {
     return sh[0];
 }
 
+// One block's share of a readout: sum of |a_i|^2 (1 - 2 bit q of i, or 1 for
+// q < 0) over [lo, lo + chunk), each thread striding in a fixed order, then
+// the fixed tree. Every load is 16 bytes: one complex128 amplitude, or two
+// adjacent complex64 ones (chunks are even; the state is 16-byte aligned).
+template <typename T>
+__device__ __forceinline__ double block_readout(const cpx<T> *__restrict__ st, uint64_t lo, uint64_t chunk,
+                                                int qubit, double *sh) {
+    double acc = 0.0;
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll 4
+        for (uint64_t i = lo + threadIdx.x; i < lo + chunk; i += kRedThreads) {
+            const cpx<T> v = ld_stream(st + i);
+            const double p = v.x * v.x + v.y * v.y;
+            acc += (qubit >= 0 && ((i >> qubit) & 1)) ? -p : p;
+        }
+    } else {
+        const uint64_t hi = lo + chunk;
+#pragma unroll 4
+        for (uint64_t i = lo + 2 * threadIdx.x; i < hi; i += 2 * kRedThreads) {
+            cpx<float> v0, v1;
+            if (i + 1 < hi) {
+                ld_stream2(st + i, v0, v1);
+            } else {   // a one-amplitude chunk (n = 0 is not a state; kept for safety)
+                v0 = st[i];
+                v1 = mk<float>(0.f, 0.f);
+            }
+            const double p0 = (double)v0.x * (double)v0.x + (double)v0.y * (double)v0.y;
+            const double p1 = (double)v1.x * (double)v1.x + (double)v1.y * (double)v1.y;
+            acc += (qubit >= 0 && ((i >> qubit) & 1)) ? -p0 : p0;
+            acc += (qubit >= 0 && (((i + 1) >> qubit) & 1)) ? -p1 : p1;
+        }
+    }
+    return block_tree_sum(acc, sh);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const cpx<T> *__restrict__ state,
                                                                 uint64_t n_amps, uint64_t chunk,
@@ -1228,15 +1279,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_partial(const cpx<T> *__
                                                                 int nblk) {
     __shared__ double sh[kRedThreads];
     const cpx<T> *st = state + (uint64_t)blockIdx.y * n_amps;
-    const uint64_t lo = (uint64_t)blockIdx.x * chunk;
-    double acc = 0.0;
-    for (uint64_t i = lo + threadIdx.x; i < lo + chunk; i += kRedThreads) {
-        const cpx<T> v = st[i];
-        const double re = (double)v.x, im = (double)v.y;
-        const double p = re * re + im * im;
-        acc += (qubit >= 0 && ((i >> qubit) & 1)) ? -p : p;
-    }
-    const double s = block_tree_sum(acc, sh);
+    const double s = block_readout<T>(st, (uint64_t)blockIdx.x * chunk, chunk, qubit, sh);
     if (threadIdx.x == 0) part[(uint64_t)blockIdx.y * nblk + blockIdx.x] = s;
 }
 
@@ -1258,16 +1301,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_multi(const RedItem *__r
                                                               double *__restrict__ part) {
     __shared__ double sh[kRedThreads];
     const RedItem it = items[blockIdx.x];
-    const cpx<T> *st = static_cast<const cpx<T> *>(it.state);
-    const uint64_t lo = (uint64_t)it.blk * it.chunk;
-    double acc = 0.0;
-    for (uint64_t i = lo + threadIdx.x; i < lo + it.chunk; i += kRedThreads) {
-        const cpx<T> v = st[i];
-        const double re = (double)v.x, im = (double)v.y;
-        const double p = re * re + im * im;
-        acc += (it.qubit >= 0 && ((i >> it.qubit) & 1)) ? -p : p;
-    }
-    const double s = block_tree_sum(acc, sh);
+    const double s = block_readout<T>(static_cast<const cpx<T> *>(it.state), (uint64_t)it.blk * it.chunk, it.chunk,
+                                      it.qubit, sh);
     if (threadIdx.x == 0) part[it.part] = s;
 }
 
@@ -1441,8 +1476,9 @@ __global__ __launch_bounds__(256) void k_copy_z(const cpx<T> *__restrict__ psi, 
                                                 uint64_t total, uint64_t n_amps, int q) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        // bit q of the index within its state (states are 2^n apart, q < n)
         const cpx<T> v = psi[i];
-        lam[i] = (((i % n_amps) >> q) & 1) ? mk<T>(-v.x, -v.y) : v;
+        lam[i] = ((i >> q) & 1) ? mk<T>(-v.x, -v.y) : v;
     }
 }
 
