@@ -10,7 +10,7 @@ from .sv import (GATE_KIND, SVError, StateVector, debug_plan, gate_array,  # noq
 
 def __getattr__(name):
     # the torch-facing QNN layer imports torch lazily
-    if name in ("QNNFunction", "qnn_expect", "ansatz_gates"):
+    if name in ("QNNFunction", "qnn_expect", "ansatz_gates", "release_cache"):
         from . import qnn
         return getattr(qnn, name)
     raise AttributeError(name)

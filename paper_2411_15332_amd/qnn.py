@@ -5,19 +5,51 @@ then L layers of RY(theta) on every qubit, RZ(theta) on every qubit and the
 CNOT ring CNOT(q, (q+1) mod n). The parameter vector of one batch entry is
 [x (n), theta (2nL)] with theta index (2l + {0: RY, 1: RZ}) n + q.
 
-Forward and backward both run in the HIP kernels behind the C ABI: forward is
-sv_apply_circuit + sv_expect_z, backward is sv_adjoint_expect_z (one forward and
-one reverse sweep over psi and lambda = Z_0 psi, with Im <lambda|P|psi>
-accumulated in FP64 at every rotation).
+Both run in the HIP kernels behind the C ABI. When a gradient is needed, the
+forward call itself is sv_adjoint_expect_z (one forward and one reverse sweep
+over psi and lambda = Z_0 psi, with Im <lambda|P|psi> accumulated in FP64 at
+every rotation), which returns <Z_0> and every gradient at once; backward
+only scales the stored gradients by the incoming ones. Otherwise forward is
+sv_apply_circuit + sv_expect_z. State handles (and the adjoint's work
+buffers) are kept between calls, a few per shape.
 """
 from __future__ import annotations
 
+import threading
+from collections import OrderedDict
 from typing import List
 
 import numpy as np
 import torch
 
 from .sv import GATE_DTYPE, StateVector
+
+_CACHE_MAX = 4
+_cache: "OrderedDict[tuple, StateVector]" = OrderedDict()
+_cache_lock = threading.Lock()
+
+
+def _handle(n: int, dtype: str, batch: int, device: int) -> StateVector:
+    """A cached state handle of this shape (least recently used ones are
+    released beyond a few)."""
+    key = (n, dtype, batch, device)
+    sv = _cache.pop(key, None)
+    if sv is None:
+        sv = StateVector(n, dtype, batch=batch, device=device)
+    _cache[key] = sv
+    while len(_cache) > _CACHE_MAX:
+        _, old = _cache.popitem(last=False)
+        old.close()
+    return sv
+
+
+def release_cache() -> None:
+    """Free the cached state handles and their device memory."""
+    with _cache_lock:
+        while _cache:
+            _, sv = _cache.popitem()
+            sv.close()
+
 
 _RY, _RZ, _CNOT = 10, 11, 13
 
@@ -50,23 +82,24 @@ class QNNFunction(torch.autograd.Function):
         B = theta.shape[0]
         gates = ansatz_gates(n, layers)
         p = _params(theta, x)
-        with StateVector(n, dtype, batch=B) as sv:
-            sv.apply(gates, p)
-            z = sv.expect_z(0)
-        ctx.save_for_backward(theta, x)
-        ctx.n, ctx.layers, ctx.dtype = n, layers, dtype
+        device = torch.cuda.current_device()
+        need_grad = ctx.needs_input_grad[0] or ctx.needs_input_grad[1]
+        with _cache_lock:
+            sv = _handle(n, dtype, B, device)
+            if need_grad:
+                z, g = sv.adjoint_expect_z(gates, p, qubit=0)   # <Z_0> and every gradient
+            else:
+                sv.set_basis(0)
+                sv.apply(gates, p)
+                z, g = sv.expect_z(0), None
+        ctx.n = n
+        ctx.grad = None if g is None else torch.as_tensor(g, dtype=theta.dtype, device=theta.device)
         return torch.as_tensor(z, dtype=theta.dtype, device=theta.device)
 
     @staticmethod
     def backward(ctx, grad_out):
-        theta, x = ctx.saved_tensors
-        n, layers, dtype = ctx.n, ctx.layers, ctx.dtype
-        B = theta.shape[0]
-        gates = ansatz_gates(n, layers)
-        p = _params(theta, x)
-        with StateVector(n, dtype, batch=B) as sv:
-            _, g = sv.adjoint_expect_z(gates, p, qubit=0)
-        g = torch.as_tensor(g, dtype=theta.dtype, device=theta.device) * grad_out[:, None]
+        n = ctx.n
+        g = ctx.grad * grad_out[:, None]
         return g[:, n:], g[:, :n], None, None, None
 
 

@@ -159,6 +159,22 @@ def test_qnn_autograd_function(P):
         ps = O.grad_param_shift(n, gates, params[b], list(range(params.shape[1])))
         got = np.concatenate([x.grad[b].numpy(), theta.grad[b].numpy()])
         assert np.max(np.abs(got - w[b].item() * ps)) <= 1e-10
+    # the cached state handle serves later calls: without gradients, then
+    # with gradients again, on other parameters
+    params2 = synth.qnn_params(n, L, B, 6)
+    with torch.no_grad():
+        f2 = P.qnn_expect(torch.tensor(params2[:, n:]), torch.tensor(params2[:, :n]), n, L, "c128")
+    x2 = torch.tensor(params2[:, :n], requires_grad=True)
+    t2 = torch.tensor(params2[:, n:], requires_grad=True)
+    f3 = P.qnn_expect(t2, x2, n, L, "c128")
+    f3.sum().backward()
+    for b in range(B):
+        ref = O.loss_z(n, gates, params2[b])
+        assert abs(f2[b].item() - ref) <= 1e-12 and abs(f3[b].item() - ref) <= 1e-12
+    ps = O.grad_param_shift(n, gates, params2[1], list(range(params2.shape[1])))
+    got = np.concatenate([x2.grad[1].numpy(), t2.grad[1].numpy()])
+    assert np.max(np.abs(got - ps)) <= 1e-10
+    P.release_cache()
 
 
 C4 = dict(n=20, L=10, B=256, seed=0)
