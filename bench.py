@@ -48,14 +48,22 @@ def traffic_per_launch():
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(n, gates, target_s=20.0):
-    """The oracle (as it stands) on the first gates of the same circuit, on all
-    host threads; amplitude-gate updates/s scaled from the sample. The sample
-    size is estimated from the first gate, which runs slower than the rest,
-    so a 20 s target gives about 10-15 s of measured work."""
-    import numpy as np
-    from oracle import oracle as O
-    threads = O.max_threads()
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(O, n, gates, threads, target_s):
+    """The oracle on the first gates of the circuit with `threads` threads;
+    the sample size is estimated from the first gate (which runs slower than
+    the rest), so the measured work is somewhat under target_s."""
+    O.set_threads(threads)
     psi = O.basis_state(n)
     t0 = time.perf_counter()
     O.apply(psi, n, gates[:1])
@@ -65,17 +73,30 @@ def cpu_baseline(n, gates, target_s=20.0):
     O.apply(psi, n, gates[1:1 + count])
     dt = time.perf_counter() - t0
     del psi
-    _ = np
-    return {"value": count * (1 << n) / dt, "unit": "amplitude-gate updates/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"gates 2..{count + 1} of the n={n} depth-100 circuit from |0...0>, "
-                      f"{dt:.1f} s on {threads} threads"}
+    return count * (1 << n) / dt, (f"gates 2..{count + 1} of the n={n} depth-100 circuit from |0...0>, "
+                                   f"{dt:.1f} s on {threads} thread{'s' if threads > 1 else ''}")
 
 
-def serving_section(P, synth, seconds=4.0):
+def cpu_baseline(n, gates, target_s=16.0, single_s=8.0):
+    """The oracle (as it stands) on the first gates of the same circuit, on
+    all host threads and on one; amplitude-gate updates/s scaled from the
+    samples, with the host's CPU model."""
+    from oracle import oracle as O
+    threads = O.max_threads()
+    v_all, s_all = _oracle_sample(O, n, gates, threads, target_s)
+    v_one, s_one = _oracle_sample(O, n, gates, 1, single_s)
+    O.set_threads(threads)
+    return {"value": v_all, "unit": "amplitude-gate updates/s", "cores": threads, "kind": "oracle",
+            "sample": s_all, "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": v_one, "sample": s_one}}
+
+
+def serving_section(P, synth, seconds=1.5):
     """QNN serving: circuits/s and latency percentiles of the complex64
-    continuous-batching engine against the complex128 one-at-a-time baseline,
-    on Poisson streams at multiples of the baseline's saturated rate."""
+    stepped continuous-batching engine against the complex128 one-at-a-time
+    baseline, on Poisson streams at multiples of the baseline's saturated
+    rate. Each distinct circuit (n, L) is registered once with an engine and
+    requests are submitted by handle with their own parameters."""
     import numpy as np
     from paper_2411_15332_amd import serving as S
     cache = {}
@@ -86,15 +107,26 @@ def serving_section(P, synth, seconds=4.0):
             cache[k] = P.gate_array(synth.qnn_ansatz(r.n, r.layers))
         return cache[k]
 
+    def key_of(r):
+        return (r.n, r.layers)
+
     def saturated(eng, reqs, warm):
+        cids = {}
+
+        def submit(r):
+            k = key_of(r)
+            if k not in cids:
+                cids[k] = eng.register(r.n, gates_of(r), len(r.params), 0)
+            eng.submit_registered(r.rid, cids[k], r.params)
+
         for r in reqs[:warm]:
-            eng.submit(r.rid, r.n, gates_of(r), r.params, 0)
+            submit(r)
         got = 0
         while got < warm:
             got += len(eng.poll(wait_us=100000))
         t0 = time.perf_counter()
         for r in reqs[warm:]:
-            eng.submit(r.rid, r.n, gates_of(r), r.params, 0)
+            submit(r)
         got = 0
         while got < len(reqs) - warm:
             got += len(eng.poll(wait_us=100000))
@@ -105,14 +137,15 @@ def serving_section(P, synth, seconds=4.0):
         mu128 = saturated(eng, reqs[:220], 20)
     sweep = []
     for name, kw, mults in (("c128_one_at_a_time", dict(dtype="c128", max_batch=1, n_streams=1), (0.5, 1.0)),
-                            ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=4),
-                             (1.0, 4.0, 8.0, 10.0, 12.0, 14.0, 16.0))):
+                            ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=2, stepped=True,
+                                                 max_active=256),
+                             (1.0, 4.0, 8.0, 12.0, 14.0, 16.0, 17.0, 18.0, 19.0, 20.0, 22.0))):
         for m in mults:
             lam = m * mu128
-            count = int(min(4000, max(300, lam * seconds)))
+            count = int(min(16000, max(600, lam * seconds)))
             sub = synth.poisson_requests(count, lam, seed=1)
             with S.ServingEngine(**kw) as eng:
-                res = S.run_stream(eng, sub, gates_of, timeout_s=90)
+                res = S.run_stream(eng, sub, gates_of, timeout_s=90, key_of=key_of)
                 summ = S.summarize(res, count)
             summ.update({"engine": name, "offered_per_s": lam, "offered_x_mu128": m})
             sweep.append(summ)
