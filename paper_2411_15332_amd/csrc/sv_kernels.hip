@@ -274,11 +274,11 @@ __device__ __forceinline__ void r_d1_half(cpx<T> (&a)[NR], cpx<T> d) {
 
 // amp *= d for the slots whose register bit P equals V and whose bit pb
 // (uniform, run time) equals xb
-template <int P, int V, typename T, int NR>
-__device__ __forceinline__ void r_d1_quarter(cpx<T> (&a)[NR], cpx<T> d, uint32_t pb, uint32_t xb) {
+template <int P, int V, int PB, int VB, typename T, int NR>
+__device__ __forceinline__ void r_d1_quarter(cpx<T> (&a)[NR], cpx<T> d) {
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-        if (((j >> P) & 1) == V && (((uint32_t)j >> pb) & 1u) == xb) cmul_ip(a[j], d);
+        if (((j >> P) & 1) == V && ((j >> PB) & 1) == VB) cmul_ip(a[j], d);
 }
 
 
@@ -709,16 +709,19 @@ __device__ __forceinline__ void run_ops(cpx<T> (&a)[1 << PassTraits<T>::R], cons
                 break;
             }
             case OP_D2Q: {
-                // the quarter of the slots with bit a == xa and bit b == xb:
-                // bit a (and its value) at compile time, bit b per slot by a
-                // uniform branch
+                // the quarter of the slots with bit a == xa and bit b == xb,
+                // both bits and both values at compile time (with bit b at
+                // run time the multiply covers the half and selects)
                 const cpx<T> d = plc<T>(op, 0);
-                const uint32_t pb = op.b(), xb = (op.sa() >> 1) & 1;
-                if (op.sa() & 1) {
-                    SV_SWITCH_A(op.a(), r_d1_quarter<PA, 1>(a, d, pb, xb))
-                } else {
-                    SV_SWITCH_A(op.a(), r_d1_quarter<PA, 0>(a, d, pb, xb))
+#define SV_D2Q(XA, XB) \
+    SV_SWITCH_A(op.a(), SV_SWITCH_B(op.b(), if constexpr (PA != PB) r_d1_quarter<PA, XA, PB, XB>(a, d)))
+                switch (op.sa() & 3u) {
+                case 0: SV_D2Q(0, 0) break;
+                case 1: SV_D2Q(1, 0) break;
+                case 2: SV_D2Q(0, 1) break;
+                default: SV_D2Q(1, 1) break;
                 }
+#undef SV_D2Q
                 break;
             }
             case OP_D1HU: {
