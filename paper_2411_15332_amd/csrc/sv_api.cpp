@@ -646,7 +646,7 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
                                ngrad * sizeof(double), "hipMalloc(grad)");
         if (st != SV_OK) return st;
         // partials: reductions (batch + 1 rows) and up to kMaxIpTerms fused inner products
-        const size_t np = reduce_partials_size(s->n) * (size_t)B * kMaxIpTerms + (size_t)B;
+        const size_t np = pauli_ip_partials_size(s->n) * (size_t)B * kMaxIpTerms + (size_t)B;
         st = ensure_device_buf(reinterpret_cast<void **>(&s->d_red), &s->d_red_cap, np * sizeof(double),
                                "hipMalloc(reduce)");
         if (st != SV_OK) return st;

@@ -1581,19 +1581,33 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
 // fixed. Its slot j holds bit k < lb of j at qubit k and bit lb + k at qubit
 // hq[k], so an X or Y term on a qubit of B finds its partner inside the staged
 // sub-chunk (terms.q of an X or Y term is the qubit's bit position in B; of a
-// Z term, the qubit). psi and lambda are both staged in LDS by TH threads, and
-// the next sub-chunk's loads are in flight while the current one is summed.
-// Block blockIdx.x walks sub-chunks [x * per, (x + 1) * per) of the 2^(n - 12);
-// the partial layout matches k_pauli_ip_multi's. MT accumulators per thread.
+// Z term, the qubit; Z terms only with h = 0). The nxy <= MXY X and Y terms
+// come first in `terms`, the Z terms after them. psi and lambda are both
+// staged in LDS by TH threads, and the next sub-chunk's loads are in flight
+// while the current one is summed. Block blockIdx.x walks sub-chunks
+// [x * per, (x + 1) * per) of the 2^(n - 12), per <= 2^kIpZw; the partial
+// layout matches k_pauli_ip_multi's.
+//
+// With j = r * TH + tid, the sign of a Z term (its bit of i) is a thread bit,
+// a bit of r, or a bit of the sub-chunk's base, and in the last case a bit of
+// the block's local sub-chunk number or the same for the whole block. So the
+// Z terms need no accumulators of their own: the thread keeps the total of
+// Im(conj(l) v), its signed sums over each bit of r and over each bit of the
+// local sub-chunk number, and each Z term takes the matching one.
+// (complex128 with more than 8 X / Y terms: 512, for the registers; LDS
+// holds one complex128 block per CU either way)
 constexpr int kIpSubThreadsC128 = 1024;
 constexpr int kIpSubThreadsC64 = 1024;
-template <typename T, int MT, int TH>
+constexpr int kIpZw = 2;            // bits of the local sub-chunk number
+constexpr int kIpMaxXY = 12;        // X / Y terms of one launch (qubits < 12)
+template <typename T, int MXY, int TH>
 __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
                                                     const cpx<T> *__restrict__ lam, uint64_t n_amps,
-                                                    uint64_t per, IpTerms terms, int nt, IpHiMap map,
+                                                    uint64_t per, IpTerms terms, int nt, int nxy, IpHiMap map,
                                                     double *__restrict__ part, int nblk) {
     constexpr int NRS = kIpSub / TH;              // slots per thread: j = r * TH + tid
     constexpr int RB = __builtin_ctz(NRS);        // bits of r: bits log2(TH) .. 11 of j
+    constexpr int TB = __builtin_ctz(TH);         // thread bits of j
     static_assert((TH & (TH - 1)) == 0 && TH >= 256 && TH <= 1024, "thread count");
     __shared__ cpx<T> buf[kIpSub], lbuf[kIpSub];
     __shared__ double sh[TH / 64];
@@ -1612,9 +1626,14 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
     uint64_t gr[RB];   // offsets of the register-slot bits of j
 #pragma unroll
     for (int b = 0; b < RB; ++b) gr[b] = dep((uint32_t)TH << b);
-    double acc[MT];
+    double acc[MXY];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) acc[t] = 0.0;
+    for (int t = 0; t < MXY; ++t) acc[t] = 0.0;
+    double ztot = 0.0, zr[RB], zw[kIpZw];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) zr[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kIpZw; ++k) zw[k] = 0.0;
     // the sub-chunk's base index: its number with zeros inserted at B
     auto base_of = [&](uint64_t sc) {
         uint64_t b = sc << lb;
@@ -1649,12 +1668,28 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
         }
     }
     for (uint64_t sc = s_beg; sc < s_end; ++sc) {
-        const uint64_t base = base_of(sc);
 #pragma clang loop unroll(full)
         for (int r = 0; r < NRS; ++r) {
             bufv[r * TH + threadIdx.x] = pv[r];
             lbufv[r * TH + threadIdx.x] = lv[r];
         }
+        // the thread's own slots, from the registers before the prefetch
+        // reuses them: lambda in FP64 for the X and Y terms, and the Z sums
+        double lx[NRS], ly[NRS];
+        double z0 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NRS; ++r) {
+            lx[r] = (double)lv[r].x;
+            ly[r] = (double)lv[r].y;
+            const double b = lx[r] * (double)pv[r].y - ly[r] * (double)pv[r].x;   // Im(conj(l) v)
+            z0 += b;
+#pragma unroll
+            for (int k = 0; k < RB; ++k) zr[k] += ((r >> k) & 1) ? -b : b;
+        }
+        ztot += z0;
+        const uint32_t u = (uint32_t)(sc - s_beg);   // the local sub-chunk number
+#pragma unroll
+        for (int k = 0; k < kIpZw; ++k) zw[k] += ((u >> k) & 1u) ? -z0 : z0;
         __syncthreads();
         {   // the last sub-chunk reloads itself (cache hits) instead of a branch
             const uint64_t b1 = base_of(sc + 1 < s_end ? sc + 1 : sc);
@@ -1664,41 +1699,89 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
                 lv[r] = lmv[b1 | slot_off(r)];
             }
         }
-        // X and Y terms per amplitude. Z terms: a slot's sign is its bit of
-        // the term's qubit, which is uniform over the thread's slots unless
-        // the qubit is one of the slot bits; so the thread sums
-        // Im(conj(l) v) over its slots once, and once per slot bit with that
-        // bit's sign, and each Z term takes the matching sum.
-        double zs[1 + RB];
+        // X and Y terms: Im(conj(l_j) (P psi)_j) with the partner slot
+        // j ^ m, m = 2^q. X gives lx wy - ly wx; Y gives s (lx wx + ly wy)
+        // with s = +1 where bit q of j is set, else -1. A bit q below TB is
+        // a thread bit: the partner is slot r of thread tid ^ m and s is the
+        // same for all of the thread's slots (applied once per sub-chunk);
+        // otherwise q is a bit of r: the partner is slot r ^ (m / TH) of this
+        // thread and s is uniform over the block.
+#pragma clang loop unroll(full)
+        for (int t = 0; t < MXY; ++t) {
+            if (t >= nxy) continue;   // a uniform branch: acc stays in registers
+            const int pa = terms.pauli[t];
+            const uint32_t m = 1u << terms.q[t];
+            double s = 0.0;
+            if (m < (uint32_t)TH) {
+                const cpx<T> *pb = buf + (threadIdx.x ^ m);
+                if (pa == 1) {
 #pragma unroll
-        for (int k = 0; k <= RB; ++k) zs[k] = 0.0;
-#pragma clang loop unroll(disable)
-        for (int r = 0; r < NRS; ++r) {
-            const uint32_t j = (uint32_t)(r * TH) + threadIdx.x;
-            const cpx<T> l = lbuf[j], v = buf[j];
-            ip_terms_at<MT, T, false>(acc, base | slot_off(r), j, l, buf, terms, nt);
-            const double b = (double)l.x * (double)v.y - (double)l.y * (double)v.x;
-            zs[0] += b;
+                    for (int r = 0; r < NRS; ++r) {
+                        const cpx<T> w = pb[r * TH];
+                        s += lx[r] * (double)w.y - ly[r] * (double)w.x;
+                    }
+                    acc[t] += s;
+                } else {
 #pragma unroll
-            for (int k = 0; k < RB; ++k) zs[1 + k] += ((r >> k) & 1) ? -b : b;
-        }
-        const uint64_t ib = base | toff;   // the bits of i outside the slot bits
+                    for (int r = 0; r < NRS; ++r) {
+                        const cpx<T> w = pb[r * TH];
+                        s += lx[r] * (double)w.x + ly[r] * (double)w.y;
+                    }
+                    acc[t] += (threadIdx.x & m) ? s : -s;
+                }
+            } else {
+                const uint32_t rm = m / (uint32_t)TH;
+                const cpx<T> *pb = buf + threadIdx.x;
+                if (pa == 1) {
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-            if (t >= nt || terms.pauli[t] != 3) continue;
-            const uint64_t m = 1ull << terms.q[t];
-            double z = (ib & m) ? -zs[0] : zs[0];
+                    for (int r = 0; r < NRS; ++r) {
+                        const cpx<T> w = pb[(r ^ rm) * TH];
+                        s += lx[r] * (double)w.y - ly[r] * (double)w.x;
+                    }
+                } else {
 #pragma unroll
-            for (int k = 0; k < RB; ++k)
-                if (gr[k] == m) z = zs[1 + k];
-            acc[t] += z;
+                    for (int r = 0; r < NRS; ++r) {
+                        const cpx<T> w = pb[(r ^ rm) * TH];
+                        const double p = lx[r] * (double)w.x + ly[r] * (double)w.y;
+                        s += ((uint32_t)r & rm) ? p : -p;
+                    }
+                }
+                acc[t] += s;
+            }
+            // one term at a time: reads of later terms hoisted above this
+            // point would hold registers the accumulators need
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();   // every read of this sub-chunk is done before the next is staged
     }
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
+    // Z term on qubit q (h = 0, so bit q of i is bit q of j for q < 12 and
+    // bit q - 12 of the sub-chunk number above): the matching sum
+    const uint64_t sb = s_beg;
+#pragma clang loop unroll(full)
+    for (int t = 0; t < kMaxIpTerms; ++t) {
         if (t >= nt) continue;
-        const double sum = block_sum_t0<TH>(acc[t], sh);
+        double v;
+        if (t < MXY && t < nxy) {
+            v = acc[t < MXY ? t : 0];
+        } else {
+            const int q = terms.q[t];
+            if (q < TB) {
+                v = ((threadIdx.x >> q) & 1u) ? -ztot : ztot;
+            } else if (q < 12) {
+                v = 0.0;
+#pragma unroll
+                for (int k = 0; k < RB; ++k)
+                    if (q - TB == k) v = zr[k];
+            } else if (q - 12 < kIpZw && (1ull << (q - 12)) < per) {
+                v = 0.0;
+#pragma unroll
+                for (int k = 0; k < kIpZw; ++k)
+                    if (q - 12 == k) v = zw[k];
+            } else {
+                v = ((sb >> (q - 12)) & 1u) ? -ztot : ztot;
+            }
+        }
+        const double sum = block_sum_t0<TH>(v, sh);
         if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
     }
 }
@@ -1899,6 +1982,13 @@ int reduce_blocks(int n) {
 
 size_t reduce_partials_size(int n) { return (size_t)reduce_blocks(n); }
 
+// blocks of the sub-chunk inner products: 4 sub-chunks of 2^12 each
+size_t pauli_ip_partials_size(int n) {
+    const size_t sub = n >= 14 ? (size_t)1 << (n - 14) : 1;
+    const size_t red = reduce_partials_size(n);
+    return sub > red ? sub : red;
+}
+
 hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
                          double *d_partials, double *d_out, hipStream_t st) {
     const uint64_t N = 1ull << n;
@@ -1981,10 +2071,8 @@ hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n
                                  double *d_grad, uint64_t grad_stride, hipStream_t st) {
     if (nt <= 0) return hipSuccess;
     if (nt > kMaxIpTerms) return hipErrorInvalidValue;
-    if (n >= 12 && dt == 2) {
-        // complex128: contiguous 2^12-amplitude sub-chunks (h = 0) of the
-        // pipelined kernel, measured faster here. complex64 keeps this kernel:
-        // with 24 accumulators the pipelined one holds one block per CU.
+    if (n >= 12) {
+        // contiguous 2^12-amplitude sub-chunks (h = 0) of the pipelined kernel
         IpHiMap map{};
         return launch_pauli_ip_sub(dt, psi, lam, n, batch, terms, offs, nt, map, d_partials, d_grad, grad_stride,
                                    st);
@@ -2019,31 +2107,50 @@ static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, 
     const int lb = 12 - map.h;
     for (int k = 0; k < map.h; ++k)   // ascending, above the low bits, inside the state
         if (map.hq[k] < lb || map.hq[k] >= n || (k && map.hq[k] <= map.hq[k - 1])) return hipErrorInvalidValue;
-    for (int t = 0; t < nt; ++t)
-        if (terms.pauli[t] < 1 || terms.pauli[t] > 3 || terms.q[t] >= (terms.pauli[t] == 3 ? n : 12))
+    // the X and Y terms first (their accumulators), then the Z terms (only
+    // with contiguous sub-chunks); the order of the terms changes no sum
+    int nxy = 0;
+    for (int t = 0; t < nt; ++t) {
+        const int pa = terms.pauli[t];
+        if (pa < 1 || pa > 3 || terms.q[t] >= (pa == 3 ? n : 12) || (pa == 3 && map.h != 0))
             return hipErrorInvalidValue;
+        nxy += pa != 3;
+    }
+    if (nxy > kIpMaxXY) return hipErrorInvalidValue;
+    IpTerms tt{};
+    IpOffsets oo{};
+    int w = 0;
+    for (int z = 0; z < 2; ++z)
+        for (int t = 0; t < nt; ++t)
+            if ((terms.pauli[t] == 3) == (z == 1)) {
+                tt.q[w] = terms.q[t];
+                tt.pauli[w] = terms.pauli[t];
+                oo.off[w] = offs.off[t];
+                ++w;
+            }
     const uint64_t N = 1ull << n;
-    // a quarter of the reduction blocks, each pipelining 4+ sub-chunks
-    const int nblk = reduce_blocks(n) >= 4 ? reduce_blocks(n) / 4 : 1;
-    const uint64_t per = (N >> 12) / (uint64_t)nblk;   // sub-chunks per block (>= 1)
-    if (per == 0 || per * (uint64_t)nblk != (N >> 12)) return hipErrorInvalidValue;
+    // 2^kIpZw sub-chunks per block (fewer when the state has fewer)
+    const uint64_t per = (N >> 12) < (1ull << kIpZw) ? (N >> 12) : (1ull << kIpZw);
+    const uint64_t nblk64 = (N >> 12) / per;
+    if (nblk64 > (uint64_t)pauli_ip_partials_size(n)) return hipErrorInvalidValue;
+    const int nblk = (int)nblk64;
     const dim3 grid(nblk, batch);
-    const bool few = nt <= kMaxIpHiTerms;   // fewer accumulators, fewer registers
+    const bool few = nxy <= kMaxIpHiTerms;   // fewer accumulators, fewer registers
 #define SV_IP_SUB(TT, MTT, THH)                                                                   \
     hipLaunchKernelGGL((k_pauli_ip_sub<TT, MTT, THH>), grid, dim3(THH), 0, st, (const cpx<TT> *)psi, \
-                       (const cpx<TT> *)lam, N, per, terms, nt, map, d_partials, nblk)
+                       (const cpx<TT> *)lam, N, per, tt, nt, nxy, map, d_partials, nblk)
     if (dt == 2) {
         if (few) SV_IP_SUB(double, kMaxIpHiTerms, kIpSubThreadsC128);
-        else SV_IP_SUB(double, kMaxIpTerms, kIpSubThreadsC128);
+        else SV_IP_SUB(double, kIpMaxXY, kIpSubThreadsC128 / 2);   // 12 FP64 accumulators: 512 threads
     } else {
         if (few) SV_IP_SUB(float, kMaxIpHiTerms, kIpSubThreadsC64);
-        else SV_IP_SUB(float, kMaxIpTerms, kIpSubThreadsC64);
+        else SV_IP_SUB(float, kIpMaxXY, kIpSubThreadsC64);
     }
 #undef SV_IP_SUB
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_accumulate_multi, dim3(batch), dim3(kRedThreads), 0, st, (const double *)d_partials,
-                       nblk, nt, d_grad, grad_stride, offs);
+                       nblk, nt, d_grad, grad_stride, oo);
     return hipGetLastError();
 }
 

@@ -67,6 +67,8 @@ hipError_t launch_reduce_multi(int dt, const RedItem *d_items, uint32_t n_items,
 // Per-state sum of |a_i|^2 * (qubit < 0 ? 1 : 1 - 2 b_qubit(i)) in FP64.
 // d_partials needs reduce_partials_size(n) * batch doubles; d_out batch doubles.
 size_t reduce_partials_size(int n);
+// partial sums per (batch entry, term) of the adjoint inner products
+size_t pauli_ip_partials_size(int n);
 hipError_t launch_reduce(int dt, const void *state, int n, int batch, int qubit,
                          double *d_partials, double *d_out, hipStream_t st);
 
@@ -98,7 +100,7 @@ struct IpOffsets {
 // grad[b * grad_stride + off[t]] += Im <lambda_b | P_t | psi_b> for nt <= kMaxIpTerms
 // terms in one read of the states. Z terms take any qubit; X and Y terms need
 // qubit < pauli_ip_multi_chunk_bits(n) (hipErrorInvalidValue otherwise).
-// d_partials holds batch * nt * reduce_partials_size(n) doubles.
+// d_partials holds batch * nt * pauli_ip_partials_size(n) doubles.
 hipError_t launch_pauli_ip_multi(int dt, const void *psi, const void *lam, int n, int batch,
                                  const IpTerms &terms, const IpOffsets &offs, int nt, double *d_partials,
                                  double *d_grad, uint64_t grad_stride, hipStream_t st);
