@@ -15,6 +15,7 @@
 // k_gather — amplitude readout.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <mutex>
 
@@ -1598,7 +1599,7 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
 // holds one complex128 block per CU either way)
 constexpr int kIpSubThreadsC128 = 1024;
 constexpr int kIpSubThreadsC64 = 1024;
-constexpr int kIpZw = 2;            // bits of the local sub-chunk number
+constexpr int kIpZw = 4;            // bits of the local sub-chunk number
 constexpr int kIpMaxXY = 12;        // X / Y terms of one launch (qubits < 12)
 template <typename T, int MXY, int TH>
 __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
@@ -1610,7 +1611,7 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
     constexpr int TB = __builtin_ctz(TH);         // thread bits of j
     static_assert((TH & (TH - 1)) == 0 && TH >= 256 && TH <= 1024, "thread count");
     __shared__ cpx<T> buf[kIpSub], lbuf[kIpSub];
-    __shared__ double sh[TH / 64];
+    __shared__ double sh[kMaxIpTerms * (TH / 64)];
     const cpx<T> *ps = psi + (uint64_t)blockIdx.y * n_amps;
     const cpx<T> *lm = lam + (uint64_t)blockIdx.y * n_amps;
     const int h = map.h, lb = 12 - h;
@@ -1755,7 +1756,10 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
         __syncthreads();   // every read of this sub-chunk is done before the next is staged
     }
     // Z term on qubit q (h = 0, so bit q of i is bit q of j for q < 12 and
-    // bit q - 12 of the sub-chunk number above): the matching sum
+    // bit q - 12 of the sub-chunk number above): the matching sum. Every
+    // term's block sum at once: a butterfly per wave, one barrier, then
+    // thread t adds term t's wave sums in order (the arithmetic of
+    // block_sum_t0, term by term).
     const uint64_t sb = s_beg;
 #pragma clang loop unroll(full)
     for (int t = 0; t < kMaxIpTerms; ++t) {
@@ -1781,8 +1785,15 @@ __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ 
                 v = ((sb >> (q - 12)) & 1u) ? -ztot : ztot;
             }
         }
-        const double sum = block_sum_t0<TH>(v, sh);
-        if (threadIdx.x == 0) part[((uint64_t)blockIdx.y * nt + t) * nblk + blockIdx.x] = sum;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0) sh[t * (TH / 64) + (threadIdx.x >> 6)] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nt) {
+        double s = 0.0;
+        for (int w = 0; w < TH / 64; ++w) s += sh[threadIdx.x * (TH / 64) + w];
+        part[((uint64_t)blockIdx.y * nt + threadIdx.x) * nblk + blockIdx.x] = s;
     }
 }
 
@@ -1982,9 +1993,9 @@ int reduce_blocks(int n) {
 
 size_t reduce_partials_size(int n) { return (size_t)reduce_blocks(n); }
 
-// blocks of the sub-chunk inner products: 4 sub-chunks of 2^12 each
+// blocks of the sub-chunk inner products: 16 sub-chunks of 2^12 each
 size_t pauli_ip_partials_size(int n) {
-    const size_t sub = n >= 14 ? (size_t)1 << (n - 14) : 1;
+    const size_t sub = n >= 16 ? (size_t)1 << (n - 16) : 1;
     const size_t red = reduce_partials_size(n);
     return sub > red ? sub : red;
 }
@@ -2129,9 +2140,12 @@ static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, 
                 ++w;
             }
     const uint64_t N = 1ull << n;
-    // 2^kIpZw sub-chunks per block (fewer when the state has fewer)
-    const uint64_t per = (N >> 12) < (1ull << kIpZw) ? (N >> 12) : (1ull << kIpZw);
-    const uint64_t nblk64 = (N >> 12) / per;
+    // up to 2^kIpZw sub-chunks per block, but at least 32 blocks per state
+    // where it has that many sub-chunks (a function of n alone, so that a
+    // term's summation order does not depend on the batch)
+    const uint64_t nsc = N >> 12;
+    const uint64_t nblk64 = std::max(nsc >> kIpZw, std::min<uint64_t>(nsc, 32));
+    const uint64_t per = nsc / nblk64;
     if (nblk64 > (uint64_t)pauli_ip_partials_size(n)) return hipErrorInvalidValue;
     const int nblk = (int)nblk64;
     const dim3 grid(nblk, batch);

@@ -92,12 +92,15 @@ def test_adjoint_high_qubit_terms(P, dtype):
         assert np.max(np.abs(g[b, which] - ps)) <= TOL_PS[dtype]
 
 
-def test_adjoint_z_terms_on_every_bit_class(P):
-    """complex128 Z generators (RZ) on thread bits (q < 10), on register-slot
-    bits of the sub-chunk kernel (q = 10, 11) and on chunk-base bits
-    (q >= 12), in the same runs as X / Y generators; every RZ gradient against
-    parameter shift."""
-    n = 16
+@pytest.mark.parametrize("n,dt", [(16, "c128"), (20, "c128"), (20, "c64")])
+def test_adjoint_z_terms_on_every_bit_class(P, n, dt):
+    """Z generators (RZ) on thread bits (q < 10), on register-slot bits of
+    the sub-chunk kernel (q = 10, 11) and on sub-chunk base bits (q >= 12):
+    at n = 20 a block walks 8 sub-chunks, so q = 12..14 take the signed sums
+    over the block's sub-chunks and q >= 15 a sign uniform over the block;
+    X / Y generators on every low qubit in the runs before them (thread and
+    slot bits of the 12-term kernel). Every sampled RZ gradient, and the X / Y
+    ones on slot bits, against parameter shift."""
     gates, k = [], 0
     for layer in range(3):
         for q in range(n):
@@ -110,14 +113,17 @@ def test_adjoint_z_terms_on_every_bit_class(P):
             gates.append(synth.Gate("CNOT", q, q + 1))
     params = np.random.default_rng(31).uniform(-3, 3, size=(2, k))
     rz = [g for g in gates if g.name == "RZ"]
-    which = [g.param for g in rz if g.q0 in (3, 10, 11, 12, 13, 15)]
+    zq = (3, 10, 11, 12, 13, 15) if n == 16 else (3, 10, 11, 12, 14, 15, 19)
+    which = [g.param for g in rz if g.q0 in zq]
+    which += [g.param for g in gates if g.name in ("RX", "RY") and g.q0 in (9, 10, 11)][:4]
     assert {g.q0 for g in rz if g.param in which} >= {10, 12, 15}
-    with P.StateVector(n, "c128", batch=2) as sv:
+    tol = (1e-12, 1e-10) if dt == "c128" else (1e-5, 1e-4)
+    with P.StateVector(n, dt, batch=2) as sv:
         f, g = sv.adjoint_expect_z(gates, params, qubit=2)
     for b in range(2):
-        assert abs(f[b] - O.loss_z(n, gates, params[b], qubit=2)) <= 1e-12
+        assert abs(f[b] - O.loss_z(n, gates, params[b], qubit=2)) <= tol[0]
         ps = O.grad_param_shift(n, gates, params[b], which, qubit=2)
-        assert np.max(np.abs(g[b, which] - ps)) <= 1e-10
+        assert np.max(np.abs(g[b, which] - ps)) <= tol[1]
 
 
 def test_adjoint_more_than_eight_high_qubits(P):
