@@ -149,6 +149,8 @@ def serving_section(P, synth, seconds=1.5):
                 summ = S.summarize(res, count)
             summ.update({"engine": name, "offered_per_s": lam, "offered_x_mu128": m})
             sweep.append(summ)
+            print(f"serving {name} {m:g}x: {summ['circuits_per_s']:.0f} circuits/s, p99 {summ['p99_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
     best = {}
     for name in ("c128_one_at_a_time", "c64_batched"):
         ok = [r for r in sweep if r["engine"] == name and r["p99_ms"] <= 100.0]
@@ -342,7 +344,7 @@ def main():
         },
         "pct_hbm_peak": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {
-            "bound": "hbm", "kernel": "k_pass<double, false, false>", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "bound": "hbm", "kernel": "k_pass<double, false, false, *>", "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": tr, "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms, "launches": k_launches,
