@@ -219,8 +219,9 @@ void *sv_device_ptr(sv_state s);
  *                         0: one pass per gate (parity of fused vs unfused).
  *   SV_OPT_MIN_LOW_QUBITS lowest qubits always inside a tile (contiguous HBM
  *                         runs of 2^value amplitudes), 3..7; 0 (default):
- *                         chosen per circuit between 6 and 4 by the planner's
- *                         cost estimate (fewer passes against shorter runs).
+ *                         chosen per circuit among 6, 4 and (complex128, still
+ *                         128-byte runs) 3 by the planner's cost estimate
+ *                         (fewer passes against shorter runs).
  *   SV_OPT_MAX_DENSE      dense gates allowed per pass (ALU budget), >= 1.
  *   SV_OPT_ON_DEMAND_H    1 (default): generate leading Hadamard layers of a
  *                         basis state on demand; 0: apply them as gates.

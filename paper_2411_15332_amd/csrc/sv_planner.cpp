@@ -1203,6 +1203,14 @@ Plan build_plan_auto(int n, const sv_gate *gates, size_t n_gates, const PlanOpti
     o4.c = 4;
     Plan alt = build_plan(n, gates, n_gates, o4);
     if (cost(alt) < cost(best)) best = std::move(alt);
+    if (opt.v == 0) {
+        // 16-byte amplitudes: 3 low qubits still give 128-byte runs, and the
+        // extra free tile slot packs more gates into each pass
+        PlanOptions o3 = opt;
+        o3.c = 3;
+        Plan alt3 = build_plan(n, gates, n_gates, o3);
+        if (cost(alt3) < cost(best)) best = std::move(alt3);
+    }
     return best;
 }
 

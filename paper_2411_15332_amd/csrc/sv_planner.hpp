@@ -110,7 +110,7 @@ struct PlanOptions {
     int v = 0;            // vector bits (complex64: 1, label 0 in register 0 for 16-byte I/O)
     int m = 3;            // swizzle width (3 for 16-byte slots, 4 for 8-byte)
     int c = 6;            // lowest qubits always in the tile
-    bool auto_low = false;  // build_plan_auto: choose c among 6 and 4
+    bool auto_low = false;  // build_plan_auto: choose c among 6, 4 and (complex128) 3
     int w_max = 8;        // thread bits of a full workgroup
     bool fuse = true;     // false: one pass per gate
     bool remap = true;    // permute the tile's address bits at each store (see build_plan)
