@@ -332,7 +332,9 @@ sv_status sv_engine_register(sv_engine e, int n_qubits, const sv_gate *gates, si
                              int qubit, int64_t *circuit);
 
 /* Queue one evaluation of a registered circuit with its own parameters
- * (exactly the registered n_params reals, copied). */
+ * (exactly the registered n_params reals, copied). SV_EINVAL for a handle
+ * this engine did not return, another parameter count, or NULL params with
+ * n_params > 0; nothing is queued then. */
 sv_status sv_engine_submit_registered(sv_engine e, uint64_t id, int64_t circuit, const double *params,
                                       size_t n_params);
 
