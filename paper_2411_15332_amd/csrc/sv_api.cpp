@@ -723,11 +723,75 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
         // commutes with the run's later rotations, so <lambda_k| P_k |psi_k>
         // equals <lambda| P_k |psi> taken after the run's last gate, and the
         // whole run is then undone in one segment.
+        // A diagonal unitary D applied to both states leaves every Z term
+        // unchanged (<D lambda| Z_q |D psi> = <lambda| Z_q |psi>: D commutes
+        // with Z_q and D^dagger D = I). So Z terms wait while only diagonal
+        // gates are undone, and join the next run's read of the states; any
+        // other gate to undo first sends them out at the point they belong to.
+        auto diagonal = [](const sv_gate &g) {
+            switch (g.kind) {
+            case SV_GATE_I: case SV_GATE_Z: case SV_GATE_S: case SV_GATE_SDG: case SV_GATE_T:
+            case SV_GATE_TDG: case SV_GATE_RZ: case SV_GATE_P: case SV_GATE_CZ: case SV_GATE_CPHASE:
+            case SV_GATE_MARK: case SV_GATE_CRZ: case SV_GATE_RZZ: case SV_GATE_CU1:
+                return true;
+            default:
+                return false;
+            }
+        };
+        struct ZTerm {
+            uint8_t q;
+            uint64_t off;
+        };
+        std::vector<ZTerm> pend_z;   // Z terms still valid at the current point
+        bool seg_diag = true;        // every gate queued in seg is diagonal
+        // Launch the contiguous-chunk inner products of `zs` (Z terms) and
+        // `xy` (X / Y terms on qubits below chunk_bits, at most kIpMaxXYTerms
+        // of them) at the current point, kMaxIpTerms at a time.
+        auto launch_low = [&](const std::vector<ZTerm> &zs, const std::vector<std::pair<sv_gate, int>> &xy)
+            -> sv_status {
+            IpTerms terms{};
+            IpOffsets offs{};
+            int nt = 0, nxy = 0;
+            auto go = [&]() -> sv_status {
+                if (nt) {
+                    SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad,
+                                                 n_params, s->stream),
+                           "launch pauli_ip_multi");
+                }
+                terms = IpTerms{};
+                offs = IpOffsets{};
+                nt = nxy = 0;
+                return SV_OK;
+            };
+            for (const auto &t : xy) {
+                if (nt == kMaxIpTerms || nxy == kIpMaxXYTerms) {
+                    sv_status r = go();
+                    if (r != SV_OK) return r;
+                }
+                terms.q[nt] = (uint8_t)t.first.q0;
+                terms.pauli[nt] = (uint8_t)t.second;
+                offs.off[nt] = (uint64_t)t.first.param;
+                ++nt;
+                ++nxy;
+            }
+            for (const ZTerm &z : zs) {
+                if (nt == kMaxIpTerms) {
+                    sv_status r = go();
+                    if (r != SV_OK) return r;
+                }
+                terms.q[nt] = z.q;
+                terms.pauli[nt] = 3;
+                offs.off[nt] = z.off;
+                ++nt;
+            }
+            return go();
+        };
         size_t i = n_gates;
         while (i > 0) {
             const sv_gate &g = gates[i - 1];
             if (g.param < 0) {
                 seg.push_back(inverse(g));
+                seg_diag = seg_diag && diagonal(g);
                 --i;
                 continue;
             }
@@ -737,36 +801,38 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
                 used |= 1ull << gates[j - 1].q0;
                 --j;
             }
+            // Z terms waiting from later runs are still valid here if every
+            // gate queued for undoing is diagonal; otherwise they go out now,
+            // at the point they were taken, before that undo
+            if (!pend_z.empty() && !seg_diag) {
+                st = launch_low(pend_z, {});
+                if (st != SV_OK) return st;
+                pend_z.clear();
+            }
             st = flush();
             if (st != SV_OK) return st;
             // one read of psi and lambda for every Z term and every X / Y term
             // whose partner amplitude lies in the same 2^12-amplitude chunk;
             // one more read per group of up to 8 X / Y terms on higher qubits
             // (the run's qubits are distinct, so a group is up to 8 qubits)
-            IpTerms terms{};
-            IpOffsets offs{};
-            int nt = 0;
+            bool run_diag = true;   // this run's own undo is diagonal (RZ only)
+            for (size_t k = j; k < i; ++k) run_diag = run_diag && gates[k].kind == SV_GATE_RZ;
+            std::vector<ZTerm> zs;
+            zs.swap(pend_z);
+            std::vector<std::pair<sv_gate, int>> xy;
             std::vector<size_t> high;   // gate indices of X / Y terms on qubits >= chunk_bits
             for (size_t k = i; k-- > j;) {
                 const sv_gate &gk = gates[k];
                 const int pauli = gk.kind == SV_GATE_RX ? 1 : gk.kind == SV_GATE_RY ? 2 : 3;
-                if (pauli == 3 || gk.q0 < chunk_bits) {
-                    terms.q[nt] = (uint8_t)gk.q0;
-                    terms.pauli[nt] = (uint8_t)pauli;
-                    offs.off[nt] = (uint64_t)gk.param;
-                    if (++nt == kMaxIpTerms) {
-                        SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad,
-                                                     n_params, s->stream),
-                               "launch pauli_ip_multi");
-                        nt = 0;
-                    }
-                } else {
+                if (pauli == 3)
+                    (run_diag ? pend_z : zs).push_back(ZTerm{(uint8_t)gk.q0, (uint64_t)gk.param});
+                else if (gk.q0 < chunk_bits)
+                    xy.emplace_back(gk, pauli);
+                else
                     high.push_back(k);
-                }
             }
-            SV_HIP(launch_pauli_ip_multi(dt, psi, lam, s->n, B, terms, offs, nt, s->d_red, s->d_grad, n_params,
-                                         s->stream),
-                   "launch pauli_ip_multi");
+            st = launch_low(zs, xy);
+            if (st != SV_OK) return st;
             for (size_t g0 = 0; g0 < high.size(); g0 += 8) {
                 const size_t g1 = std::min(high.size(), g0 + 8);
                 std::vector<int> qs;
@@ -791,10 +857,14 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
                        "launch pauli_ip_hi");
             }
             for (size_t k = i; k-- > j;) seg.push_back(inverse(gates[k]));
+            seg_diag = run_diag;
             i = j;
         }
-        st = flush();
+        // Z terms still waiting are valid at the current point (the queued
+        // undo has not been applied); that undo itself is never read
+        st = launch_low(pend_z, {});
         if (st != SV_OK) return st;
+        seg.clear();
         if (n_params) {
             std::vector<double> tmp((size_t)B * n_params);
             SV_HIP(hipMemcpyAsync(tmp.data(), s->d_grad, tmp.size() * sizeof(double), hipMemcpyDeviceToHost,

@@ -1600,7 +1600,6 @@ __global__ __launch_bounds__(kRedThreads) void k_pauli_ip_multi(const cpx<T> *__
 constexpr int kIpSubThreadsC128 = 1024;
 constexpr int kIpSubThreadsC64 = 1024;
 constexpr int kIpZw = 4;            // bits of the local sub-chunk number
-constexpr int kIpMaxXY = 12;        // X / Y terms of one launch (qubits < 12)
 template <typename T, int MXY, int TH>
 __global__ __launch_bounds__(TH) void k_pauli_ip_sub(const cpx<T> *__restrict__ psi,
                                                     const cpx<T> *__restrict__ lam, uint64_t n_amps,
@@ -2127,7 +2126,7 @@ static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, 
             return hipErrorInvalidValue;
         nxy += pa != 3;
     }
-    if (nxy > kIpMaxXY) return hipErrorInvalidValue;
+    if (nxy > kIpMaxXYTerms) return hipErrorInvalidValue;
     IpTerms tt{};
     IpOffsets oo{};
     int w = 0;
@@ -2155,10 +2154,10 @@ static hipError_t launch_pauli_ip_sub(int dt, const void *psi, const void *lam, 
                        (const cpx<TT> *)lam, N, per, tt, nt, nxy, map, d_partials, nblk)
     if (dt == 2) {
         if (few) SV_IP_SUB(double, kMaxIpHiTerms, kIpSubThreadsC128);
-        else SV_IP_SUB(double, kIpMaxXY, kIpSubThreadsC128 / 2);   // 12 FP64 accumulators: 512 threads
+        else SV_IP_SUB(double, kIpMaxXYTerms, kIpSubThreadsC128 / 2);   // 12 FP64 accumulators: 512 threads
     } else {
         if (few) SV_IP_SUB(float, kMaxIpHiTerms, kIpSubThreadsC64);
-        else SV_IP_SUB(float, kIpMaxXY, kIpSubThreadsC64);
+        else SV_IP_SUB(float, kIpMaxXYTerms, kIpSubThreadsC64);
     }
 #undef SV_IP_SUB
     hipError_t e = hipGetLastError();

@@ -89,7 +89,8 @@ hipError_t launch_copy_z(int dt, const void *psi, void *lam, uint64_t n_amps, in
 // Adjoint inner products Im <lambda_b | P | psi_b>, P = X (1), Y (2) or Z (3)
 // on one qubit, accumulated in FP64 in a fixed order. Several (qubit, Pauli)
 // terms of one adjoint run go by value in one launch.
-constexpr int kMaxIpTerms = 24;
+constexpr int kMaxIpTerms = 32;
+constexpr int kIpMaxXYTerms = 12;   // X / Y terms of one contiguous-chunk launch (qubits < 12)
 struct IpTerms {
     uint8_t q[kMaxIpTerms];
     uint8_t pauli[kMaxIpTerms];   // 1 = X, 2 = Y, 3 = Z

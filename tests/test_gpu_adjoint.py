@@ -126,6 +126,35 @@ def test_adjoint_z_terms_on_every_bit_class(P, n, dt):
         assert np.max(np.abs(g[b, which] - ps)) <= tol[1]
 
 
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_adjoint_z_terms_across_diagonal_gates(P, dt):
+    """Z-generator gradients taken after undoing only diagonal gates (an RZ
+    run's own undo, fixed CZ / S / T) join an earlier run's read of the
+    states; a non-diagonal gate to undo first (H, CNOT) sends them out at the
+    point they belong to. Every gradient against parameter shift."""
+    n = 14
+    gates, k = [], 0
+    for q in range(n):
+        gates.append(synth.Gate("RY", q, -1, 0.0, k)); k += 1
+    gates.append(synth.Gate("H", 3))
+    for q in range(n):
+        gates.append(synth.Gate("RZ", q, -1, 0.0, k)); k += 1
+    gates += [synth.Gate("CZ", 0, 1), synth.Gate("S", 2), synth.Gate("T", 12)]
+    for q in range(7):
+        gates.append(synth.Gate("RZ", q, -1, 0.0, k)); k += 1
+    gates.append(synth.Gate("CNOT", 1, 2))
+    for q in range(n):
+        gates.append(synth.Gate("RX", q, -1, 0.0, k)); k += 1
+    params = np.random.default_rng(41).uniform(-3, 3, size=(2, k))
+    tol = (1e-12, 1e-10) if dt == "c128" else (1e-5, 1e-4)
+    with P.StateVector(n, dt, batch=2) as sv:
+        f, g = sv.adjoint_expect_z(gates, params, qubit=4)
+    for b in range(2):
+        assert abs(f[b] - O.loss_z(n, gates, params[b], qubit=4)) <= tol[0]
+        ps = O.grad_param_shift(n, gates, params[b], list(range(k)), qubit=4)
+        assert np.max(np.abs(g[b] - ps)) <= tol[1]
+
+
 def test_adjoint_more_than_eight_high_qubits(P):
     """A run with X / Y generators on 9 qubits >= 12 takes two fused launches
     (8 qubits, then 1); every high-qubit gradient against parameter shift."""
