@@ -49,6 +49,28 @@ struct Request {
     std::vector<double> params;
 };
 
+// Remove the entries at the ascending, distinct indices `idx` from `q`,
+// keeping the order of the rest, in one pass: a prefix is erased from the
+// front; otherwise the rest moves down once. (One erase per entry would move
+// the queue once per entry: quadratic in the group size.)
+template <typename Q>
+void erase_indices(Q &q, const std::vector<size_t> &idx) {
+    if (idx.empty()) return;
+    if (idx.back() + 1 == idx.size()) {
+        q.erase(q.begin(), q.begin() + (long)idx.size());
+        return;
+    }
+    size_t w = idx[0], k = 0;
+    for (size_t i = idx[0]; i < q.size(); ++i) {
+        if (k < idx.size() && idx[k] == i) {
+            ++k;
+            continue;
+        }
+        q[w++] = std::move(q[i]);
+    }
+    q.erase(q.begin() + (long)w, q.end());
+}
+
 // A few host threads that share one batch of independent jobs with the
 // calling thread (the op records of a step's newly admitted requests).
 class JobPool {
@@ -434,7 +456,7 @@ sv_status launch_ready(sv_engine_s *e) {
         std::vector<Request> grp;
         grp.reserve(pick.size());
         for (size_t i : pick) grp.push_back(std::move(queue[i]));
-        for (size_t j = pick.size(); j-- > 0;) queue.erase(queue.begin() + (long)pick[j]);
+        erase_indices(queue, pick);
         sv_status st = small ? launch_small_group(e, s, grp) : launch_large_group(e, s, grp);
         if (st != SV_OK) return st;
         sv_status st2 = ensure_pinned(reinterpret_cast<void **>(&s.h_res), &s.h_res_cap,
@@ -726,12 +748,12 @@ sv_status stepped_launch(sv_engine_s *e) {
     }
     // finished requests leave the active set; their state memory returns to
     // the pool after the readout (stream order)
-    for (size_t k = done_idx.size(); k-- > 0;) {
-        Active &a = e->active[done_idx[k]];
+    for (size_t k : done_idx) {
+        Active &a = e->active[k];
         SV_HIP(hipFreeAsync(a.state, ss), "hipFreeAsync(state)");
         e->bytes_held -= a.bytes;
-        e->active.erase(e->active.begin() + (long)done_idx[k]);
     }
+    erase_indices(e->active, done_idx);
     SV_HIP(hipEventRecord(S.done, ss), "hipEventRecord(step)");
     S.busy = true;
     e->step_order.push_back(e->next_step);
