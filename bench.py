@@ -139,7 +139,7 @@ def serving_section(P, synth, seconds=1.5):
     for name, kw, mults in (("c128_one_at_a_time", dict(dtype="c128", max_batch=1, n_streams=1), (0.5, 1.0)),
                             ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=2, stepped=True,
                                                  max_active=256),
-                             (1.0, 4.0, 8.0, 12.0, 14.0, 16.0, 17.0, 18.0, 19.0, 20.0, 22.0))):
+                             (1.0, 4.0, 8.0, 12.0, 16.0, 18.0, 20.0, 21.0, 22.0, 23.0, 24.0, 26.0, 28.0))):
         for m in mults:
             lam = m * mu128
             count = int(min(16000, max(600, lam * seconds)))

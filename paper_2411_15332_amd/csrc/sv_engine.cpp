@@ -250,7 +250,7 @@ struct sv_engine_s {
     std::vector<std::pair<uint64_t, uint64_t>> uploads;   // arena ranges to copy with the next step
     uint64_t ops_live = 0;   // ring bytes held by active requests' op records (at most half the ring,
                              // so that step tables always find room)
-    std::unique_ptr<JobPool> jobs;   // materializes admitted requests' op records in parallel
+    std::unique_ptr<JobPool> jobs;   // builds admitted requests' op records and small groups' constants in parallel
 };
 
 namespace {
@@ -348,11 +348,26 @@ sv_status launch_small_group(sv_engine_s *e, Slot &s, std::vector<Request> &grp)
     char *h = static_cast<char *>(s.h_stage);
     std::memcpy(h + o_jobs, jobs.data(), jobs.size() * sizeof(SmallJob));
     if (!ops.empty()) std::memcpy(h + o_ops, ops.data(), ops.size() * sizeof(SmallOp));
-    for (size_t i = 0; i < grp.size(); ++i) {
+    // each request's constants into its own range of the staging buffer; on
+    // the host thread pool where the engine has one (stepped mode)
+    auto consts_of = [&](size_t i) {
         const Template &t = *grp[i].t;
-        if (t.plan.cstride == 0) continue;
+        if (t.plan.cstride == 0) return;
         materialize_consts(t.plan, t.gates.data(), grp[i].params.data(), t.n_params, 1, f32,
                            h + o_c + jobs[i].const_begin * rb);
+    };
+    if (e->jobs) {
+        std::atomic<bool> bad{false};
+        e->jobs->run(grp.size(), [&](size_t i) {
+            try {
+                consts_of(i);
+            } catch (...) {   // no exception may leave a worker thread
+                bad.store(true);
+            }
+        });
+        if (bad.load()) return fail(SV_EUNSUPPORTED, "serving engine: constants could not be built");
+    } else {
+        for (size_t i = 0; i < grp.size(); ++i) consts_of(i);
     }
     SV_HIP(hipMemcpyAsync(s.d_stage, s.h_stage, total, hipMemcpyHostToDevice, s.stream), "hipMemcpyAsync(jobs)");
     st = ensure_device_buf(reinterpret_cast<void **>(&s.d_res), &s.d_res_cap, grp.size() * sizeof(double),
