@@ -238,6 +238,11 @@ struct sv_engine_s {
     bool stepped = false;
     hipStream_t step_stream = nullptr;
     hipMemPool_t pool = nullptr;   // state memory; keeps what is freed for the next requests
+    // finished requests' state buffers by n, reused by the next requests of
+    // that size in stream order (a pool allocation and free per request cost
+    // tens of microseconds of host time); counted against the budget
+    std::vector<void *> free_states[64];
+    size_t bytes_cached = 0;
     char *d_arena = nullptr;
     char *h_arena = nullptr;     // pinned mirror: records are written here, then copied
     uint64_t arena_cap = 0, tmpl_used = 0, tmpl_cap = 0;
@@ -524,12 +529,22 @@ sv_status stepped_init(sv_engine_s *e) {
     return SV_OK;
 }
 
+// Return the cached state buffers to the pool (stream order).
+void stepped_drop_cache(sv_engine_s *e) {
+    for (auto &v : e->free_states) {
+        for (void *p : v) hipFreeAsync(p, e->step_stream);
+        v.clear();
+    }
+    e->bytes_cached = 0;
+}
+
 void stepped_release(sv_engine_s *e) {
     e->jobs.reset();
     if (e->step_stream) {
         hipStreamSynchronize(e->step_stream);
         for (Active &a : e->active)
             if (a.state) hipFreeAsync(a.state, e->step_stream);
+        stepped_drop_cache(e);
         hipStreamSynchronize(e->step_stream);
     }
     e->active.clear();
@@ -599,6 +614,8 @@ sv_status stepped_admit(sv_engine_s *e) {
             ++e->deferred;
             break;   // admission by HBM footprint: wait for running requests to finish
         }
+        if (e->free_states[t.n].empty() && e->budget && e->bytes_held + e->bytes_cached + bytes > e->budget)
+            stepped_drop_cache(e);   // new memory needed: cached buffers of other sizes go first
         const uint64_t ob = (uint64_t)t.plan.ops.size() * sizeof(DevOp);
         const uint64_t held = (std::max<uint64_t>(ob, 256) + 255) & ~(uint64_t)255;
         if (e->ops_live + held > (e->ring.re - e->ring.rb) / 2) break;   // wait for arena space
@@ -614,7 +631,13 @@ sv_status stepped_admit(sv_engine_s *e) {
         a.ring_entry = seq;
         a.ring_bytes = held;
         e->ops_live += held;
-        SV_HIP(hipMallocFromPoolAsync(&a.state, bytes, e->pool, e->step_stream), "hipMallocFromPoolAsync(state)");
+        if (!e->free_states[t.n].empty()) {
+            a.state = e->free_states[t.n].back();
+            e->free_states[t.n].pop_back();
+            e->bytes_cached -= bytes;
+        } else {
+            SV_HIP(hipMallocFromPoolAsync(&a.state, bytes, e->pool, e->step_stream), "hipMallocFromPoolAsync(state)");
+        }
         if (ob) mats.push_back({&t, std::move(r.params), off});
         stepped_note_upload(e, off, held);   // the allocation's extent: neighbours merge
         if (t.plan.passes.empty())   // nothing to apply: the readout sees |0...0>
@@ -765,7 +788,8 @@ sv_status stepped_launch(sv_engine_s *e) {
     // the pool after the readout (stream order)
     for (size_t k : done_idx) {
         Active &a = e->active[k];
-        SV_HIP(hipFreeAsync(a.state, ss), "hipFreeAsync(state)");
+        e->free_states[a.t->n].push_back(a.state);   // reused after this step's readout (stream order)
+        e->bytes_cached += a.bytes;
         e->bytes_held -= a.bytes;
     }
     erase_indices(e->active, done_idx);
