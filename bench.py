@@ -139,10 +139,10 @@ def serving_section(P, synth, seconds=1.5):
     for name, kw, mults in (("c128_one_at_a_time", dict(dtype="c128", max_batch=1, n_streams=1), (0.5, 1.0)),
                             ("c64_batched", dict(dtype="c64", max_batch=256, n_streams=2, stepped=True,
                                                  max_active=256),
-                             (1.0, 4.0, 8.0, 12.0, 16.0, 18.0, 20.0, 21.0, 22.0, 23.0, 24.0, 26.0, 28.0))):
+                             (1.0, 4.0, 8.0, 12.0, 16.0, 20.0, 24.0, 28.0, 30.0, 32.0, 34.0, 36.0, 38.0, 40.0, 44.0))):
         for m in mults:
             lam = m * mu128
-            count = int(min(16000, max(600, lam * seconds)))
+            count = int(min(24000, max(600, lam * seconds)))
             sub = synth.poisson_requests(count, lam, seed=1)
             with S.ServingEngine(**kw) as eng:
                 res = S.run_stream(eng, sub, gates_of, timeout_s=90, key_of=key_of)
