@@ -1,5 +1,7 @@
 """Serving engine: every result matches the oracle, a request's result is the
 same alone and inside a mixed stream, admission by HBM footprint, errors."""
+import time
+
 import numpy as np
 import pytest
 
@@ -103,6 +105,35 @@ def test_admission_by_hbm_footprint(P, stepped):
     for r in reqs[:3]:
         ref = O.loss_z(n, synth.qnn_ansatz(n, 2), r.params)
         assert abs(got[r.rid] - ref) <= 1e-5
+
+
+def test_stepped_state_buffers_across_sizes(P):
+    """The stepped engine keeps finished requests' state buffers for the
+    next requests of the same size; a request of another size that needs new
+    memory beyond the budget first returns them to the pool. Six n = 17
+    requests, then three n = 18 ones under a budget of three n = 18 states,
+    then n = 17 again: every result against the oracle, the live state bytes
+    within the budget throughout."""
+    pkg, serving = P
+    budget = 3 * (1 << 18) * 8
+    rounds = [synth.poisson_requests(6, 1e9, seed=5, n_range=(17, 17), layer_range=(2, 2)),
+              synth.poisson_requests(3, 1e9, seed=6, n_range=(18, 18), layer_range=(2, 2)),
+              synth.poisson_requests(4, 1e9, seed=7, n_range=(17, 17), layer_range=(2, 2))]
+    got = {}
+    with serving.ServingEngine("c64", max_batch=8, n_streams=2, hbm_budget_bytes=budget, stepped=True) as eng:
+        for k, reqs in enumerate(rounds):
+            for r in reqs:
+                eng.submit(1000 * k + r.rid, r.n, _gates(pkg, r), r.params, 0)
+            want = sum(len(x) for x in rounds[:k + 1])
+            t0 = time.time()
+            while len(got) < want:
+                assert time.time() - t0 < 60, "requests did not finish"
+                got.update(eng.poll(wait_us=100_000))
+                assert eng.stats()["state_bytes"] <= budget
+    for k, reqs in enumerate(rounds):
+        for r in reqs:
+            ref = O.loss_z(r.n, synth.qnn_ansatz(r.n, 2), r.params)
+            assert abs(got[1000 * k + r.rid] - ref) <= 1e-5
 
 
 def test_submit_validation(P):
