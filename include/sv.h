@@ -308,9 +308,12 @@ sv_status sv_engine_create(sv_dtype dtype, int max_batch, int n_streams,
  * request's first pass generates its initial product state (its leading
  * 1-qubit gates applied to |0...0>, on demand) instead of reading a filled
  * state. Every request runs the same code whatever shares its steps, so its
- * result does not depend on the mix. The plan arena holds 256 MiB of op
- * records (requests wait when it is full) and 32 MiB of distinct circuits
- * (SV_ENOMEM beyond). */
+ * result does not depend on the mix. A finished request's state buffer is
+ * kept for the next request of the same n; kept buffers count against a
+ * nonzero HBM budget and are given back when a request needs new memory,
+ * and with no budget (0) they stay with the engine until sv_engine_free.
+ * The plan arena holds 256 MiB of op records (requests wait when it is
+ * full) and 32 MiB of distinct circuits (SV_ENOMEM beyond). */
 sv_status sv_engine_create_stepped(sv_dtype dtype, int max_active, int max_small_batch, int n_small_streams,
                                    size_t hbm_budget_bytes, sv_engine *out);
 
