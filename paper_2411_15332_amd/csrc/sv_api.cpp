@@ -161,29 +161,32 @@ sv_status check_handle(sv_state s) {
 
 // Upload plan and launch it on the handle's stream, on `state`.
 sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const sv_gate *gates,
-                   const double *params, size_t n_params) {
+                   const double *params, size_t n_params, bool uploaded) {
     const bool f32 = s->dt == SV_C64;
     const size_t real_bytes = f32 ? 4 : 8;
     const Layout L = plan_sections(p, batch, real_bytes);
-    if (s->upload_pending) {
-        SV_HIP(hipEventSynchronize(s->upload_done), "wait for previous plan upload");
-        s->upload_pending = false;
-    }
-    sv_status st = ensure_host_buf(&s->h_stage, &s->h_cap, L.total, "hipHostMalloc(plan)");
-    if (st != SV_OK) return st;
-    // the device plan buffer may still be read by queued kernels: grow only
-    // after the stream has drained
-    if (s->d_cap < L.total) {
-        SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
-        st = ensure_device_buf(&s->d_plan, &s->d_cap, L.total, "hipMalloc(plan)");
+    if (!uploaded) {
+        s->dplan_current = false;   // the upload below replaces what the buffer held
+        if (s->upload_pending) {
+            SV_HIP(hipEventSynchronize(s->upload_done), "wait for previous plan upload");
+            s->upload_pending = false;
+        }
+        sv_status st = ensure_host_buf(&s->h_stage, &s->h_cap, L.total, "hipHostMalloc(plan)");
         if (st != SV_OK) return st;
+        // the device plan buffer may still be read by queued kernels: grow only
+        // after the stream has drained
+        if (s->d_cap < L.total) {
+            SV_HIP(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+            st = ensure_device_buf(&s->d_plan, &s->d_cap, L.total, "hipMalloc(plan)");
+            if (st != SV_OK) return st;
+        }
+        serialize_plan(p, L, gates, params, n_params, batch, f32, static_cast<char *>(s->h_stage));
+        SV_HIP(hipMemcpyAsync(s->d_plan, s->h_stage, L.total, hipMemcpyHostToDevice, s->stream),
+               "hipMemcpyAsync(plan)");
+        if (!s->upload_done) SV_HIP(hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming), "hipEventCreate");
+        SV_HIP(hipEventRecord(s->upload_done, s->stream), "hipEventRecord");
+        s->upload_pending = true;
     }
-    serialize_plan(p, L, gates, params, n_params, batch, f32, static_cast<char *>(s->h_stage));
-    SV_HIP(hipMemcpyAsync(s->d_plan, s->h_stage, L.total, hipMemcpyHostToDevice, s->stream),
-           "hipMemcpyAsync(plan)");
-    if (!s->upload_done) SV_HIP(hipEventCreateWithFlags(&s->upload_done, hipEventDisableTiming), "hipEventCreate");
-    SV_HIP(hipEventRecord(s->upload_done, s->stream), "hipEventRecord");
-    s->upload_pending = true;
 
     char *d = static_cast<char *>(s->d_plan);
     const uint64_t N = 1ull << s->n;
@@ -387,6 +390,7 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
                          std::memcmp(s->plan_gates.data(), gates, n_gates * sizeof(sv_gate)) == 0;
         if (!hit) {
             s->plan_valid = false;
+            s->dplan_current = false;
             lower_gates(gates, n_gates, n_params, s->plan_low);
             s->plan = build_plan_auto(s->n, s->plan_low.gates.data(), s->plan_low.gates.size(), po);
             s->plan_gates.assign(gates, gates + n_gates);
@@ -401,10 +405,20 @@ sv_status sv_apply_circuit(sv_state s, const sv_gate *gates, size_t n_gates, con
         }
         std::vector<double> ext;
         lower_params(s->plan_low, params, n_params, s->batch, ext);
-        st = ext.empty() ? run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), params, n_params)
-                         : run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), ext.data(),
-                                    n_params + s->plan_low.src.size());
+        const double *pp = ext.empty() ? params : ext.data();
+        const size_t np = ext.empty() ? n_params : n_params + s->plan_low.src.size();
+        const size_t cnt = pp ? np * (size_t)s->batch : 0;
+        // the same plan, batch and parameters as the last upload: the device
+        // plan buffer already holds this serialization
+        const bool same = s->dplan_current && s->dplan_batch == s->batch && s->dplan_params.size() == cnt &&
+                          (cnt == 0 || std::memcmp(s->dplan_params.data(), pp, cnt * sizeof(double)) == 0);
+        st = run_plan(s, s->buf, s->batch, p, s->plan_low.gates.data(), pp, np, same);
         if (st != SV_OK) return st;
+        if (!same) {
+            s->dplan_current = true;
+            s->dplan_batch = s->batch;
+            s->dplan_params.assign(pp, pp + cnt);
+        }
         s->fill_pending = false;   // the first pass generated the recorded basis state
         s->stats[0] = p.small ? 1 : (int64_t)p.passes.size();
         s->stats[1] = p.n_exch;

@@ -102,6 +102,11 @@ struct sv_state_s {
     sv::Lowering plan_low;   // the gates the plan was built from (composite kinds lowered)
     sv::Plan plan;
     bool plan_valid = false;
+    // the device plan buffer holds `plan` serialized for dplan_batch entries
+    // and this parameter table: a repeated sv_apply_circuit uploads nothing
+    bool dplan_current = false;
+    int dplan_batch = 0;
+    std::vector<double> dplan_params;
 
     int64_t stats[8] = {0};
 
@@ -117,8 +122,10 @@ sv_status ensure_device_buf(void **p, size_t *cap, size_t need, const char *what
 sv_status materialize(sv_state_s *s);
 sv_status ensure_host_buf(void **p, size_t *cap, size_t need, const char *what);
 // Upload plan `p` and launch it on `state` (`batch` states) on the handle's stream.
+// uploaded: the device plan buffer already holds this serialization (the
+// caller checked plan, batch and parameters); otherwise it is uploaded.
 sv_status run_plan(sv_state_s *s, void *state, int batch, const Plan &p, const sv_gate *gates,
-                   const double *params, size_t n_params);
+                   const double *params, size_t n_params, bool uploaded = false);
 // Release every buffer the handle owns or caches (not the handle itself).
 void release_handle_buffers(sv_state_s *s);
 
