@@ -823,14 +823,31 @@ sv_status sv_adjoint_expect_z(sv_state s, const sv_gate *gates, size_t n_gates, 
                 if (st != SV_OK) return st;
                 pend_z.clear();
             }
+            bool run_diag = true;   // this run's own undo is diagonal (RZ only)
+            for (size_t k = j; k < i; ++k) run_diag = run_diag && gates[k].kind == SV_GATE_RZ;
+            // An RZ-only run's terms all wait, so the states are not needed
+            // at its own point. When only diagonal gates separate it from the
+            // previous run, its undo joins the next segment instead of being
+            // applied here: its terms, and those already waiting, are still
+            // valid at that run's point and go with its launch.
+            if (run_diag) {
+                size_t k = j;
+                while (k > 0 && gates[k - 1].param < 0 && diagonal(gates[k - 1])) --k;
+                if (k > 0 && gates[k - 1].param >= 0) {
+                    for (size_t t = i; t-- > j;)
+                        pend_z.push_back(ZTerm{(uint8_t)gates[t].q0, (uint64_t)gates[t].param});
+                    for (size_t t = i; t-- > j;) seg.push_back(inverse(gates[t]));
+                    seg_diag = true;   // every waiting term stays valid through the next flush
+                    i = j;
+                    continue;
+                }
+            }
             st = flush();
             if (st != SV_OK) return st;
             // one read of psi and lambda for every Z term and every X / Y term
             // whose partner amplitude lies in the same 2^12-amplitude chunk;
             // one more read per group of up to 8 X / Y terms on higher qubits
             // (the run's qubits are distinct, so a group is up to 8 qubits)
-            bool run_diag = true;   // this run's own undo is diagonal (RZ only)
-            for (size_t k = j; k < i; ++k) run_diag = run_diag && gates[k].kind == SV_GATE_RZ;
             std::vector<ZTerm> zs;
             zs.swap(pend_z);
             std::vector<std::pair<sv_gate, int>> xy;
